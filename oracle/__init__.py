@@ -1,0 +1,306 @@
+"""FP64 CPU oracle for the pulse-noise Landau-Lifshitz-Langevin hot path.
+
+TEST INFRASTRUCTURE ONLY.  The product library never imports, links or calls
+anything here; only the test suite, the smoke check and the benchmark's CPU
+baseline leg do.  The arithmetic lives in ``lll_oracle.c`` (plain C, FP64,
+built with ``-O2 -fno-fast-math -ffp-contract=off``); this module only marshals
+numpy arrays through ctypes.
+
+Array convention: a spin state is a float64 array of shape (3, N) with the
+site index i = x + Lx*(y + Ly*z) (component-major, as in the paper's Appendix).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lll_oracle.c")
+_LIB = os.path.join(_HERE, "liblll_oracle.so")
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no GPU code involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Geom(C.Structure):
+    _fields_ = [("Lx", C.c_int32), ("Ly", C.c_int32), ("Lz", C.c_int32), ("bc", C.c_int32)]
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("J", C.c_double), ("H", C.c_double * 3), ("D", C.c_double), ("e", C.c_double * 3),
+        ("D_site", C.c_void_p), ("e_site", C.c_void_p),
+        ("lam", C.c_double), ("T", C.c_double), ("dt", C.c_double), ("Dt", C.c_double),
+        ("precession", C.c_int32), ("pad_", C.c_int32),
+    ]
+
+
+class Obs(C.Structure):
+    _fields_ = [("E_total", C.c_double), ("E_exch", C.c_double), ("E_zeeman", C.c_double),
+                ("E_anis", C.c_double), ("m", C.c_double * 3), ("max_norm_dev", C.c_double)]
+
+    def as_dict(self):
+        return {"E_total": self.E_total, "E_exch": self.E_exch, "E_zeeman": self.E_zeeman,
+                "E_anis": self.E_anis, "m": tuple(self.m), "max_norm_dev": self.max_norm_dev}
+
+
+@dataclass
+class Params:
+    """Physical and numerical parameters (units gamma = mu_0 = k_B = 1)."""
+    J: float = 1.0
+    H: Sequence[float] = (0.0, 0.0, 0.0)
+    D: float = 0.0
+    e: Sequence[float] = (0.0, 0.0, 1.0)
+    lam: float = 0.01
+    T: float = 1.0
+    dt: float = 0.1
+    Dt: float = 1.0
+    precession: bool = True
+    D_site: Optional[np.ndarray] = None   # (N,)
+    e_site: Optional[np.ndarray] = None   # (3, N)
+    _keep: list = field(default_factory=list, repr=False)
+
+    def c(self) -> _Params:
+        p = _Params()
+        p.J = self.J
+        p.H[:] = list(map(float, self.H))
+        p.D = self.D
+        p.e[:] = list(map(float, self.e))
+        self._keep = []
+        if self.D_site is not None:
+            a = np.ascontiguousarray(self.D_site, dtype=np.float64)
+            self._keep.append(a)
+            p.D_site = a.ctypes.data
+        if self.e_site is not None:
+            a = np.ascontiguousarray(self.e_site, dtype=np.float64)
+            self._keep.append(a)
+            p.e_site = a.ctypes.data
+        p.lam = self.lam
+        p.T = self.T
+        p.dt = self.dt
+        p.Dt = self.Dt
+        p.precession = 1 if self.precession else 0
+        return p
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        u32p = C.POINTER(C.c_uint32)
+        G = C.POINTER(Geom)
+        P = C.POINTER(_Params)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox_stream.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32,
+                                        C.c_uint32, C.c_uint32, u32p]
+        L.orc_u01.argtypes = [C.c_uint32]
+        L.orc_u01.restype = C.c_double
+        L.orc_gauss3.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp]
+        L.orc_init_random_sphere.argtypes = [G, C.c_uint64, C.c_uint32, dp]
+        L.orc_init_direction.argtypes = [G, dp, dp]
+        for nm in ("orc_heff", "orc_rhs"):
+            getattr(L, nm).argtypes = [G, P, dp, dp]
+        L.orc_energy_parts.argtypes = [G, P, dp, dp]
+        for nm in ("orc_step_rk4", "orc_step_heun", "orc_step_rk2mid", "orc_step_rk5b"):
+            getattr(L, nm).argtypes = [G, P, dp, C.c_int64]
+        L.orc_rotate.argtypes = [dp, dp, dp]
+        L.orc_kick.argtypes = [G, P, C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, dp]
+        L.orc_kick.restype = C.c_double
+        L.orc_observables.argtypes = [G, P, dp, C.POINTER(Obs)]
+        L.orc_steps_per_interval.argtypes = [P]
+        L.orc_steps_per_interval.restype = C.c_int64
+        L.orc_run.argtypes = [G, P, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, dp, C.c_int32,
+                              dp, C.POINTER(Obs)]
+        L.orc_run.restype = C.c_double
+        L.orc_adjoint.argtypes = [G, P, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, dp, dp,
+                                  C.c_double, dp, dp, dp, dp, dp, dp]
+        L.orc_adjoint.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _state(s, N):
+    a = np.ascontiguousarray(s, dtype=np.float64).reshape(3, N).copy()
+    return a
+
+
+def geom(shape, bc: str = "periodic") -> Geom:
+    Lx, Ly, Lz = shape
+    return Geom(int(Lx), int(Ly), int(Lz), 0 if bc == "periodic" else 1)
+
+
+def nsites(g: Geom) -> int:
+    return g.Lx * g.Ly * g.Lz
+
+
+# ---------------------------------------------------------------- RNG ------
+def philox4x32_10(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def philox_stream(seed: int, i0: int, n: int, c1: int, c2: int, c3: int) -> np.ndarray:
+    out = np.zeros((n, 4), dtype=np.uint32)
+    lib().orc_philox_stream(C.c_uint64(seed), i0, n, c1, c2, c3,
+                            out.ctypes.data_as(C.POINTER(C.c_uint32)))
+    return out
+
+
+def u01(w: int) -> float:
+    return lib().orc_u01(int(w) & 0xFFFFFFFF)
+
+
+def gauss3(seed, i, k, r, tag) -> np.ndarray:
+    G = np.zeros(3)
+    lib().orc_gauss3(C.c_uint64(seed), i, k, r, tag, _dp(G))
+    return G
+
+
+# ------------------------------------------------------------- state -------
+def init_random_sphere(g: Geom, seed: int, r: int = 0) -> np.ndarray:
+    s = np.zeros((3, nsites(g)))
+    lib().orc_init_random_sphere(C.byref(g), C.c_uint64(seed), r, _dp(s))
+    return s
+
+
+def init_direction(g: Geom, d) -> np.ndarray:
+    s = np.zeros((3, nsites(g)))
+    dd = np.asarray(d, dtype=np.float64)
+    lib().orc_init_direction(C.byref(g), _dp(dd), _dp(s))
+    return s
+
+
+def heff(g: Geom, p: Params, s) -> np.ndarray:
+    N = nsites(g)
+    s = _state(s, N)
+    h = np.zeros((3, N))
+    pc = p.c()
+    lib().orc_heff(C.byref(g), C.byref(pc), _dp(s), _dp(h))
+    return h
+
+
+def rhs(g: Geom, p: Params, s) -> np.ndarray:
+    N = nsites(g)
+    s = _state(s, N)
+    f = np.zeros((3, N))
+    pc = p.c()
+    lib().orc_rhs(C.byref(g), C.byref(pc), _dp(s), _dp(f))
+    return f
+
+
+def energy_parts(g: Geom, p: Params, s) -> np.ndarray:
+    N = nsites(g)
+    s = _state(s, N)
+    out = np.zeros(3)
+    pc = p.c()
+    lib().orc_energy_parts(C.byref(g), C.byref(pc), _dp(s), _dp(out))
+    return out
+
+
+def step(g: Geom, p: Params, s, n_steps: int = 1, method: str = "rk4") -> np.ndarray:
+    N = nsites(g)
+    s = _state(s, N)
+    pc = p.c()
+    fn = {"rk4": "orc_step_rk4", "heun": "orc_step_heun", "rk2mid": "orc_step_rk2mid",
+          "rk5b": "orc_step_rk5b"}[method]
+    getattr(lib(), fn)(C.byref(g), C.byref(pc), _dp(s), int(n_steps))
+    return s
+
+
+def rotate(s3, phi3) -> np.ndarray:
+    a = np.ascontiguousarray(s3, dtype=np.float64)
+    b = np.ascontiguousarray(phi3, dtype=np.float64)
+    o = np.zeros(3)
+    lib().orc_rotate(_dp(a), _dp(b), _dp(o))
+    return o
+
+
+def kick(g: Geom, p: Params, s, T: float, seed: int, r: int, k: int):
+    N = nsites(g)
+    s = _state(s, N)
+    pc = p.c()
+    dev = lib().orc_kick(C.byref(g), C.byref(pc), float(T), C.c_uint64(seed), r,
+                         C.c_uint64(k), _dp(s))
+    return s, dev
+
+
+def observables(g: Geom, p: Params, s) -> dict:
+    N = nsites(g)
+    s = _state(s, N)
+    pc = p.c()
+    o = Obs()
+    lib().orc_observables(C.byref(g), C.byref(pc), _dp(s), C.byref(o))
+    return o.as_dict()
+
+
+def steps_per_interval(p: Params) -> int:
+    pc = p.c()
+    return int(lib().orc_steps_per_interval(C.byref(pc)))
+
+
+def run(g: Geom, p: Params, s, seed: int, r: int = 0, first_pulse: int = 0, n_pulses: int = 1,
+        T_per_pulse=None, obs_every: int = 0):
+    """Runs the schedule; returns (state, trace list of dicts, max kick deviation)."""
+    N = nsites(g)
+    s = _state(s, N)
+    pc = p.c()
+    nm = (n_pulses // obs_every) if obs_every > 0 else 0
+    trace = (Obs * max(nm, 1))()
+    Tp = None
+    if T_per_pulse is not None:
+        Tp = np.ascontiguousarray(T_per_pulse, dtype=np.float64)
+    dev = lib().orc_run(C.byref(g), C.byref(pc), C.c_uint64(seed), r, C.c_uint64(first_pulse),
+                        int(n_pulses), _dp(Tp) if Tp is not None else None, int(obs_every),
+                        _dp(s), trace)
+    if dev < 0:
+        raise ValueError("invalid schedule: Dt/dt must be a positive integer")
+    return s, [trace[i].as_dict() for i in range(nm)], dev
+
+
+def adjoint(g: Geom, p: Params, s0, seed: int, r: int = 0, first_pulse: int = 0,
+            n_pulses: int = 1, T_per_pulse=None, wE: float = 1.0, wm=(0.0, 0.0, 0.0)):
+    """Loss L = wE*E(s_T) + wm.m(s_T) and its gradients (dict)."""
+    N = nsites(g)
+    s0 = _state(s0, N)
+    pc = p.c()
+    wm_a = np.asarray(wm, dtype=np.float64)
+    loss = np.zeros(1)
+    gs0 = np.zeros((3, N))
+    gH = np.zeros(3)
+    gJ = np.zeros(1)
+    gD = np.zeros(N if p.D_site is not None else 1)
+    Tp = None
+    if T_per_pulse is not None:
+        Tp = np.ascontiguousarray(T_per_pulse, dtype=np.float64)
+    rc = lib().orc_adjoint(C.byref(g), C.byref(pc), C.c_uint64(seed), r, C.c_uint64(first_pulse),
+                           int(n_pulses), _dp(Tp) if Tp is not None else None, _dp(s0), float(wE),
+                           _dp(wm_a), _dp(loss), _dp(gs0), _dp(gH), _dp(gJ), _dp(gD))
+    if rc != 0:
+        raise ValueError(f"orc_adjoint failed: {rc}")
+    return {"loss": float(loss[0]), "g_s0": gs0, "g_H": gH, "g_J": float(gJ[0]),
+            "g_D": gD if p.D_site is not None else float(gD[0])}

@@ -1,0 +1,224 @@
+/*
+ * lll.h -- C ABI of the MI355X (gfx950) pulse-noise Landau-Lifshitz-Langevin
+ * library (D. A. Garanin, "Pulse-noise approach for classical spin systems",
+ * arXiv:1610.04914).
+ *
+ * The library integrates a simple-cubic lattice of classical unit spins:
+ *   - between noise pulses, the noise-free Landau-Lifshitz equation
+ *     (Eq. (1) with zeta = 0, gamma = 1):
+ *        ds_i/dt = s_i x h_i - lambda s_i x (s_i x h_i)
+ *     (the slow equation of Sec. II drops the first term), with classical
+ *     fourth-order Runge-Kutta steps of size dt;
+ *   - the effective field h_i = J sum_{6 neighbours} s_j + H + 2 D_i (s_i.e_i) e_i
+ *     belongs to E = -J sum_<ij> s_i.s_j - sum_i H.s_i - sum_i D_i (s_i.e_i)^2
+ *     (each bond counted once; anisotropy convention of Eq. (12));
+ *   - every Delta t = n dt a pulse-noise kick (Eqs. (5)-(6)): each spin is
+ *     rotated by the vector angle phi = sqrt(2 lambda T Delta t) G, G a vector
+ *     of three unit normals, and renormalised to unit length;
+ *   - the kick sits in the middle of each interval (Eq. (7)): an interval is
+ *     n1 = floor(n/2) steps, kick, n2 = n - n1 steps, measurement.
+ * Units: gamma = mu_0 = k_B = 1.
+ *
+ * Memory: spins are stored structure-of-arrays (three arrays sx, sy, sz of N
+ * elements each, site index i = x + Lx*(y + Ly*z)) in device memory, in fp64
+ * (double) or fp32 (float).  Energies, magnetisation and the renormalisation
+ * check are always computed in fp64.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (site i, pulse k mod 2^32, replica r, tag) and key (seed lo32, seed hi32);
+ * tag 0 = kick, tag 1 = random-sphere initial state.  u = (w + 1/2) 2^-32;
+ * normals by Box-Muller: G = (sqrt(-2 ln u0) cos 2pi u1,
+ * sqrt(-2 ln u0) sin 2pi u1, sqrt(-2 ln u2) cos 2pi u3).
+ *
+ * Conventions for every entry point:
+ *   - all functions return lll_status; 0 = success, < 0 = error (nothing was
+ *     enqueued unless stated), > 0 = warning (the work was done);
+ *   - after a non-zero status, lll_last_error() returns a message (per thread);
+ *   - all GPU work is enqueued on the handle's HIP stream in call order; only
+ *     calls that return host data (lll_observables, lll_run with a trace,
+ *     lll_accumulators, lll_kick_norm_dev, batch observables, the adjoint)
+ *     synchronise that stream;
+ *   - a handle must not be used by two host threads at once.
+ */
+#ifndef LLL_H
+#define LLL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LLL_OK = 0,
+    LLL_EINVAL = -1,        /* invalid argument (null pointer, bad size, non-integral Dt/dt, ...) */
+    LLL_ENOMEM = -2,        /* device allocation failed */
+    LLL_EDEVICE = -3,       /* a HIP runtime call failed */
+    LLL_EUNSUPPORTED = -4,  /* valid request this build or device does not support */
+    LLL_ENONFINITE = -5,    /* a NaN/Inf was found in the state by a reduction */
+    LLL_WARN_APPLICABILITY = 1 /* work done, but Eq. (8)/(9) or the step-size rule is violated */
+} lll_status;
+
+typedef enum { LLL_FP64 = 0, LLL_FP32 = 1 } lll_precision;
+typedef enum { LLL_BC_PERIODIC = 0, LLL_BC_FREE = 1 } lll_bc;
+typedef enum {
+    LLL_INIT_RANDOM_SPHERE = 0, /* uniform on the sphere from Philox tag 1 */
+    LLL_INIT_DIRECTION = 1,     /* every spin along dir (normalised) */
+    LLL_INIT_KEEP = 2           /* the caller has filled the buffers it passes */
+} lll_init;
+typedef enum { LLL_RK4 = 0 } lll_integrator;
+
+/* Physical and numerical parameters, copied on every call.  Thresholds of the
+ * applicability warning: 2 lambda T Dt > 0.2 (Eq. (8)); lambda h_max Dt > 0.2
+ * (Eq. (9)); with precession, h_max dt > 0.25 (Sec. II, step-size rule), where
+ * h_max = 6|J| + |H| + 2|D|. */
+typedef struct {
+    double J;             /* exchange constant */
+    double H[3];          /* external field */
+    double D;             /* uniform uniaxial anisotropy (ignored when D_site is set) */
+    double e[3];          /* uniform easy axis, normalised by the library; (0,0,0) means z */
+    const void* D_site;   /* optional device array [N] of the lattice precision: per-site D_i,
+                             caller-owned, must stay valid while the handle uses it */
+    const void* e_site;   /* optional device array [3*N] (x block, y block, z block) of the
+                             lattice precision: per-site unit easy axes; needs D_site */
+    double lambda;        /* damping, >= 0 */
+    double T;             /* temperature, >= 0 (T = 0: the kick only renormalises) */
+    double dt;            /* RK4 step, > 0 */
+    double Dt;            /* pulse spacing; Dt/dt must be an integer n >= 1 (|Dt/dt - n| <= 1e-9 n) */
+    int32_t precession;   /* 1: full Eq. (1); 0: slow equation (precession dropped) */
+    int32_t integrator;   /* LLL_RK4 */
+    uint64_t seed;        /* Philox key of the kicks */
+} lll_params;
+
+/* Observables of one state, fp64. */
+typedef struct {
+    double E_total, E_exch, E_zeeman, E_anis; /* energies (sums over the lattice) */
+    double m[3];                              /* magnetisation per site, sum_i s_i / N */
+    double max_norm_dev;                      /* max_i | |s_i| - 1 | */
+} lll_obs;
+
+typedef struct lll_lattice lll_lattice;
+typedef struct lll_batch lll_batch;
+
+/* Creates a lattice of Lx*Ly*Lz sites on the current HIP device.
+ * sx, sy, sz: caller-owned device buffers of N elements of the precision
+ * (all three or none); when NULL the library allocates and owns them.
+ * hip_stream: the hipStream_t to enqueue on (NULL = the default stream).
+ * mode/dir/seed: initial state (dir is read for LLL_INIT_DIRECTION only; the
+ * seed keys the random sphere, replica 0).
+ * On success *out receives the handle.  Errors: LLL_EINVAL (L < 1, null out,
+ * partial buffers, dir zero), LLL_ENOMEM, LLL_EDEVICE. */
+lll_status lll_init_lattice(int32_t Lx, int32_t Ly, int32_t Lz, lll_bc bc, lll_precision prec,
+                            lll_init mode, const double dir[3], uint64_t seed, void* sx, void* sy,
+                            void* sz, void* hip_stream, lll_lattice** out);
+
+/* n_steps >= 0 classical RK4 steps of the noise-free equation (Eq. (1) with
+ * zeta = 0; no renormalisation).  Only params' physics and dt are used. */
+lll_status lll_step_conservative(lll_lattice* lat, const lll_params* params, int64_t n_steps);
+
+/* One pulse-noise kick with pulse index pulse_index at temperature params->T
+ * (Eqs. (5)-(6)) followed by renormalisation of every spin.  Stateless: the
+ * noise depends only on (seed, site, pulse_index, replica 0). */
+lll_status lll_noise_pulse(lll_lattice* lat, const lll_params* params, uint64_t pulse_index);
+
+/* Observables of the current state into *out_host (synchronises the stream).
+ * LLL_ENONFINITE when the state holds a NaN or Inf (out_host is still filled). */
+lll_status lll_observables(lll_lattice* lat, const lll_params* params, lll_obs* out_host);
+
+/* n_pulses intervals (n1 steps, kick k, n2 steps) for k = first_pulse ...
+ * first_pulse + n_pulses - 1.  T_per_pulse: optional host array [n_pulses] of
+ * kick temperatures (NULL: params->T).  When obs_every > 0 and trace != NULL,
+ * the observables after every obs_every-th interval are written to
+ * trace[0 .. n_pulses/obs_every) (host memory; the call then synchronises).
+ * Calling step(n1), pulse(k), step(n2) in order gives the same result bit for
+ * bit.  Returns LLL_WARN_APPLICABILITY (> 0) after doing the work when the
+ * parameters violate the applicability conditions. */
+lll_status lll_run(lll_lattice* lat, const lll_params* params, uint64_t first_pulse,
+                   int64_t n_pulses, const double* T_per_pulse, int32_t obs_every,
+                   lll_obs* trace);
+
+/* Device pointers of the current state (valid until lll_destroy). */
+lll_status lll_get_state(lll_lattice* lat, void** sx, void** sy, void** sz);
+
+/* Largest | |s'| - 1 | before renormalisation over all kicks since the last
+ * reset, fp64 (synchronises).  reset != 0 clears it afterwards. */
+lll_status lll_kick_norm_dev(lll_lattice* lat, double* out_host, int32_t reset);
+
+/* FP64 running sums over measured intervals since the last reset, out_host[8] =
+ * {count, sum E_total, sum E_total^2, sum |m|, sum |m|^2, sum m_x, sum m_y,
+ * sum m_z}.  Synchronises; reset != 0 clears them afterwards. */
+lll_status lll_accumulators(lll_lattice* lat, double* out_host, int32_t reset);
+
+/* Kernel configuration of the RK4 step.  variant: 0 = unfused (one launch per
+ * RK stage), 1..LLL_N_FUSED = fused tile shapes listed by
+ * lll_step_variant_info; bz = z-chunk of the fused kernel (0 = automatic). */
+lll_status lll_set_step_config(lll_lattice* lat, int32_t variant, int32_t bz);
+lll_status lll_get_step_config(lll_lattice* lat, int32_t* variant, int32_t* bz);
+/* Tile shape of a variant for a precision: out[0..3] = {bx, by, threads, lds_bytes};
+ * LLL_EINVAL past the last variant. */
+lll_status lll_step_variant_info(lll_precision prec, int32_t variant, int32_t* out4);
+
+/* Times every step configuration on this lattice (RK4 steps with params,
+ * restoring the state afterwards) and selects the fastest.  cache_path
+ * (optional) is a text file of "key variant bz" lines that is read first and
+ * updated; the key is the shape, precision, boundary, precession and
+ * anisotropy mode.  *chosen_variant and *chosen_bz may be NULL. */
+lll_status lll_autotune(lll_lattice* lat, const lll_params* params, const char* cache_path,
+                        int32_t* chosen_variant, int32_t* chosen_bz);
+
+/* Discrete adjoint (reverse mode) of lll_run from the current state (the
+ * state is left unchanged) for L = wE * E(s_T) + wm . m(s_T).  The forward
+ * pass stores a checkpoint every ckpt_every RK4 steps; the backward pass
+ * recomputes each checkpoint block.  Kicks are fixed by the seed.
+ * Outputs: *loss; g_H[3], *g_J (host); g_D: host double[1] = dL/dD when
+ * params->D_site is NULL, else a device fp64 array [N] of dL/dD_i;
+ * g_s0 (optional): device array [3*N] of the lattice precision = dL/ds_0.
+ * Synchronises. */
+lll_status lll_adjoint(lll_lattice* lat, const lll_params* params, uint64_t first_pulse,
+                       int64_t n_pulses, int32_t ckpt_every, double wE, const double wm[3],
+                       double* loss, double* g_H, double* g_J, void* g_D, void* g_s0);
+
+void lll_destroy(lll_lattice* lat);
+
+/* ---------------------------------------------------------------- batch --
+ * Many independent replicas (uneven sizes, own T, lambda, seed) advanced
+ * together: every kernel of the schedule covers all replicas in one launch,
+ * and the whole run is one captured HIP graph.  Spins of all replicas live in
+ * one packed SoA allocation owned by the batch. */
+typedef struct {
+    int32_t Lx, Ly, Lz;
+    int32_t bc;          /* lll_bc */
+    double J, H[3], D, e[3];
+    double lambda, T;
+    uint64_t seed;       /* Philox key of this replica */
+    uint32_t replica;    /* Philox counter word 2 of this replica */
+    int32_t init;        /* lll_init: RANDOM_SPHERE (keyed by seed, replica) or DIRECTION (+z) */
+} lll_replica_desc;
+
+lll_status lll_batch_create(int32_t n_rep, const lll_replica_desc* reps, lll_precision prec,
+                            double dt, double Dt, int32_t precession, void* hip_stream,
+                            lll_batch** out);
+/* Runs n_pulses intervals on every replica.  trace (optional, host):
+ * [n_pulses/obs_every][n_rep] lll_obs. */
+lll_status lll_batch_run(lll_batch* b, uint64_t first_pulse, int64_t n_pulses, int32_t obs_every,
+                         lll_obs* trace);
+lll_status lll_batch_observables(lll_batch* b, lll_obs* out_host /* [n_rep] */);
+lll_status lll_batch_state(lll_batch* b, int32_t rep, void** sx, void** sy, void** sz);
+/* FP64 running sums of every replica since creation: out_host[8*n_rep] as in lll_accumulators. */
+lll_status lll_batch_accumulators(lll_batch* b, double* out_host, int32_t reset);
+void lll_batch_destroy(lll_batch* b);
+
+/* ---------------------------------------------------------------- misc --- */
+/* Philox4x32-10 words for counters (i0 + j, c1, c2, c3), j < n, key = seed,
+ * into the device array out_dev[4*n] (enqueued on hip_stream). */
+lll_status lll_philox4x32_10(uint64_t seed, uint32_t i0, int64_t n, uint32_t c1, uint32_t c2,
+                             uint32_t c3, uint32_t* out_dev, void* hip_stream);
+
+const char* lll_last_error(void);
+const char* lll_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLL_H */

@@ -124,6 +124,8 @@ def lib():
         L.orc_rotate.argtypes = [dp, dp, dp]
         L.orc_kick.argtypes = [G, P, C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, dp]
         L.orc_kick.restype = C.c_double
+        L.orc_kick_indexed.argtypes = [G, P, C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, u32p, dp]
+        L.orc_kick_indexed.restype = C.c_double
         L.orc_observables.argtypes = [G, P, dp, C.POINTER(Obs)]
         L.orc_steps_per_interval.argtypes = [P]
         L.orc_steps_per_interval.restype = C.c_int64
@@ -246,6 +248,17 @@ def kick(g: Geom, p: Params, s, T: float, seed: int, r: int, k: int):
     pc = p.c()
     dev = lib().orc_kick(C.byref(g), C.byref(pc), float(T), C.c_uint64(seed), r,
                          C.c_uint64(k), _dp(s))
+    return s, dev
+
+
+def kick_indexed(g: Geom, p: Params, s, T: float, seed: int, r: int, k: int, site_id):
+    """Kick of a cut-out whose site j draws its normals from counter site_id[j]."""
+    N = nsites(g)
+    s = _state(s, N)
+    ids = np.ascontiguousarray(site_id, dtype=np.uint32)
+    pc = p.c()
+    dev = lib().orc_kick_indexed(C.byref(g), C.byref(pc), float(T), C.c_uint64(seed), r,
+                                 C.c_uint64(k), ids.ctypes.data_as(C.POINTER(C.c_uint32)), _dp(s))
     return s, dev
 
 

@@ -417,16 +417,19 @@ void orc_rotate(const double s[3], const double phv[3], double out[3])
  * root scales each Cartesian component of G.  Each spin is rotated by
  * Eq. (6), then READING: renormalised to unit length (the paper requires
  * conserved spin length; renormalisation happens after kicks only).
- * Returns max_i | |s_i'| - 1 | measured before the renormalisation. */
-double orc_kick(const orc_geom* g, const orc_params* p, double T, uint64_t seed, uint32_t r,
-                uint64_t k, double* s)
+ * Returns max_i | |s_i'| - 1 | measured before the renormalisation.
+ * site_id (optional) gives the counter of every site when the array holds a
+ * cut-out of a larger lattice; NULL means site i uses counter i. */
+double orc_kick_indexed(const orc_geom* g, const orc_params* p, double T, uint64_t seed,
+                        uint32_t r, uint64_t k, const uint32_t* site_id, double* s)
 {
     int64_t N = nsites(g);
     double sigma = sqrt(2.0 * p->lambda * T * p->Dt);
     double maxdev = 0.0;
     for (int64_t i = 0; i < N; ++i) {
         double G[3];
-        orc_gauss3(seed, (uint32_t)i, (uint32_t)k, r, 0u, G);
+        uint32_t id = site_id ? site_id[i] : (uint32_t)i;
+        orc_gauss3(seed, id, (uint32_t)k, r, 0u, G);
         double phv[3] = {sigma * G[0], sigma * G[1], sigma * G[2]};
         double si[3] = {s[i], s[N + i], s[2 * N + i]}, so[3];
         orc_rotate(si, phv, so);
@@ -438,6 +441,13 @@ double orc_kick(const orc_geom* g, const orc_params* p, double T, uint64_t seed,
         s[2 * N + i] = so[2] / nrm;
     }
     return maxdev;
+}
+
+/* The kick of the whole lattice: site i draws its normals from counter i. */
+double orc_kick(const orc_geom* g, const orc_params* p, double T, uint64_t seed, uint32_t r,
+                uint64_t k, double* s)
+{
+    return orc_kick_indexed(g, p, T, seed, r, k, NULL, s);
 }
 
 /* ------------------------------------------------------------------------ */

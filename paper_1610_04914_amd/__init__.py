@@ -1,0 +1,429 @@
+"""Python binding of liblll, the MI355X (gfx950) pulse-noise
+Landau-Lifshitz-Langevin library (Garanin, arXiv:1610.04914).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``liblll.so``; PyTorch provides device memory and the HIP stream.  The
+functions ``lll_*`` mirror the C ABI of ``include/lll.h`` one to one;
+``Lattice`` and ``Batch`` are thin handles over them.  There is no CPU
+fallback: importing works anywhere, but any call fails loudly when the
+library or a GPU is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import warnings
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblll.so")
+
+LLL_OK = 0
+LLL_EINVAL, LLL_ENOMEM, LLL_EDEVICE, LLL_EUNSUPPORTED, LLL_ENONFINITE = -1, -2, -3, -4, -5
+LLL_WARN_APPLICABILITY = 1
+LLL_FP64, LLL_FP32 = 0, 1
+LLL_BC_PERIODIC, LLL_BC_FREE = 0, 1
+LLL_INIT_RANDOM_SPHERE, LLL_INIT_DIRECTION, LLL_INIT_KEEP = 0, 1, 2
+
+
+class LLLError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"liblll status {status}: {msg}")
+        self.status = status
+
+
+class ApplicabilityWarning(UserWarning):
+    pass
+
+
+class lll_params(C.Structure):
+    _fields_ = [
+        ("J", C.c_double), ("H", C.c_double * 3), ("D", C.c_double), ("e", C.c_double * 3),
+        ("D_site", C.c_void_p), ("e_site", C.c_void_p),
+        ("lambda_", C.c_double), ("T", C.c_double), ("dt", C.c_double), ("Dt", C.c_double),
+        ("precession", C.c_int32), ("integrator", C.c_int32), ("seed", C.c_uint64),
+    ]
+
+
+class lll_obs(C.Structure):
+    _fields_ = [("E_total", C.c_double), ("E_exch", C.c_double), ("E_zeeman", C.c_double),
+                ("E_anis", C.c_double), ("m", C.c_double * 3), ("max_norm_dev", C.c_double)]
+
+    def as_dict(self):
+        return {"E_total": self.E_total, "E_exch": self.E_exch, "E_zeeman": self.E_zeeman,
+                "E_anis": self.E_anis, "m": tuple(self.m), "max_norm_dev": self.max_norm_dev}
+
+
+class lll_replica_desc(C.Structure):
+    _fields_ = [
+        ("Lx", C.c_int32), ("Ly", C.c_int32), ("Lz", C.c_int32), ("bc", C.c_int32),
+        ("J", C.c_double), ("H", C.c_double * 3), ("D", C.c_double), ("e", C.c_double * 3),
+        ("lambda_", C.c_double), ("T", C.c_double),
+        ("seed", C.c_uint64), ("replica", C.c_uint32), ("init", C.c_int32),
+    ]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """Loads liblll.so; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "or python -m paper_1610_04914_amd.build")
+    L = C.CDLL(LIB_PATH)
+    pp = C.POINTER(lll_params)
+    L.lll_init_lattice.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                   C.POINTER(C.c_double), C.c_uint64, _P, _P, _P, _P, C.POINTER(_P)]
+    L.lll_step_conservative.argtypes = [_P, pp, C.c_int64]
+    L.lll_noise_pulse.argtypes = [_P, pp, C.c_uint64]
+    L.lll_observables.argtypes = [_P, pp, C.POINTER(lll_obs)]
+    L.lll_run.argtypes = [_P, pp, C.c_uint64, C.c_int64, C.POINTER(C.c_double), C.c_int32,
+                          C.POINTER(lll_obs)]
+    L.lll_get_state.argtypes = [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P)]
+    L.lll_kick_norm_dev.argtypes = [_P, C.POINTER(C.c_double), C.c_int32]
+    L.lll_accumulators.argtypes = [_P, C.POINTER(C.c_double), C.c_int32]
+    L.lll_set_step_config.argtypes = [_P, C.c_int32, C.c_int32]
+    L.lll_get_step_config.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.lll_step_variant_info.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    L.lll_autotune.argtypes = [_P, pp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.lll_adjoint.argtypes = [_P, pp, C.c_uint64, C.c_int64, C.c_int32, C.c_double,
+                              C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_double), _P, _P]
+    L.lll_destroy.argtypes = [_P]
+    L.lll_destroy.restype = None
+    L.lll_batch_create.argtypes = [C.c_int32, C.POINTER(lll_replica_desc), C.c_int32, C.c_double,
+                                   C.c_double, C.c_int32, _P, C.POINTER(_P)]
+    L.lll_batch_run.argtypes = [_P, C.c_uint64, C.c_int64, C.c_int32, C.POINTER(lll_obs)]
+    L.lll_batch_observables.argtypes = [_P, C.POINTER(lll_obs)]
+    L.lll_batch_state.argtypes = [_P, C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P)]
+    L.lll_batch_accumulators.argtypes = [_P, C.POINTER(C.c_double), C.c_int32]
+    L.lll_batch_destroy.argtypes = [_P]
+    L.lll_batch_destroy.restype = None
+    L.lll_philox4x32_10.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32, C.c_uint32,
+                                    C.c_uint32, _P, _P]
+    L.lll_last_error.restype = C.c_char_p
+    L.lll_version.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str = "") -> int:
+    if status < 0:
+        raise LLLError(status, (lib().lll_last_error() or b"").decode() + (f" ({what})" if what else ""))
+    if status > 0:
+        warnings.warn((lib().lll_last_error() or b"").decode(), ApplicabilityWarning, stacklevel=3)
+    return status
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("liblll needs a HIP GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------- C ABI, same names --
+def lll_init_lattice(Lx, Ly, Lz, bc, prec, mode, dir3, seed, sx, sy, sz, stream):
+    h = _P()
+    d = (C.c_double * 3)(*dir3) if dir3 is not None else None
+    _check(lib().lll_init_lattice(Lx, Ly, Lz, bc, prec, mode, d, C.c_uint64(seed), sx, sy, sz,
+                                  stream, C.byref(h)), "lll_init_lattice")
+    return h
+
+
+def lll_step_conservative(h, params: lll_params, n_steps: int):
+    return _check(lib().lll_step_conservative(h, C.byref(params), int(n_steps)))
+
+
+def lll_noise_pulse(h, params: lll_params, pulse_index: int):
+    return _check(lib().lll_noise_pulse(h, C.byref(params), C.c_uint64(pulse_index)))
+
+
+def lll_observables(h, params: lll_params) -> dict:
+    o = lll_obs()
+    _check(lib().lll_observables(h, C.byref(params), C.byref(o)))
+    return o.as_dict()
+
+
+def lll_run(h, params: lll_params, first_pulse: int, n_pulses: int, T_per_pulse=None,
+            obs_every: int = 0):
+    nm = n_pulses // obs_every if obs_every > 0 else 0
+    tr = (lll_obs * max(nm, 1))()
+    Tp = None
+    if T_per_pulse is not None:
+        Tp = (C.c_double * n_pulses)(*[float(v) for v in T_per_pulse])
+    st = lib().lll_run(h, C.byref(params), C.c_uint64(first_pulse), int(n_pulses), Tp,
+                       int(obs_every), tr if nm > 0 else None)
+    _check(st, "lll_run")
+    return [tr[i].as_dict() for i in range(nm)]
+
+
+def lll_destroy(h):
+    lib().lll_destroy(h)
+
+
+def lll_philox4x32_10(seed: int, i0: int, n: int, c1: int, c2: int, c3: int, out_ptr, stream):
+    return _check(lib().lll_philox4x32_10(C.c_uint64(seed), i0, int(n), c1, c2, c3,
+                                          C.c_void_p(out_ptr), stream))
+
+
+def lll_version() -> str:
+    return lib().lll_version().decode()
+
+
+# ------------------------------------------------------------ handles -------
+@dataclass
+class Params:
+    """Parameters of the method (units gamma = mu_0 = k_B = 1)."""
+    J: float = 1.0
+    H: Sequence[float] = (0.0, 0.0, 0.0)
+    D: float = 0.0
+    e: Sequence[float] = (0.0, 0.0, 1.0)
+    lam: float = 0.01
+    T: float = 1.0
+    dt: float = 0.1
+    Dt: float = 1.0
+    precession: bool = True
+    seed: int = 0
+    D_site: Optional[object] = None   # device tensor [N] of the lattice dtype
+    e_site: Optional[object] = None   # device tensor [3, N] of the lattice dtype
+
+    def c(self) -> lll_params:
+        p = lll_params()
+        p.J = float(self.J)
+        p.H[:] = [float(v) for v in self.H]
+        p.D = float(self.D)
+        p.e[:] = [float(v) for v in self.e]
+        p.D_site = self.D_site.data_ptr() if self.D_site is not None else None
+        p.e_site = self.e_site.data_ptr() if self.e_site is not None else None
+        p.lambda_ = float(self.lam)
+        p.T = float(self.T)
+        p.dt = float(self.dt)
+        p.Dt = float(self.Dt)
+        p.precession = 1 if self.precession else 0
+        p.integrator = 0
+        p.seed = int(self.seed)
+        return p
+
+
+_PREC = {"fp64": LLL_FP64, "fp32": LLL_FP32}
+_BC = {"periodic": LLL_BC_PERIODIC, "free": LLL_BC_FREE}
+
+
+class Lattice:
+    """A lattice whose spins live in a torch tensor `state` of shape (3, N)
+    (component-major, i = x + Lx*(y + Ly*z)) on the current HIP device."""
+
+    def __init__(self, shape, bc: str = "periodic", precision: str = "fp32", init: str = "random",
+                 direction=(0.0, 0.0, 1.0), seed: int = 0, state=None):
+        torch = _torch()
+        self.shape = tuple(int(v) for v in shape)
+        self.N = self.shape[0] * self.shape[1] * self.shape[2]
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        if state is None:
+            state = torch.empty((3, self.N), dtype=self.dtype, device="cuda")
+            mode = {"random": LLL_INIT_RANDOM_SPHERE, "direction": LLL_INIT_DIRECTION}[init]
+        else:
+            if state.dtype != self.dtype or tuple(state.shape) != (3, self.N) or not state.is_cuda:
+                raise ValueError("state must be a (3, N) CUDA tensor of the lattice dtype")
+            state = state.contiguous()
+            mode = LLL_INIT_KEEP
+        self.state = state
+        ptrs = [C.c_void_p(state[c].data_ptr()) for c in range(3)]
+        self.h = lll_init_lattice(*self.shape, _BC[bc], _PREC[precision], mode, direction, seed,
+                                  *ptrs, _stream())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lll_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, p: Params, n_steps: int = 1):
+        return lll_step_conservative(self.h, p.c(), n_steps)
+
+    def pulse(self, p: Params, k: int):
+        return lll_noise_pulse(self.h, p.c(), k)
+
+    def observables(self, p: Params) -> dict:
+        return lll_observables(self.h, p.c())
+
+    def run(self, p: Params, first_pulse: int = 0, n_pulses: int = 1, T_per_pulse=None,
+            obs_every: int = 0):
+        return lll_run(self.h, p.c(), first_pulse, n_pulses, T_per_pulse, obs_every)
+
+    def kick_norm_dev(self, reset: bool = False) -> float:
+        v = C.c_double()
+        _check(lib().lll_kick_norm_dev(self.h, C.byref(v), 1 if reset else 0))
+        return v.value
+
+    def accumulators(self, reset: bool = False):
+        a = (C.c_double * 8)()
+        _check(lib().lll_accumulators(self.h, a, 1 if reset else 0))
+        return list(a)
+
+    def set_step_config(self, variant: int, bz: int = 0):
+        _check(lib().lll_set_step_config(self.h, variant, bz))
+
+    def step_config(self):
+        v, b = C.c_int32(), C.c_int32()
+        _check(lib().lll_get_step_config(self.h, C.byref(v), C.byref(b)))
+        return v.value, b.value
+
+    def autotune(self, p: Params, cache_path: Optional[str] = None):
+        v, b = C.c_int32(), C.c_int32()
+        _check(lib().lll_autotune(self.h, p.c(), cache_path.encode() if cache_path else None,
+                                  C.byref(v), C.byref(b)))
+        return v.value, b.value
+
+    def adjoint(self, p: Params, first_pulse: int, n_pulses: int, ckpt_every: int = 10,
+                wE: float = 1.0, wm=(0.0, 0.0, 0.0), want_g_s0: bool = False):
+        """Loss L = wE E(s_T) + wm.m(s_T) of lll_run from the current state and
+        its gradients w.r.t. H, J, D (per site when p.D_site is set) and s_0."""
+        torch = _torch()
+        loss = C.c_double()
+        gH = (C.c_double * 3)()
+        gJ = C.c_double()
+        wmc = (C.c_double * 3)(*[float(v) for v in wm])
+        if p.D_site is not None:
+            gD = torch.zeros(self.N, dtype=torch.float64, device="cuda")
+            gDp = C.c_void_p(gD.data_ptr())
+        else:
+            gDh = C.c_double()
+            gD = None
+            gDp = C.cast(C.byref(gDh), C.c_void_p)
+        gs0 = torch.zeros((3, self.N), dtype=self.dtype, device="cuda") if want_g_s0 else None
+        _check(lib().lll_adjoint(self.h, C.byref(p.c()), C.c_uint64(first_pulse), int(n_pulses),
+                                 int(ckpt_every), float(wE), wmc, C.byref(loss), gH, C.byref(gJ),
+                                 gDp, C.c_void_p(gs0.data_ptr()) if gs0 is not None else None),
+               "lll_adjoint")
+        return {"loss": loss.value, "g_H": list(gH), "g_J": gJ.value,
+                "g_D": gD if gD is not None else gDh.value, "g_s0": gs0}
+
+
+def step_variant_info(precision: str, variant: int):
+    a = (C.c_int32 * 4)()
+    _check(lib().lll_step_variant_info(_PREC[precision], variant, a))
+    return {"bx": a[0], "by": a[1], "threads": a[2], "lds_bytes": a[3]}
+
+
+def step_variants(precision: str):
+    out = [0]
+    v = 1
+    while True:
+        a = (C.c_int32 * 4)()
+        if lib().lll_step_variant_info(_PREC[precision], v, a) != 0:
+            break
+        out.append(v)
+        v += 1
+    return out
+
+
+class Batch:
+    """Many independent replicas advanced together (one captured graph per run)."""
+
+    def __init__(self, replicas, precision: str = "fp32", dt: float = 0.1, Dt: float = 1.0,
+                 precession: bool = True):
+        _torch()
+        n = len(replicas)
+        arr = (lll_replica_desc * n)()
+        self.shapes = []
+        for i, r in enumerate(replicas):
+            d = arr[i]
+            d.Lx, d.Ly, d.Lz = r["L"]
+            d.bc = _BC[r.get("bc", "periodic")]
+            d.J = float(r.get("J", 1.0))
+            d.H[:] = [float(v) for v in r.get("H", (0, 0, 0))]
+            d.D = float(r.get("D", 0.0))
+            d.e[:] = [float(v) for v in r.get("e", (0, 0, 1))]
+            d.lambda_ = float(r["lam"])
+            d.T = float(r["T"])
+            d.seed = int(r["seed"])
+            d.replica = int(r.get("replica", i))
+            d.init = LLL_INIT_DIRECTION if r.get("init", "random") == "direction" else LLL_INIT_RANDOM_SPHERE
+            self.shapes.append(tuple(r["L"]))
+        self.n = n
+        self.precision = precision
+        h = _P()
+        _check(lib().lll_batch_create(n, arr, _PREC[precision], float(dt), float(Dt),
+                                      1 if precession else 0, _stream(), C.byref(h)),
+               "lll_batch_create")
+        self.h = h
+
+    def run(self, first_pulse: int, n_pulses: int, obs_every: int = 0):
+        nm = n_pulses // obs_every if obs_every > 0 else 0
+        tr = (lll_obs * max(nm * self.n, 1))()
+        _check(lib().lll_batch_run(self.h, C.c_uint64(first_pulse), int(n_pulses), int(obs_every),
+                                   tr if nm > 0 else None), "lll_batch_run")
+        return [[tr[m * self.n + r].as_dict() for r in range(self.n)] for m in range(nm)]
+
+    def observables(self):
+        o = (lll_obs * self.n)()
+        _check(lib().lll_batch_observables(self.h, o))
+        return [o[r].as_dict() for r in range(self.n)]
+
+    def state(self, r: int):
+        """Copy of replica r's state as a (3, N) torch tensor."""
+        torch = _torch()
+        px, py, pz = _P(), _P(), _P()
+        _check(lib().lll_batch_state(self.h, r, C.byref(px), C.byref(py), C.byref(pz)))
+        Lx, Ly, Lz = self.shapes[r]
+        N = Lx * Ly * Lz
+        dt = torch.float64 if self.precision == "fp64" else torch.float32
+        es = 8 if self.precision == "fp64" else 4
+        out = torch.empty((3, N), dtype=dt, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        hipMemcpy = _hip_memcpy()
+        for c, p in enumerate((px, py, pz)):
+            _hip_check(hipMemcpy(C.c_void_p(out[c].data_ptr()), p, C.c_size_t(N * es), 3))
+        return out
+
+    def accumulators(self, reset: bool = False):
+        a = (C.c_double * (8 * self.n))()
+        _check(lib().lll_batch_accumulators(self.h, a, 1 if reset else 0))
+        return [list(a[8 * r: 8 * r + 8]) for r in range(self.n)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lll_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip = None
+
+
+def _hip_memcpy():
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    return _hip.hipMemcpy
+
+
+def _hip_check(rc: int):
+    if rc != 0:
+        raise LLLError(LLL_EDEVICE, f"hipMemcpy failed with {rc}")

@@ -1,0 +1,462 @@
+// Per-site kernels of the pulse-noise path: random words, initial states,
+// the pulse-noise kick, fp64 observables, and the unfused RK4 step (one
+// launch per Runge-Kutta stage, used for small lattices and as a tuning
+// candidate).
+#include "lll_device.hpp"
+
+namespace lll {
+
+constexpr int kSiteBlock = 256;
+constexpr int kObsBlock = 256;
+
+// ------------------------------------------------------------------ words --
+__global__ void __launch_bounds__(256) philox_words_kernel(uint64_t seed, uint32_t i0, int64_t n,
+                                                           uint32_t c1, uint32_t c2, uint32_t c3,
+                                                           uint32_t* out) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint4 w = philox_site(seed, i0 + (uint32_t)j, c1, c2, c3);
+    out[4 * j + 0] = w.x;
+    out[4 * j + 1] = w.y;
+    out[4 * j + 2] = w.z;
+    out[4 * j + 3] = w.w;
+}
+
+hipError_t launch_philox_words(uint64_t seed, uint32_t i0, int64_t n, uint32_t c1, uint32_t c2,
+                               uint32_t c3, uint32_t* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(philox_words_kernel, dim3((unsigned)nb), dim3(256), 0, st, seed, i0, n, c1,
+                       c2, c3, out);
+    return hipGetLastError();
+}
+
+// Site owned by this thread in a per-site launch: block b belongs to replica
+// blk_rep[b]; returns false past the replica's last site.
+struct SiteCtx {
+    int r;
+    int64_t i;   // site within the replica
+    int64_t gi;  // site in the packed arrays
+};
+
+__device__ __forceinline__ bool site_of_thread(const RepDev* reps, const int32_t* blk_rep,
+                                               SiteCtx& c) {
+    const int b = blockIdx.x;
+    c.r = blk_rep[b];
+    const RepDev& R = reps[c.r];
+    const int64_t N = (int64_t)R.Lx * R.Ly * R.Lz;
+    c.i = (int64_t)(b - R.sb0) * kSiteBlock + threadIdx.x;
+    c.gi = R.off + c.i;
+    return c.i < N;
+}
+
+// ------------------------------------------------------------------ init ---
+// Random sphere: Philox (i, 0, r, tag 1), z = 2 u0 - 1, azimuth 2 pi u1.
+template <typename T>
+__global__ void __launch_bounds__(kSiteBlock)
+    init_kernel(const RepDev* reps, const int32_t* blk_rep, State s, double dx, double dy,
+                double dz) {
+    SiteCtx c;
+    if (!site_of_thread(reps, blk_rep, c)) return;
+    const RepDev& R = reps[c.r];
+    double x, y, z;
+    if (R.init == 0) {
+        const uint4 w = philox_site(R.seed, (uint32_t)c.i, 0u, R.rid, 1u);
+        const double sc = 2.3283064365386963e-10;
+        z = 2.0 * (((double)w.x + 0.5) * sc) - 1.0;
+        const double ph = 6.283185307179586 * (((double)w.y + 0.5) * sc);
+        const double rho = sqrt(1.0 - z * z);
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        x = rho * cs;
+        y = rho * sn;
+    } else {
+        x = dx;
+        y = dy;
+        z = dz;
+    }
+    static_cast<T*>(s.x)[c.gi] = (T)x;
+    static_cast<T*>(s.y)[c.gi] = (T)y;
+    static_cast<T*>(s.z)[c.gi] = (T)z;
+}
+
+hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
+                       int mode, double dx, double dy, double dz, hipStream_t st) {
+    (void)mode;
+    if (nblk <= 0) return hipSuccess;
+    if (prec == 0)
+        hipLaunchKernelGGL(init_kernel<double>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
+                           s, dx, dy, dz);
+    else
+        hipLaunchKernelGGL(init_kernel<float>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
+                           s, dx, dy, dz);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ kick ---
+// Block-wide max of a non-negative double, then one integer atomic on its bit
+// pattern (order-independent, so deterministic; a NaN compares above all).
+__device__ __forceinline__ void block_max_to(double v, unsigned long long* dst) {
+    __shared__ double red[kSiteBlock];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kSiteBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double a = red[threadIdx.x], b = red[threadIdx.x + o];
+            red[threadIdx.x] = (b > a || b != b) ? b : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(dst, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSiteBlock)
+    kick_kernel(const RepDev* reps, const int32_t* blk_rep, State s, uint64_t k,
+                double sigma_override, unsigned long long* kickdev) {
+    SiteCtx c;
+    const bool live = site_of_thread(reps, blk_rep, c);
+    double dev = 0.0;
+    if (live) {
+        const RepDev& R = reps[c.r];
+        const double sg = sigma_override >= 0.0 ? sigma_override : R.sigma;
+        const uint4 w = philox_site(R.seed, (uint32_t)c.i, (uint32_t)k, R.rid, 0u);
+        T* px = static_cast<T*>(s.x);
+        T* py = static_cast<T*>(s.y);
+        T* pz = static_cast<T*>(s.z);
+        T x = px[c.gi], y = py[c.gi], z = pz[c.gi];
+        dev = kick_spin<T>(x, y, z, w, (T)sg);
+        px[c.gi] = x;
+        py[c.gi] = y;
+        pz[c.gi] = z;
+    }
+    block_max_to(dev, kickdev + blk_rep[blockIdx.x]);
+}
+
+hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
+                       uint64_t k, double sigma_override, unsigned long long* kickdev,
+                       hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    if (prec == 0)
+        hipLaunchKernelGGL(kick_kernel<double>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
+                           s, k, sigma_override, kickdev);
+    else
+        hipLaunchKernelGGL(kick_kernel<float>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
+                           s, k, sigma_override, kickdev);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- observables ---
+// Pass 1: per-block fp64 partial sums {sum_bonds s_i.s_j, sum H.s, sum D (s.e)^2,
+// sum s (3), max | |s| - 1 |} in a fixed order; pass 2 sums the partials of
+// every replica in a fixed order.  No floating-point atomics: results are
+// bit-identical from run to run.
+template <typename T>
+__device__ __forceinline__ void load3(const State& s, int64_t g, double& x, double& y, double& z) {
+    x = (double)static_cast<const T*>(s.x)[g];
+    y = (double)static_cast<const T*>(s.y)[g];
+    z = (double)static_cast<const T*>(s.z)[g];
+}
+
+template <typename T, int ANIS>
+__global__ void __launch_bounds__(kObsBlock)
+    obs_partial_kernel(const RepDev* reps, const int32_t* oblk_rep, State s, double* partials) {
+    const int b = blockIdx.x;
+    const int r = oblk_rep[b];
+    const RepDev& R = reps[r];
+    const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
+    const int64_t N = (int64_t)Lx * Ly * Lz;
+    const int lb = b - R.ob0, nb = R.nob;
+    const bool pbc = R.bc == 0;
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    double dev = 0.0;
+    for (int64_t i = (int64_t)lb * kObsBlock + threadIdx.x; i < N; i += (int64_t)nb * kObsBlock) {
+        const int x = (int)(i % Lx);
+        const int y = (int)((i / Lx) % Ly);
+        const int z = (int)(i / ((int64_t)Lx * Ly));
+        const int64_t g = R.off + i;
+        double sx, sy, sz;
+        load3<T>(s, g, sx, sy, sz);
+        double bx = 0, by = 0, bz = 0;
+        if (pbc || x + 1 < Lx) {
+            const int xn = (x + 1 == Lx) ? 0 : x + 1;
+            double tx, ty, tz;
+            load3<T>(s, R.off + xn + (int64_t)Lx * (y + (int64_t)Ly * z), tx, ty, tz);
+            bx += tx; by += ty; bz += tz;
+        }
+        if (pbc || y + 1 < Ly) {
+            const int yn = (y + 1 == Ly) ? 0 : y + 1;
+            double tx, ty, tz;
+            load3<T>(s, R.off + x + (int64_t)Lx * (yn + (int64_t)Ly * z), tx, ty, tz);
+            bx += tx; by += ty; bz += tz;
+        }
+        if (pbc || z + 1 < Lz) {
+            const int zn = (z + 1 == Lz) ? 0 : z + 1;
+            double tx, ty, tz;
+            load3<T>(s, R.off + x + (int64_t)Lx * (y + (int64_t)Ly * zn), tx, ty, tz);
+            bx += tx; by += ty; bz += tz;
+        }
+        q[0] += sx * bx + sy * by + sz * bz;
+        q[1] += R.H[0] * sx + R.H[1] * sy + R.H[2] * sz;
+        if constexpr (ANIS == ANIS_Z) {
+            q[2] += R.D * sz * sz;
+        } else if constexpr (ANIS == ANIS_AXIS) {
+            const double se = sx * R.e[0] + sy * R.e[1] + sz * R.e[2];
+            q[2] += R.D * se * se;
+        } else if constexpr (ANIS == ANIS_SITE) {
+            const T* Ds = static_cast<const T*>(R.D_site);
+            const T* es = static_cast<const T*>(R.e_site);
+            const double se = sx * (double)es[i] + sy * (double)es[N + i] + sz * (double)es[2 * N + i];
+            q[2] += (double)Ds[i] * se * se;
+        }
+        q[3] += sx;
+        q[4] += sy;
+        q[5] += sz;
+        const double d = fabs(sqrt(sx * sx + sy * sy + sz * sz) - 1.0);
+        dev = (d > dev || d != d) ? d : dev;
+    }
+    __shared__ double red[7][kObsBlock];
+    for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = q[j];
+    red[6][threadIdx.x] = dev;
+    __syncthreads();
+    for (int o = kObsBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
+            const double a = red[6][threadIdx.x], c = red[6][threadIdx.x + o];
+            red[6][threadIdx.x] = (c > a || c != c) ? c : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) partials[(int64_t)b * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256)
+    obs_final_kernel(const RepDev* reps, const double* partials, double* result, double* accum,
+                     int accumulate) {
+    const int r = blockIdx.x;
+    const RepDev& R = reps[r];
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    double dev = 0.0;
+    for (int b = R.ob0 + threadIdx.x; b < R.ob0 + R.nob; b += 256) {
+        for (int j = 0; j < 6; ++j) q[j] += partials[(int64_t)b * 8 + j];
+        const double d = partials[(int64_t)b * 8 + 6];
+        dev = (d > dev || d != d) ? d : dev;
+    }
+    __shared__ double red[7][256];
+    for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = q[j];
+    red[6][threadIdx.x] = dev;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
+            const double a = red[6][threadIdx.x], c = red[6][threadIdx.x + o];
+            red[6][threadIdx.x] = (c > a || c != c) ? c : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double N = (double)R.Lx * R.Ly * R.Lz;
+        const double Eex = -R.J * red[0][0];
+        const double Ez = -red[1][0];
+        const double Ea = -red[2][0];
+        const double Et = Eex + Ez + Ea;
+        const double mx = red[3][0] / N, my = red[4][0] / N, mz = red[5][0] / N;
+        double* o = result + (int64_t)r * 8;
+        o[0] = Et;
+        o[1] = Eex;
+        o[2] = Ez;
+        o[3] = Ea;
+        o[4] = mx;
+        o[5] = my;
+        o[6] = mz;
+        o[7] = red[6][0];
+        if (accumulate) {
+            double* a = accum + (int64_t)r * 8;
+            const double m2 = mx * mx + my * my + mz * mz;
+            a[0] += 1.0;
+            a[1] += Et;
+            a[2] += Et * Et;
+            a[3] += sqrt(m2);
+            a[4] += m2;
+            a[5] += mx;
+            a[6] += my;
+            a[7] += mz;
+        }
+    }
+}
+
+template <typename T>
+static void launch_obs_t(int anis, const RepDev* reps, const int32_t* oblk_rep, int nobblk, State s,
+                         double* partials, hipStream_t st) {
+    switch (anis) {
+        case ANIS_NONE:
+            hipLaunchKernelGGL((obs_partial_kernel<T, ANIS_NONE>), dim3(nobblk), dim3(kObsBlock), 0,
+                               st, reps, oblk_rep, s, partials);
+            break;
+        case ANIS_Z:
+            hipLaunchKernelGGL((obs_partial_kernel<T, ANIS_Z>), dim3(nobblk), dim3(kObsBlock), 0, st,
+                               reps, oblk_rep, s, partials);
+            break;
+        case ANIS_AXIS:
+            hipLaunchKernelGGL((obs_partial_kernel<T, ANIS_AXIS>), dim3(nobblk), dim3(kObsBlock), 0,
+                               st, reps, oblk_rep, s, partials);
+            break;
+        default:
+            hipLaunchKernelGGL((obs_partial_kernel<T, ANIS_SITE>), dim3(nobblk), dim3(kObsBlock), 0,
+                               st, reps, oblk_rep, s, partials);
+            break;
+    }
+}
+
+hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
+                      int nobblk, int nrep, State s, double* partials, double* result,
+                      double* accum, int accumulate, hipStream_t st) {
+    if (nobblk <= 0 || nrep <= 0) return hipSuccess;
+    if (prec == 0)
+        launch_obs_t<double>(anis, reps, oblk_rep, nobblk, s, partials, st);
+    else
+        launch_obs_t<float>(anis, reps, oblk_rep, nobblk, s, partials, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(obs_final_kernel, dim3(nrep), dim3(256), 0, st, reps, partials, result,
+                       accum, accumulate);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------- unfused RK4 step --
+// Stage s reads its input y_s (neighbourhood), the step's start state x and
+// the accumulator; stage 1: acc = x + k/6, y2 = x + k/2; stage 2: acc += k/3,
+// y3 = x + k/2; stage 3: acc += k/3, y4 = x + k; stage 4: x' = acc + k/6
+// (written over x, which stage 4 does not read).
+template <typename T, bool PREC, int ANIS>
+__global__ void __launch_bounds__(kSiteBlock)
+    stage_kernel(const RepDev* reps, const int32_t* blk_rep, State yin, State xs, State acc,
+                 State out, int stage) {
+    SiteCtx c;
+    if (!site_of_thread(reps, blk_rep, c)) return;
+    const RepDev& R = reps[c.r];
+    const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
+    const int64_t N = (int64_t)Lx * Ly * Lz;
+    const int x = (int)(c.i % Lx);
+    const int y = (int)((c.i / Lx) % Ly);
+    const int z = (int)(c.i / ((int64_t)Lx * Ly));
+    const bool pbc = R.bc == 0;
+    const T* yx = static_cast<const T*>(yin.x);
+    const T* yy = static_cast<const T*>(yin.y);
+    const T* yz = static_cast<const T*>(yin.z);
+    T nx = 0, ny = 0, nz = 0;
+    auto add = [&](int xx, int yy_, int zz) {
+        const int64_t j = R.off + xx + (int64_t)Lx * (yy_ + (int64_t)Ly * zz);
+        nx += yx[j];
+        ny += yy[j];
+        nz += yz[j];
+    };
+    if (pbc || x > 0) add(x > 0 ? x - 1 : Lx - 1, y, z);
+    if (pbc || x + 1 < Lx) add(x + 1 < Lx ? x + 1 : 0, y, z);
+    if (pbc || y > 0) add(x, y > 0 ? y - 1 : Ly - 1, z);
+    if (pbc || y + 1 < Ly) add(x, y + 1 < Ly ? y + 1 : 0, z);
+    if (pbc || z > 0) add(x, y, z > 0 ? z - 1 : Lz - 1);
+    if (pbc || z + 1 < Lz) add(x, y, z + 1 < Lz ? z + 1 : 0);
+    const T sx = yx[c.gi], sy = yy[c.gi], sz = yz[c.gi];
+    const Coef<T> C = load_coef<T>(R);
+    T Di = 0, ex = 0, ey = 0, ez = 0;
+    if constexpr (ANIS == ANIS_SITE) {
+        Di = static_cast<const T*>(R.D_site)[c.i];
+        const T* es = static_cast<const T*>(R.e_site);
+        ex = es[c.i];
+        ey = es[N + c.i];
+        ez = es[2 * N + c.i];
+    }
+    T kx, ky, kz;
+    stage_k<T, PREC, ANIS>(sx, sy, sz, nx, ny, nz, C, Di, ex, ey, ez, kx, ky, kz);
+    T* ax = static_cast<T*>(acc.x);
+    T* ay = static_cast<T*>(acc.y);
+    T* az = static_cast<T*>(acc.z);
+    T* ox = static_cast<T*>(out.x);
+    T* oy = static_cast<T*>(out.y);
+    T* oz = static_cast<T*>(out.z);
+    const T* xx = static_cast<const T*>(xs.x);
+    const T* xy = static_cast<const T*>(xs.y);
+    const T* xz = static_cast<const T*>(xs.z);
+    const T c6 = T(1) / T(6), c3 = T(1) / T(3), c2 = T(0.5);
+    const int64_t g = c.gi;
+    if (stage == 1) {
+        const T x0 = xx[g], x1 = xy[g], x2 = xz[g];
+        ax[g] = kx * c6 + x0;
+        ay[g] = ky * c6 + x1;
+        az[g] = kz * c6 + x2;
+        ox[g] = kx * c2 + x0;
+        oy[g] = ky * c2 + x1;
+        oz[g] = kz * c2 + x2;
+    } else if (stage == 2 || stage == 3) {
+        ax[g] = kx * c3 + ax[g];
+        ay[g] = ky * c3 + ay[g];
+        az[g] = kz * c3 + az[g];
+        const T w = stage == 2 ? c2 : T(1);
+        ox[g] = kx * w + xx[g];
+        oy[g] = ky * w + xy[g];
+        oz[g] = kz * w + xz[g];
+    } else {
+        ox[g] = kx * c6 + ax[g];
+        oy[g] = ky * c6 + ay[g];
+        oz[g] = kz * c6 + az[g];
+    }
+}
+
+template <typename T, bool PREC, int ANIS>
+static hipError_t step_unfused_t(const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
+                                 State yA, State yB, State acc, hipStream_t st) {
+    const State ins[4] = {s, yA, yB, yA};
+    const State outs[4] = {yA, yB, yA, s};
+    for (int q = 0; q < 4; ++q) {
+        hipLaunchKernelGGL((stage_kernel<T, PREC, ANIS>), dim3(nblk), dim3(kSiteBlock), 0, st, reps,
+                           blk_rep, ins[q], s, acc, outs[q], q + 1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T, bool PREC>
+static hipError_t step_unfused_p(int anis, const RepDev* reps, const int32_t* blk_rep, int nblk,
+                                 State s, State yA, State yB, State acc, hipStream_t st) {
+    switch (anis) {
+        case ANIS_NONE: return step_unfused_t<T, PREC, ANIS_NONE>(reps, blk_rep, nblk, s, yA, yB, acc, st);
+        case ANIS_Z: return step_unfused_t<T, PREC, ANIS_Z>(reps, blk_rep, nblk, s, yA, yB, acc, st);
+        case ANIS_AXIS: return step_unfused_t<T, PREC, ANIS_AXIS>(reps, blk_rep, nblk, s, yA, yB, acc, st);
+        default: return step_unfused_t<T, PREC, ANIS_SITE>(reps, blk_rep, nblk, s, yA, yB, acc, st);
+    }
+}
+
+hipError_t launch_step_unfused(int prec, int precession, int anis, const RepDev* reps,
+                               const int32_t* blk_rep, int nblk, State s, State yA, State yB,
+                               State acc, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    if (prec == 0)
+        return precession ? step_unfused_p<double, true>(anis, reps, blk_rep, nblk, s, yA, yB, acc, st)
+                          : step_unfused_p<double, false>(anis, reps, blk_rep, nblk, s, yA, yB, acc, st);
+    return precession ? step_unfused_p<float, true>(anis, reps, blk_rep, nblk, s, yA, yB, acc, st)
+                      : step_unfused_p<float, false>(anis, reps, blk_rep, nblk, s, yA, yB, acc, st);
+}
+
+// ------------------------------------------------------------------ copy ---
+template <typename T>
+__global__ void __launch_bounds__(256) copy_kernel(State dst, State src, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    static_cast<T*>(dst.x)[i] = static_cast<const T*>(src.x)[i];
+    static_cast<T*>(dst.y)[i] = static_cast<const T*>(src.y)[i];
+    static_cast<T*>(dst.z)[i] = static_cast<const T*>(src.z)[i];
+}
+
+hipError_t launch_copy(int prec, State dst, State src, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    if (prec == 0)
+        hipLaunchKernelGGL(copy_kernel<double>, dim3((unsigned)nb), dim3(256), 0, st, dst, src, n);
+    else
+        hipLaunchKernelGGL(copy_kernel<float>, dim3((unsigned)nb), dim3(256), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace lll

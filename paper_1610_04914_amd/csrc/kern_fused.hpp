@@ -1,0 +1,406 @@
+// Fused classical RK4 step: one launch advances every replica of the batch
+// by one step, reading the state once and writing it once.
+//
+// Each workgroup owns an output tile BX x BY x bz and marches along z.  The
+// four stages are pipelined one plane apart: while plane P is loaded,
+// stage 1 works on plane P-1, stage 2 on P-2, stage 3 on P-3 and stage 4
+// writes plane P-4.  Stage s of RK4 needs its input one lattice step further
+// out than stage s+1, so stage s is evaluated on the tile grown by 4-s sites
+// in x and y (the "cone"); stage inputs of the current plane are shared
+// through LDS, while the values of a point on the planes below/above stay in
+// registers of the thread that owns the point in every stage.  Points are
+// handed to threads in ring order (core first, then rings 1..4), so each
+// stage's region is a prefix of the point list and idle lanes are confined to
+// one partial wave per stage.  With the kick flag, the pulse-noise kick of
+// Eqs. (5)-(6) is applied to the output before it is stored.
+#pragma once
+#include "lll_device.hpp"
+
+namespace lll {
+
+template <int BX, int BY>
+__host__ __device__ inline void ring_decode(int idx, int& lx, int& ly) {
+    if (idx < BX * BY) {
+        lx = idx % BX;
+        ly = idx / BX;
+        return;
+    }
+    int base = BX * BY;
+    int L = 1;
+#pragma unroll
+    for (int q = 1; q <= 4; ++q) {
+        const int cnt = (BX + 2 * q) * (BY + 2 * q) - (BX + 2 * q - 2) * (BY + 2 * q - 2);
+        if (L == q && idx >= base + cnt) {
+            base += cnt;
+            L = q + 1;
+        }
+    }
+    const int j = idx - base;
+    const int w = BX + 2 * L, h = BY + 2 * L;
+    if (j < w) {
+        lx = -L + j;
+        ly = -L;
+    } else if (j < 2 * w) {
+        lx = -L + (j - w);
+        ly = BY + L - 1;
+    } else {
+        const int jj = j - 2 * w;
+        if (jj < h - 2) {
+            lx = -L;
+            ly = -L + 1 + jj;
+        } else {
+            lx = BX + L - 1;
+            ly = -L + 1 + (jj - (h - 2));
+        }
+    }
+}
+
+template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, bool KICK>
+__global__ void __launch_bounds__(NT)
+    rk4_fused_kernel(const RepDev* __restrict__ reps, const int4* __restrict__ tiles, State in,
+                     State out, int bz_arg, uint64_t kpulse, double sigma_override,
+                     unsigned long long* kickdev) {
+    constexpr int W0 = BX + 8, W1 = BX + 6, W2 = BX + 4, W3 = BX + 2;
+    constexpr int R0 = (BX + 8) * (BY + 8);
+    constexpr int R1 = (BX + 6) * (BY + 6);
+    constexpr int R2 = (BX + 4) * (BY + 4);
+    constexpr int R3 = (BX + 2) * (BY + 2);
+    constexpr int R4 = BX * BY;
+    constexpr int NI = (R0 + NT - 1) / NT;
+
+    // Stage-input planes, double-buffered by plane parity: A1 = x on the
+    // load region, A2 = y2 on R1, A3 = y3 on R2, A4 = y4 on R3.
+    __shared__ T sA1[2][3][R0];
+    __shared__ T sA2[2][3][R1];
+    __shared__ T sA3[2][3][R2];
+    __shared__ T sA4[2][3][R3];
+
+    const int tid = threadIdx.x;
+    const int4 tl = tiles[blockIdx.x];
+    const RepDev& R = reps[tl.x];
+    const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
+    const bool pbc = R.bc == 0;
+    int bzr = bz_arg > 0 ? bz_arg : 16;
+    if (bzr > Lz) bzr = Lz;
+    const int x0 = tl.y * BX, y0 = tl.z * BY, z0 = tl.w * bzr;
+    const int zend = min(z0 + bzr, Lz);
+    const int niter = (zend - z0) + 8;
+    const int64_t plane = (int64_t)Lx * Ly;
+    const int64_t N = plane * Lz;
+    const T* __restrict__ ix = static_cast<const T*>(in.x) + R.off;
+    const T* __restrict__ iy = static_cast<const T*>(in.y) + R.off;
+    const T* __restrict__ iz = static_cast<const T*>(in.z) + R.off;
+    T* __restrict__ ox = static_cast<T*>(out.x) + R.off;
+    T* __restrict__ oy = static_cast<T*>(out.y) + R.off;
+    T* __restrict__ oz = static_cast<T*>(out.z) + R.off;
+    const Coef<T> C = load_coef<T>(R);
+    const T* Dsite = static_cast<const T*>(R.D_site);
+    const T* esite = static_cast<const T*>(R.e_site);
+
+    int o1[NI], o2[NI], o3[NI], o4[NI];
+    int col[NI];
+    bool colok[NI], outok[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+        const int idx = j * NT + tid;
+        int lx = 0, ly = 0;
+        if (idx < R0) ring_decode<BX, BY>(idx, lx, ly);
+        o1[j] = (ly + 4) * W0 + (lx + 4);
+        o2[j] = (ly + 3) * W1 + (lx + 3);
+        o3[j] = (ly + 2) * W2 + (lx + 2);
+        o4[j] = (ly + 1) * W3 + (lx + 1);
+        int gx = x0 + lx, gy = y0 + ly;
+        bool ok = idx < R0;
+        if (pbc) {
+            gx = wrap_coord(gx, Lx);
+            gy = wrap_coord(gy, Ly);
+        } else {
+            ok = ok && gx >= 0 && gx < Lx && gy >= 0 && gy < Ly;
+        }
+        colok[j] = ok;
+        col[j] = ok ? gx + Lx * gy : 0;
+        outok[j] = idx < R4 && (x0 + lx) < Lx && (y0 + ly) < Ly;
+    }
+
+    T X[NI][4][3], Y2[NI][4][3], Y3[NI][4][3], Y4[NI][4][3], A[NI][4][3], XN[NI][3];
+
+    auto load_plane = [&](int P) {
+        bool zok = true;
+        int gz = P;
+        if (pbc)
+            gz = wrap_coord(P, Lz);
+        else
+            zok = P >= 0 && P < Lz;
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+            if (zok && colok[j]) {
+                const int64_t g = (int64_t)col[j] + plane * gz;
+                XN[j][0] = ix[g];
+                XN[j][1] = iy[g];
+                XN[j][2] = iz[g];
+            } else {
+                XN[j][0] = T(0);
+                XN[j][1] = T(0);
+                XN[j][2] = T(0);
+            }
+        }
+    };
+
+    // per-site anisotropy of point j on plane q (zero outside the lattice)
+    auto site_aniso = [&](int j, int q, T& Di, T& ex, T& ey, T& ez) {
+        Di = T(0);
+        ex = ey = ez = T(0);
+        if constexpr (ANIS == ANIS_SITE) {
+            int gz = q;
+            bool zok = true;
+            if (pbc)
+                gz = wrap_coord(q, Lz);
+            else
+                zok = q >= 0 && q < Lz;
+            if (zok && colok[j]) {
+                const int64_t g = (int64_t)col[j] + plane * gz;
+                Di = Dsite[g];
+                ex = esite[g];
+                ey = esite[N + g];
+                ez = esite[2 * N + g];
+            }
+        }
+    };
+
+    const T c6 = T(1) / T(6), c3 = T(1) / T(3), c2 = T(0.5);
+    double kmax = 0.0;
+    T sg = T(0);
+    if constexpr (KICK) sg = (T)(sigma_override >= 0.0 ? sigma_override : R.sigma);
+
+    load_plane(z0 - 4);
+
+    for (int t0 = 0; t0 < niter; t0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u;
+            if (t < niter) {
+                const int P = z0 - 4 + t;
+                constexpr int dummy = 0;
+                (void)dummy;
+                const int u1 = (u + 3) & 3, u2 = (u + 2) & 3, u3 = (u + 1) & 3;  // planes P-1, P-2, P-3
+                // ---- commit x(P), prefetch x(P+1)
+#pragma unroll
+                for (int j = 0; j < NI; ++j)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) X[j][u][c] = XN[j][c];
+                if (t + 1 < niter) load_plane(P + 1);
+                {
+                    const int sl = t & 1;
+#pragma unroll
+                    for (int j = 0; j < NI; ++j) {
+                        if (j * NT + tid < R0) {
+                            sA1[sl][0][o1[j]] = X[j][u][0];
+                            sA1[sl][1][o1[j]] = X[j][u][1];
+                            sA1[sl][2][o1[j]] = X[j][u][2];
+                        }
+                    }
+                }
+                // ---- stage 1 on plane P-1 (region R1)
+                if (t >= 2) {
+                    const int sl = (t - 1) & 1;
+                    const T* Lxp = sA1[sl][0];
+                    const T* Lyp = sA1[sl][1];
+                    const T* Lzp = sA1[sl][2];
+#pragma unroll
+                    for (int j = 0; j < NI; ++j) {
+                        if (j * NT >= R1) continue;
+                        if (j * NT + tid < R1) {
+                            const int o = o1[j];
+                            const T nx = (Lxp[o - 1] + Lxp[o + 1]) + (Lxp[o - W0] + Lxp[o + W0]) +
+                                         (X[j][u2][0] + X[j][u][0]);
+                            const T ny = (Lyp[o - 1] + Lyp[o + 1]) + (Lyp[o - W0] + Lyp[o + W0]) +
+                                         (X[j][u2][1] + X[j][u][1]);
+                            const T nz = (Lzp[o - 1] + Lzp[o + 1]) + (Lzp[o - W0] + Lzp[o + W0]) +
+                                         (X[j][u2][2] + X[j][u][2]);
+                            T Di, ex, ey, ez;
+                            site_aniso(j, P - 1, Di, ex, ey, ez);
+                            T kx, ky, kz;
+                            stage_k<T, PREC, ANIS>(X[j][u1][0], X[j][u1][1], X[j][u1][2], nx, ny, nz,
+                                                   C, Di, ex, ey, ez, kx, ky, kz);
+                            Y2[j][u1][0] = kx * c2 + X[j][u1][0];
+                            Y2[j][u1][1] = ky * c2 + X[j][u1][1];
+                            Y2[j][u1][2] = kz * c2 + X[j][u1][2];
+                            sA2[sl][0][o2[j]] = Y2[j][u1][0];
+                            sA2[sl][1][o2[j]] = Y2[j][u1][1];
+                            sA2[sl][2][o2[j]] = Y2[j][u1][2];
+                            if (j * NT < R4) {
+                                A[j][u1][0] = kx * c6 + X[j][u1][0];
+                                A[j][u1][1] = ky * c6 + X[j][u1][1];
+                                A[j][u1][2] = kz * c6 + X[j][u1][2];
+                            }
+                        }
+                    }
+                }
+                // ---- stage 2 on plane P-2 (region R2)
+                if (t >= 4) {
+                    const int sl = (t - 2) & 1;
+                    const T* Lxp = sA2[sl][0];
+                    const T* Lyp = sA2[sl][1];
+                    const T* Lzp = sA2[sl][2];
+#pragma unroll
+                    for (int j = 0; j < NI; ++j) {
+                        if (j * NT >= R2) continue;
+                        if (j * NT + tid < R2) {
+                            const int o = o2[j];
+                            const T nx = (Lxp[o - 1] + Lxp[o + 1]) + (Lxp[o - W1] + Lxp[o + W1]) +
+                                         (Y2[j][u3][0] + Y2[j][u1][0]);
+                            const T ny = (Lyp[o - 1] + Lyp[o + 1]) + (Lyp[o - W1] + Lyp[o + W1]) +
+                                         (Y2[j][u3][1] + Y2[j][u1][1]);
+                            const T nz = (Lzp[o - 1] + Lzp[o + 1]) + (Lzp[o - W1] + Lzp[o + W1]) +
+                                         (Y2[j][u3][2] + Y2[j][u1][2]);
+                            T Di, ex, ey, ez;
+                            site_aniso(j, P - 2, Di, ex, ey, ez);
+                            T kx, ky, kz;
+                            stage_k<T, PREC, ANIS>(Y2[j][u2][0], Y2[j][u2][1], Y2[j][u2][2], nx, ny,
+                                                   nz, C, Di, ex, ey, ez, kx, ky, kz);
+                            Y3[j][u2][0] = kx * c2 + X[j][u2][0];
+                            Y3[j][u2][1] = ky * c2 + X[j][u2][1];
+                            Y3[j][u2][2] = kz * c2 + X[j][u2][2];
+                            sA3[sl][0][o3[j]] = Y3[j][u2][0];
+                            sA3[sl][1][o3[j]] = Y3[j][u2][1];
+                            sA3[sl][2][o3[j]] = Y3[j][u2][2];
+                            if (j * NT < R4) {
+                                A[j][u2][0] = kx * c3 + A[j][u2][0];
+                                A[j][u2][1] = ky * c3 + A[j][u2][1];
+                                A[j][u2][2] = kz * c3 + A[j][u2][2];
+                            }
+                        }
+                    }
+                }
+                // ---- stage 3 on plane P-3 (region R3)
+                if (t >= 6) {
+                    const int sl = (t - 3) & 1;
+                    const T* Lxp = sA3[sl][0];
+                    const T* Lyp = sA3[sl][1];
+                    const T* Lzp = sA3[sl][2];
+#pragma unroll
+                    for (int j = 0; j < NI; ++j) {
+                        if (j * NT >= R3) continue;
+                        if (j * NT + tid < R3) {
+                            const int o = o3[j];
+                            const T nx = (Lxp[o - 1] + Lxp[o + 1]) + (Lxp[o - W2] + Lxp[o + W2]) +
+                                         (Y3[j][u][0] + Y3[j][u2][0]);
+                            const T ny = (Lyp[o - 1] + Lyp[o + 1]) + (Lyp[o - W2] + Lyp[o + W2]) +
+                                         (Y3[j][u][1] + Y3[j][u2][1]);
+                            const T nz = (Lzp[o - 1] + Lzp[o + 1]) + (Lzp[o - W2] + Lzp[o + W2]) +
+                                         (Y3[j][u][2] + Y3[j][u2][2]);
+                            T Di, ex, ey, ez;
+                            site_aniso(j, P - 3, Di, ex, ey, ez);
+                            T kx, ky, kz;
+                            stage_k<T, PREC, ANIS>(Y3[j][u3][0], Y3[j][u3][1], Y3[j][u3][2], nx, ny,
+                                                   nz, C, Di, ex, ey, ez, kx, ky, kz);
+                            Y4[j][u3][0] = kx + X[j][u3][0];
+                            Y4[j][u3][1] = ky + X[j][u3][1];
+                            Y4[j][u3][2] = kz + X[j][u3][2];
+                            sA4[sl][0][o4[j]] = Y4[j][u3][0];
+                            sA4[sl][1][o4[j]] = Y4[j][u3][1];
+                            sA4[sl][2][o4[j]] = Y4[j][u3][2];
+                            if (j * NT < R4) {
+                                A[j][u3][0] = kx * c3 + A[j][u3][0];
+                                A[j][u3][1] = ky * c3 + A[j][u3][1];
+                                A[j][u3][2] = kz * c3 + A[j][u3][2];
+                            }
+                        }
+                    }
+                }
+                // ---- stage 4 on plane P-4 (core), store
+                if (t >= 8) {
+                    const int sl = (t - 4) & 1;
+                    const T* Lxp = sA4[sl][0];
+                    const T* Lyp = sA4[sl][1];
+                    const T* Lzp = sA4[sl][2];
+                    const int gz = P - 4;
+#pragma unroll
+                    for (int j = 0; j < NI; ++j) {
+                        if (j * NT >= R4) continue;
+                        if (j * NT + tid < R4) {
+                            const int o = o4[j];
+                            const T nx = (Lxp[o - 1] + Lxp[o + 1]) + (Lxp[o - W3] + Lxp[o + W3]) +
+                                         (Y4[j][u1][0] + Y4[j][u3][0]);
+                            const T ny = (Lyp[o - 1] + Lyp[o + 1]) + (Lyp[o - W3] + Lyp[o + W3]) +
+                                         (Y4[j][u1][1] + Y4[j][u3][1]);
+                            const T nz = (Lzp[o - 1] + Lzp[o + 1]) + (Lzp[o - W3] + Lzp[o + W3]) +
+                                         (Y4[j][u1][2] + Y4[j][u3][2]);
+                            T Di, ex, ey, ez;
+                            site_aniso(j, gz, Di, ex, ey, ez);
+                            T kx, ky, kz;
+                            stage_k<T, PREC, ANIS>(Y4[j][u][0], Y4[j][u][1], Y4[j][u][2], nx, ny, nz,
+                                                   C, Di, ex, ey, ez, kx, ky, kz);
+                            T rx = kx * c6 + A[j][u][0];
+                            T ry = ky * c6 + A[j][u][1];
+                            T rz = kz * c6 + A[j][u][2];
+                            if (outok[j]) {
+                                const int64_t g = (int64_t)col[j] + plane * gz;
+                                if constexpr (KICK) {
+                                    const uint4 w =
+                                        philox_site(R.seed, (uint32_t)g, (uint32_t)kpulse, R.rid, 0u);
+                                    const double d = kick_spin<T>(rx, ry, rz, w, sg);
+                                    kmax = (d > kmax || d != d) ? d : kmax;
+                                }
+                                ox[g] = rx;
+                                oy[g] = ry;
+                                oz[g] = rz;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if constexpr (KICK) {
+        // block max of the renormalisation deviation, one integer atomic per block
+        __shared__ double red[NT];
+        red[tid] = kmax;
+        __syncthreads();
+        for (int o = NT / 2; o > 0; o >>= 1) {
+            if (tid < o) {
+                const double a = red[tid], b = red[tid + o];
+                red[tid] = (b > a || b != b) ? b : a;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) atomicMax(kickdev + tl.x, (unsigned long long)__double_as_longlong(red[0]));
+    }
+}
+
+template <typename T, int BX, int BY, int NT, bool PREC, int ANIS>
+inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, State in, State out,
+                           int bz, int kick, uint64_t k, double so, unsigned long long* kd,
+                           hipStream_t st) {
+    if (kick)
+        hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, true>), dim3(ntiles), dim3(NT),
+                           0, st, reps, tiles, in, out, bz, k, so, kd);
+    else
+        hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false>), dim3(ntiles),
+                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd);
+    return hipGetLastError();
+}
+
+template <typename T, int BX, int BY, int NT, bool PREC>
+inline hipError_t launch_a(int anis, const RepDev* reps, const int4* tiles, int ntiles, State in,
+                           State out, int bz, int kick, uint64_t k, double so,
+                           unsigned long long* kd, hipStream_t st) {
+    switch (anis) {
+        case ANIS_NONE: return launch_v<T, BX, BY, NT, PREC, ANIS_NONE>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+        case ANIS_Z: return launch_v<T, BX, BY, NT, PREC, ANIS_Z>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+        case ANIS_AXIS: return launch_v<T, BX, BY, NT, PREC, ANIS_AXIS>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+        default: return hipErrorInvalidValue;  // per-site anisotropy runs on the unfused step
+    }
+}
+
+template <typename T, int BX, int BY, int NT>
+inline hipError_t launch_p(int precession, int anis, const RepDev* reps, const int4* tiles,
+                           int ntiles, State in, State out, int bz, int kick, uint64_t k,
+                           double so, unsigned long long* kd, hipStream_t st) {
+    if (precession)
+        return launch_a<T, BX, BY, NT, true>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+    return launch_a<T, BX, BY, NT, false>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+}
+
+}  // namespace lll

@@ -1,0 +1,964 @@
+// Host runtime and C ABI of liblll: lattice and batch handles, parameter
+// validation, the interval schedule of the pulse-noise method (Eq. (7): n1
+// steps, kick, n2 steps, measurement), graph capture of batched runs, and
+// the autotuner of the RK4 step kernel.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lll.h"
+#include "lll_internal.hpp"
+
+using namespace lll;
+
+// ------------------------------------------------------------- errors -----
+static thread_local std::string g_err;
+
+static lll_status set_err(lll_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return set_err(LLL_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+extern "C" const char* lll_last_error(void) { return g_err.c_str(); }
+extern "C" const char* lll_version(void) { return "lll-mi355x 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------- engine -----
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Engine {
+    int prec = 0;          // 0 fp64, 1 fp32
+    size_t esz = 8;
+    hipStream_t st = nullptr;
+    int nrep = 0;
+    int64_t nsites = 0;
+    std::vector<RepDev> hreps;
+    RepDev* dreps = nullptr;
+    int precession = 1;
+    int anis = ANIS_NONE;
+    State s{};             // current state at API boundaries
+    State alt{};           // second state buffer of the fused ping-pong
+    State yA{}, yB{}, acc{};
+    bool own_s = false;
+    int32_t* d_blk_rep = nullptr;
+    int nblk = 0;
+    int32_t* d_oblk_rep = nullptr;
+    int nobblk = 0;
+    int4* d_tiles = nullptr;
+    int ntiles = 0, tiles_variant = -1, tiles_bz = -1, tiles_cap = 0;
+    double* d_partials = nullptr;
+    double* d_result = nullptr;   // [nrep][8]
+    double* d_accum = nullptr;    // [nrep][8]
+    unsigned long long* d_kickdev = nullptr;  // [nrep]
+    double* d_trace = nullptr;
+    size_t trace_cap = 0;         // doubles
+    int variant = 0, bz = 0;      // step configuration (0 = unfused)
+    int cur = 0;                  // 0: state in s, 1: state in alt
+
+    ~Engine() { release(); }
+
+    void release() {
+        auto fr = [](void* p) {
+            if (p) (void)hipFree(p);
+        };
+        if (own_s) {
+            fr(s.x); fr(s.y); fr(s.z);
+        }
+        fr(alt.x); fr(alt.y); fr(alt.z);
+        fr(yA.x); fr(yA.y); fr(yA.z);
+        fr(yB.x); fr(yB.y); fr(yB.z);
+        fr(acc.x); fr(acc.y); fr(acc.z);
+        fr(dreps); fr(d_blk_rep); fr(d_oblk_rep); fr(d_tiles); fr(d_partials); fr(d_result);
+        fr(d_accum); fr(d_kickdev); fr(d_trace);
+        s = alt = yA = yB = acc = State{};
+        dreps = nullptr; d_blk_rep = d_oblk_rep = nullptr; d_tiles = nullptr;
+        d_partials = d_result = d_accum = d_trace = nullptr; d_kickdev = nullptr;
+    }
+};
+
+lll_status alloc_state(Engine& E, State& S) {
+    if (S.x) return LLL_OK;
+    size_t bytes = (size_t)E.nsites * E.esz;
+    void* p[3] = {nullptr, nullptr, nullptr};
+    for (int c = 0; c < 3; ++c) {
+        if (hipMalloc(&p[c], bytes) != hipSuccess) {
+            for (int d = 0; d < c; ++d) (void)hipFree(p[d]);
+            return set_err(LLL_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+        }
+    }
+    S.x = p[0]; S.y = p[1]; S.z = p[2];
+    return LLL_OK;
+}
+
+// Geometry-dependent tables: per-site blocks and observables blocks.
+lll_status build_tables(Engine& E) {
+    std::vector<int32_t> blk, oblk;
+    int64_t off = 0;
+    for (int r = 0; r < E.nrep; ++r) {
+        RepDev& R = E.hreps[r];
+        const int64_t N = (int64_t)R.Lx * R.Ly * R.Lz;
+        R.off = off;
+        off += N;
+        R.sb0 = (int32_t)blk.size();
+        R.nsb = (int32_t)((N + 255) / 256);
+        for (int b = 0; b < R.nsb; ++b) blk.push_back(r);
+        R.ob0 = (int32_t)oblk.size();
+        R.nob = (int32_t)std::min<int64_t>(std::max<int64_t>((N + 1023) / 1024, 1), 2048);
+        for (int b = 0; b < R.nob; ++b) oblk.push_back(r);
+    }
+    E.nsites = off;
+    E.nblk = (int)blk.size();
+    E.nobblk = (int)oblk.size();
+    HIP_TRY(hipMalloc(&E.d_blk_rep, sizeof(int32_t) * blk.size()));
+    HIP_TRY(hipMemcpy(E.d_blk_rep, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&E.d_oblk_rep, sizeof(int32_t) * oblk.size()));
+    HIP_TRY(hipMemcpy(E.d_oblk_rep, oblk.data(), sizeof(int32_t) * oblk.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&E.d_partials, sizeof(double) * 8 * oblk.size()));
+    HIP_TRY(hipMalloc(&E.d_result, sizeof(double) * 8 * E.nrep));
+    HIP_TRY(hipMalloc(&E.d_accum, sizeof(double) * 8 * E.nrep));
+    HIP_TRY(hipMemset(E.d_accum, 0, sizeof(double) * 8 * E.nrep));
+    HIP_TRY(hipMalloc(&E.d_kickdev, sizeof(unsigned long long) * E.nrep));
+    HIP_TRY(hipMemset(E.d_kickdev, 0, sizeof(unsigned long long) * E.nrep));
+    HIP_TRY(hipMalloc(&E.dreps, sizeof(RepDev) * E.nrep));
+    return LLL_OK;
+}
+
+lll_status upload_reps(Engine& E) {
+    HIP_TRY(hipStreamSynchronize(E.st));
+    HIP_TRY(hipMemcpy(E.dreps, E.hreps.data(), sizeof(RepDev) * E.nrep, hipMemcpyHostToDevice));
+    return LLL_OK;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+struct Phys {
+    double J, H[3], D, e[3], lambda, T;
+    const void* D_site;
+    const void* e_site;
+};
+
+// Stage coefficients and physics of one replica (see RepDev).
+void fill_physics(RepDev& R, const Phys& p, double dt, double Dt, int precession, uint64_t seed,
+                  uint32_t rid) {
+    double en = sqrt(p.e[0] * p.e[0] + p.e[1] * p.e[1] + p.e[2] * p.e[2]);
+    double e[3] = {0, 0, 1};
+    if (en > 0) {
+        e[0] = p.e[0] / en; e[1] = p.e[1] / en; e[2] = p.e[2] / en;
+    }
+    const double f = precession ? dt : -p.lambda * dt;
+    R.cJ = f * p.J;
+    for (int c = 0; c < 3; ++c) {
+        R.cH[c] = f * p.H[c];
+        R.e[c] = e[c];
+        R.H[c] = p.H[c];
+    }
+    R.cD = p.D_site ? 2.0 * f : 2.0 * p.D * f;
+    R.lam = precession ? p.lambda : 0.0;
+    R.J = p.J;
+    R.D = p.D;
+    R.pad2 = 0;
+    R.lambda = p.lambda;
+    R.Dt = Dt;
+    R.sigma = sqrt(2.0 * p.lambda * p.T * Dt);
+    R.seed = seed;
+    R.rid = rid;
+    R.D_site = p.D_site;
+    R.e_site = p.e_site;
+}
+
+int anis_mode_of(const Phys& p) {
+    if (p.D_site) return ANIS_SITE;
+    if (p.D == 0.0) return ANIS_NONE;
+    double en = sqrt(p.e[0] * p.e[0] + p.e[1] * p.e[1] + p.e[2] * p.e[2]);
+    if (en == 0.0 || (p.e[0] == 0.0 && p.e[1] == 0.0)) return ANIS_Z;
+    return ANIS_AXIS;
+}
+
+lll_status steps_per_interval(double dt, double Dt, int64_t* n) {
+    if (!(dt > 0) || !(Dt > 0) || !is_fin(dt) || !is_fin(Dt))
+        return set_err(LLL_EINVAL, "dt and Dt must be positive and finite");
+    double q = Dt / dt;
+    double r = floor(q + 0.5);
+    if (r < 1 || fabs(q - r) > 1e-9 * r)
+        return set_err(LLL_EINVAL, "Dt/dt = %.17g is not a positive integer", q);
+    *n = (int64_t)r;
+    return LLL_OK;
+}
+
+lll_status check_phys(const Phys& p) {
+    const double v[] = {p.J, p.H[0], p.H[1], p.H[2], p.D, p.e[0], p.e[1], p.e[2], p.lambda, p.T};
+    for (double x : v)
+        if (!is_fin(x)) return set_err(LLL_EINVAL, "non-finite parameter");
+    if (p.lambda < 0) return set_err(LLL_EINVAL, "lambda must be >= 0");
+    if (p.T < 0) return set_err(LLL_EINVAL, "T must be >= 0");
+    if (p.e_site && !p.D_site) return set_err(LLL_EINVAL, "e_site needs D_site");
+    return LLL_OK;
+}
+
+// Eq. (8): sqrt(Lambda_N Dt) small; Eq. (9): lambda h Dt small; step-size rule
+// of Sec. II: h dt about 0.2-0.25 at most with precession.
+bool applicability_warning(const Phys& p, double dt, double Dt, int precession, double Tmax) {
+    const double hmax = 6 * fabs(p.J) +
+                        sqrt(p.H[0] * p.H[0] + p.H[1] * p.H[1] + p.H[2] * p.H[2]) +
+                        2 * fabs(p.D);
+    if (2 * p.lambda * Tmax * Dt > 0.2) return true;
+    if (p.lambda * hmax * Dt > 0.2) return true;
+    if (precession && hmax * dt > 0.25) return true;
+    return false;
+}
+
+// ----------------------------------------------------- step machinery -----
+lll_status ensure_unfused_scratch(Engine& E) {
+    lll_status s;
+    if ((s = alloc_state(E, E.yA)) != LLL_OK) return s;
+    if ((s = alloc_state(E, E.yB)) != LLL_OK) return s;
+    if ((s = alloc_state(E, E.acc)) != LLL_OK) return s;
+    return LLL_OK;
+}
+
+// Tile list of the fused kernel: (replica, tile x, tile y, tile z) per
+// workgroup, ordered so that the eight XCDs (workgroups are dealt out to them
+// round-robin) each receive a contiguous z-major range of tiles, keeping halo
+// re-reads inside one XCD's L2.
+lll_status ensure_tiles(Engine& E) {
+    if (E.tiles_variant == E.variant && E.tiles_bz == E.bz && E.d_tiles) return LLL_OK;
+    FusedInfo fi;
+    if (!fused_variant_info(E.prec, E.variant, &fi))
+        return set_err(LLL_EINVAL, "invalid step variant %d", E.variant);
+    std::vector<int4> list;
+    for (int r = 0; r < E.nrep; ++r) {
+        RepDev& R = E.hreps[r];
+        int bzr = E.bz > 0 ? E.bz : 16;
+        if (bzr > R.Lz) bzr = R.Lz;
+        R.tx = (R.Lx + fi.bx - 1) / fi.bx;
+        R.ty = (R.Ly + fi.by - 1) / fi.by;
+        R.tz = (R.Lz + bzr - 1) / bzr;
+        R.tile0 = (int32_t)list.size();
+        for (int tz = 0; tz < R.tz; ++tz)
+            for (int ty = 0; ty < R.ty; ++ty)
+                for (int tx = 0; tx < R.tx; ++tx) list.push_back(make_int4(r, tx, ty, tz));
+    }
+    // XCD-aware order: workgroup w runs on XCD w % 8.
+    const int n = (int)list.size();
+    std::vector<int4> ord(n);
+    const int per = (n + 7) / 8;
+    int w = 0;
+    std::vector<int> slot_of(n);
+    {
+        // position p of the contiguous list goes to workgroup id
+        // (p % per) * 8 + p / per when that id exists; fall back to identity otherwise
+        std::vector<int> taken(n, 0);
+        bool ok = true;
+        for (int p = 0; p < n; ++p) {
+            int id = (p % per) * 8 + p / per;
+            if (id >= n || taken[id]) { ok = false; break; }
+            taken[id] = 1;
+            slot_of[p] = id;
+        }
+        if (!ok)
+            for (int p = 0; p < n; ++p) slot_of[p] = p;
+    }
+    for (int p = 0; p < n; ++p) ord[slot_of[p]] = list[p];
+    (void)w;
+    if (n > E.tiles_cap) {
+        if (E.d_tiles) (void)hipFree(E.d_tiles);
+        E.d_tiles = nullptr;
+        HIP_TRY(hipMalloc(&E.d_tiles, sizeof(int4) * n));
+        E.tiles_cap = n;
+    }
+    HIP_TRY(hipStreamSynchronize(E.st));
+    HIP_TRY(hipMemcpy(E.d_tiles, ord.data(), sizeof(int4) * n, hipMemcpyHostToDevice));
+    E.ntiles = n;
+    E.tiles_variant = E.variant;
+    E.tiles_bz = E.bz;
+    lll_status st = upload_reps(E);
+    return st;
+}
+
+State cur_state(Engine& E) { return E.cur ? E.alt : E.s; }
+
+// n RK4 steps; when kick_last, kick k is applied right after the last step
+// (as the fused kernel's epilogue, or as a separate launch).
+lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sigma_override) {
+    if (n <= 0) return LLL_OK;
+    if (E.variant == 0 || E.anis == ANIS_SITE) {
+        lll_status s = ensure_unfused_scratch(E);
+        if (s != LLL_OK) return s;
+        for (int64_t q = 0; q < n; ++q)
+            HIP_TRY(launch_step_unfused(E.prec, E.precession, E.anis, E.dreps, E.d_blk_rep, E.nblk,
+                                        cur_state(E), E.yA, E.yB, E.acc, E.st));
+        if (kick_last)
+            HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k,
+                                sigma_override, E.d_kickdev, E.st));
+        return LLL_OK;
+    }
+    lll_status s = alloc_state(E, E.alt);
+    if (s != LLL_OK) return s;
+    if ((s = ensure_tiles(E)) != LLL_OK) return s;
+    for (int64_t q = 0; q < n; ++q) {
+        const bool kk = kick_last && q == n - 1;
+        State in = cur_state(E);
+        State out = E.cur ? E.s : E.alt;
+        HIP_TRY(launch_step_fused(E.prec, E.precession, E.anis, E.variant, E.bz, E.dreps, E.d_tiles,
+                                  E.ntiles, in, out, kk ? 1 : 0, k, sigma_override, E.d_kickdev,
+                                  E.st));
+        E.cur ^= 1;
+    }
+    return LLL_OK;
+}
+
+lll_status do_kick(Engine& E, uint64_t k, double sigma_override) {
+    HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k, sigma_override,
+                        E.d_kickdev, E.st));
+    return LLL_OK;
+}
+
+lll_status settle(Engine& E) {
+    if (E.cur) {
+        HIP_TRY(launch_copy(E.prec, E.s, E.alt, E.nsites, E.st));
+        E.cur = 0;
+    }
+    return LLL_OK;
+}
+
+// One interval of Eq. (7): n1 steps, kick, n2 steps.
+lll_status do_interval(Engine& E, int64_t n, uint64_t k, double sigma_override) {
+    const int64_t n1 = n / 2, n2 = n - n1;
+    lll_status s;
+    if (n1 > 0) {
+        if ((s = do_steps(E, n1, true, k, sigma_override)) != LLL_OK) return s;
+    } else {
+        if ((s = do_kick(E, k, sigma_override)) != LLL_OK) return s;
+    }
+    return do_steps(E, n2, false, 0, -1.0);
+}
+
+lll_status do_obs(Engine& E, double* result, int accumulate) {
+    HIP_TRY(launch_obs(E.prec, E.anis, E.dreps, E.d_oblk_rep, E.nobblk, E.nrep, cur_state(E),
+                       E.d_partials, result, E.d_accum, accumulate, E.st));
+    return LLL_OK;
+}
+
+lll_status ensure_trace(Engine& E, size_t doubles) {
+    if (doubles <= E.trace_cap) return LLL_OK;
+    if (E.d_trace) (void)hipFree(E.d_trace);
+    E.d_trace = nullptr;
+    E.trace_cap = 0;
+    HIP_TRY(hipMalloc(&E.d_trace, sizeof(double) * doubles));
+    E.trace_cap = doubles;
+    return LLL_OK;
+}
+
+void obs_from(const double* r, lll_obs* o) {
+    o->E_total = r[0];
+    o->E_exch = r[1];
+    o->E_zeeman = r[2];
+    o->E_anis = r[3];
+    o->m[0] = r[4];
+    o->m[1] = r[5];
+    o->m[2] = r[6];
+    o->max_norm_dev = r[7];
+}
+
+bool obs_finite(const double* r) {
+    for (int j = 0; j < 8; ++j)
+        if (!std::isfinite(r[j])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- lattice ----
+struct lll_lattice {
+    Engine E;
+    int32_t Lx, Ly, Lz, bc;
+    bool have_params = false;
+    Phys phys{};
+    double dt = 0, Dt = 0;
+    int precession = 1;
+    uint64_t seed = 0;
+};
+
+static lll_status lattice_params(lll_lattice* L, const lll_params* p, bool need_schedule) {
+    if (!p) return set_err(LLL_EINVAL, "params is NULL");
+    Phys ph{};
+    ph.J = p->J;
+    for (int c = 0; c < 3; ++c) {
+        ph.H[c] = p->H[c];
+        ph.e[c] = p->e[c];
+    }
+    ph.D = p->D;
+    ph.lambda = p->lambda;
+    ph.T = p->T;
+    ph.D_site = p->D_site;
+    ph.e_site = p->e_site;
+    lll_status s = check_phys(ph);
+    if (s != LLL_OK) return s;
+    if (p->integrator != LLL_RK4) return set_err(LLL_EUNSUPPORTED, "only LLL_RK4 is implemented");
+    if (!(p->dt > 0) || !is_fin(p->dt)) return set_err(LLL_EINVAL, "dt must be positive");
+    double Dt = p->Dt;
+    if (need_schedule) {
+        int64_t n;
+        if ((s = steps_per_interval(p->dt, p->Dt, &n)) != LLL_OK) return s;
+    } else if (!(Dt > 0) || !is_fin(Dt)) {
+        Dt = p->dt;
+    }
+    if (p->D_site && !p->e_site) return set_err(LLL_EINVAL, "D_site needs e_site");
+    const int prec = p->precession ? 1 : 0;
+    const bool same = L->have_params && memcmp(&ph, &L->phys, sizeof ph) == 0 && L->dt == p->dt &&
+                      L->Dt == Dt && L->precession == prec && L->seed == p->seed;
+    if (same) return LLL_OK;
+    Engine& E = L->E;
+    RepDev& R = E.hreps[0];
+    fill_physics(R, ph, p->dt, Dt, prec, p->seed, 0u);
+    E.precession = prec;
+    E.anis = anis_mode_of(ph);
+    if ((s = upload_reps(E)) != LLL_OK) return s;
+    L->phys = ph;
+    L->dt = p->dt;
+    L->Dt = Dt;
+    L->precession = prec;
+    L->seed = p->seed;
+    L->have_params = true;
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_init_lattice(int32_t Lx, int32_t Ly, int32_t Lz, lll_bc bc,
+                                       lll_precision prec, lll_init mode, const double dir[3],
+                                       uint64_t seed, void* sx, void* sy, void* sz,
+                                       void* hip_stream, lll_lattice** out) {
+    if (!out) return set_err(LLL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (Lx < 1 || Ly < 1 || Lz < 1) return set_err(LLL_EINVAL, "lattice sizes must be >= 1");
+    const int64_t N = (int64_t)Lx * Ly * Lz;
+    if (N > 0x7FFFFFFFLL) return set_err(LLL_EINVAL, "at most 2^31-1 sites");
+    if (bc != LLL_BC_PERIODIC && bc != LLL_BC_FREE) return set_err(LLL_EINVAL, "bad boundary");
+    if (prec != LLL_FP64 && prec != LLL_FP32) return set_err(LLL_EINVAL, "bad precision");
+    if (mode != LLL_INIT_RANDOM_SPHERE && mode != LLL_INIT_DIRECTION && mode != LLL_INIT_KEEP)
+        return set_err(LLL_EINVAL, "bad init mode");
+    const int nbuf = (sx != nullptr) + (sy != nullptr) + (sz != nullptr);
+    if (nbuf != 0 && nbuf != 3) return set_err(LLL_EINVAL, "pass all three buffers or none");
+    if (mode == LLL_INIT_KEEP && nbuf == 0)
+        return set_err(LLL_EINVAL, "LLL_INIT_KEEP needs caller buffers");
+    double d[3] = {0, 0, 1};
+    if (mode == LLL_INIT_DIRECTION) {
+        if (!dir) return set_err(LLL_EINVAL, "dir is NULL");
+        double n = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+        if (!(n > 0) || !is_fin(n)) return set_err(LLL_EINVAL, "dir must be a non-zero vector");
+        d[0] = dir[0] / n; d[1] = dir[1] / n; d[2] = dir[2] / n;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_err(LLL_EDEVICE, "no HIP device");
+    lll_lattice* L = new lll_lattice();
+    L->Lx = Lx; L->Ly = Ly; L->Lz = Lz; L->bc = bc;
+    Engine& E = L->E;
+    E.prec = prec == LLL_FP64 ? 0 : 1;
+    E.esz = E.prec == 0 ? 8 : 4;
+    E.st = (hipStream_t)hip_stream;
+    E.nrep = 1;
+    E.hreps.assign(1, RepDev{});
+    RepDev& R = E.hreps[0];
+    memset(&R, 0, sizeof R);
+    R.Lx = Lx; R.Ly = Ly; R.Lz = Lz; R.bc = bc;
+    R.seed = seed;
+    R.init = mode == LLL_INIT_RANDOM_SPHERE ? 0 : 1;
+    lll_status s = build_tables(E);
+    if (s != LLL_OK) { delete L; return s; }
+    if (nbuf == 3) {
+        E.s.x = sx; E.s.y = sy; E.s.z = sz;
+        E.own_s = false;
+    } else {
+        E.own_s = true;
+        if ((s = alloc_state(E, E.s)) != LLL_OK) { delete L; return s; }
+    }
+    if ((s = upload_reps(E)) != LLL_OK) { delete L; return s; }
+    if (mode != LLL_INIT_KEEP) {
+        hipError_t e = launch_init(E.prec, E.dreps, E.d_blk_rep, E.nblk, E.s, mode, d[0], d[1], d[2], E.st);
+        if (e != hipSuccess) {
+            delete L;
+            return set_err(LLL_EDEVICE, "init launch failed: %s", hipGetErrorString(e));
+        }
+    }
+    // default step configuration: fused when the lattice is large enough
+    E.variant = 0;
+    E.bz = 0;
+    if (fused_variant_count(E.prec) > 0 && N >= 4096) E.variant = 1;
+    *out = L;
+    return LLL_OK;
+}
+
+extern "C" void lll_destroy(lll_lattice* L) {
+    if (!L) return;
+    if (L->E.st) (void)hipStreamSynchronize(L->E.st);
+    else (void)hipDeviceSynchronize();
+    delete L;
+}
+
+extern "C" lll_status lll_step_conservative(lll_lattice* L, const lll_params* p, int64_t n_steps) {
+    if (!L) return set_err(LLL_EINVAL, "lattice is NULL");
+    if (n_steps < 0) return set_err(LLL_EINVAL, "n_steps < 0");
+    lll_status s = lattice_params(L, p, false);
+    if (s != LLL_OK) return s;
+    if ((s = do_steps(L->E, n_steps, false, 0, -1.0)) != LLL_OK) return s;
+    return settle(L->E);
+}
+
+extern "C" lll_status lll_noise_pulse(lll_lattice* L, const lll_params* p, uint64_t pulse_index) {
+    if (!L) return set_err(LLL_EINVAL, "lattice is NULL");
+    lll_status s = lattice_params(L, p, true);
+    if (s != LLL_OK) return s;
+    if ((s = settle(L->E)) != LLL_OK) return s;
+    return do_kick(L->E, pulse_index, -1.0);
+}
+
+extern "C" lll_status lll_observables(lll_lattice* L, const lll_params* p, lll_obs* out) {
+    if (!L || !out) return set_err(LLL_EINVAL, "NULL argument");
+    lll_status s = lattice_params(L, p, false);
+    if (s != LLL_OK) return s;
+    Engine& E = L->E;
+    if ((s = settle(E)) != LLL_OK) return s;
+    if ((s = do_obs(E, E.d_result, 0)) != LLL_OK) return s;
+    double r[8];
+    HIP_TRY(hipMemcpyAsync(r, E.d_result, sizeof r, hipMemcpyDeviceToHost, E.st));
+    HIP_TRY(hipStreamSynchronize(E.st));
+    obs_from(r, out);
+    if (!obs_finite(r)) return set_err(LLL_ENONFINITE, "state contains NaN or Inf");
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_run(lll_lattice* L, const lll_params* p, uint64_t first_pulse,
+                              int64_t n_pulses, const double* T_per_pulse, int32_t obs_every,
+                              lll_obs* trace) {
+    if (!L) return set_err(LLL_EINVAL, "lattice is NULL");
+    if (n_pulses < 0) return set_err(LLL_EINVAL, "n_pulses < 0");
+    if (obs_every < 0) return set_err(LLL_EINVAL, "obs_every < 0");
+    lll_status s = lattice_params(L, p, true);
+    if (s != LLL_OK) return s;
+    Engine& E = L->E;
+    int64_t n;
+    if ((s = steps_per_interval(p->dt, p->Dt, &n)) != LLL_OK) return s;
+    double Tmax = p->T;
+    if (T_per_pulse) {
+        Tmax = 0;
+        for (int64_t q = 0; q < n_pulses; ++q) {
+            if (!(T_per_pulse[q] >= 0) || !is_fin(T_per_pulse[q]))
+                return set_err(LLL_EINVAL, "T_per_pulse[%lld] invalid", (long long)q);
+            Tmax = std::max(Tmax, T_per_pulse[q]);
+        }
+    }
+    const int64_t nmeas = obs_every > 0 ? n_pulses / obs_every : 0;
+    const bool want_trace = trace && nmeas > 0;
+    if (want_trace && (s = ensure_trace(E, (size_t)nmeas * 8)) != LLL_OK) return s;
+    if ((s = settle(E)) != LLL_OK) return s;
+    int64_t m = 0;
+    for (int64_t q = 0; q < n_pulses; ++q) {
+        const uint64_t k = first_pulse + (uint64_t)q;
+        const double so = T_per_pulse ? sqrt(2.0 * p->lambda * T_per_pulse[q] * L->Dt) : -1.0;
+        if ((s = do_interval(E, n, k, so)) != LLL_OK) return s;
+        if (obs_every > 0 && (q + 1) % obs_every == 0) {
+            double* dst = want_trace ? E.d_trace + 8 * m : E.d_result;
+            if ((s = do_obs(E, dst, 1)) != LLL_OK) return s;
+            ++m;
+        }
+    }
+    if ((s = settle(E)) != LLL_OK) return s;
+    if (want_trace) {
+        std::vector<double> h((size_t)nmeas * 8);
+        HIP_TRY(hipMemcpyAsync(h.data(), E.d_trace, sizeof(double) * h.size(),
+                               hipMemcpyDeviceToHost, E.st));
+        HIP_TRY(hipStreamSynchronize(E.st));
+        bool fin = true;
+        for (int64_t j = 0; j < nmeas; ++j) {
+            obs_from(&h[8 * j], &trace[j]);
+            fin = fin && obs_finite(&h[8 * j]);
+        }
+        if (!fin) return set_err(LLL_ENONFINITE, "state became NaN or Inf during the run");
+    }
+    if (applicability_warning(L->phys, p->dt, p->Dt, L->precession, Tmax))
+        return set_err(LLL_WARN_APPLICABILITY,
+                       "applicability: 2 lambda T Dt, lambda h Dt or h dt exceeds its bound");
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_get_state(lll_lattice* L, void** sx, void** sy, void** sz) {
+    if (!L || !sx || !sy || !sz) return set_err(LLL_EINVAL, "NULL argument");
+    *sx = L->E.s.x;
+    *sy = L->E.s.y;
+    *sz = L->E.s.z;
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_kick_norm_dev(lll_lattice* L, double* out, int32_t reset) {
+    if (!L || !out) return set_err(LLL_EINVAL, "NULL argument");
+    unsigned long long v = 0;
+    HIP_TRY(hipMemcpyAsync(&v, L->E.d_kickdev, sizeof v, hipMemcpyDeviceToHost, L->E.st));
+    HIP_TRY(hipStreamSynchronize(L->E.st));
+    memcpy(out, &v, sizeof v);
+    if (reset) {
+        HIP_TRY(hipMemsetAsync(L->E.d_kickdev, 0, sizeof v, L->E.st));
+        HIP_TRY(hipStreamSynchronize(L->E.st));
+    }
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_accumulators(lll_lattice* L, double* out, int32_t reset) {
+    if (!L || !out) return set_err(LLL_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(out, L->E.d_accum, sizeof(double) * 8, hipMemcpyDeviceToHost, L->E.st));
+    HIP_TRY(hipStreamSynchronize(L->E.st));
+    if (reset) {
+        HIP_TRY(hipMemsetAsync(L->E.d_accum, 0, sizeof(double) * 8, L->E.st));
+        HIP_TRY(hipStreamSynchronize(L->E.st));
+    }
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_step_variant_info(lll_precision prec, int32_t variant, int32_t* out4) {
+    if (!out4) return set_err(LLL_EINVAL, "NULL argument");
+    const int pr = prec == LLL_FP64 ? 0 : 1;
+    if (variant == 0) {
+        out4[0] = 1; out4[1] = 1; out4[2] = 256; out4[3] = 0;
+        return LLL_OK;
+    }
+    FusedInfo fi;
+    if (!fused_variant_info(pr, variant, &fi)) return set_err(LLL_EINVAL, "no such variant");
+    out4[0] = fi.bx; out4[1] = fi.by; out4[2] = fi.threads; out4[3] = fi.lds_bytes;
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_set_step_config(lll_lattice* L, int32_t variant, int32_t bz) {
+    if (!L) return set_err(LLL_EINVAL, "lattice is NULL");
+    if (variant < 0 || variant > fused_variant_count(L->E.prec))
+        return set_err(LLL_EINVAL, "variant %d out of range", variant);
+    if (bz < 0) return set_err(LLL_EINVAL, "bz < 0");
+    lll_status s = settle(L->E);
+    if (s != LLL_OK) return s;
+    L->E.variant = variant;
+    L->E.bz = bz;
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_get_step_config(lll_lattice* L, int32_t* variant, int32_t* bz) {
+    if (!L) return set_err(LLL_EINVAL, "lattice is NULL");
+    if (variant) *variant = L->E.variant;
+    if (bz) *bz = L->E.bz;
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_philox4x32_10(uint64_t seed, uint32_t i0, int64_t n, uint32_t c1,
+                                        uint32_t c2, uint32_t c3, uint32_t* out_dev,
+                                        void* hip_stream) {
+    if (n < 0) return set_err(LLL_EINVAL, "n < 0");
+    if (n > 0 && !out_dev) return set_err(LLL_EINVAL, "out_dev is NULL");
+    HIP_TRY(launch_philox_words(seed, i0, n, c1, c2, c3, out_dev, (hipStream_t)hip_stream));
+    return LLL_OK;
+}
+
+// ------------------------------------------------------------- autotune ---
+static std::string tune_key(const lll_lattice* L) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "L%dx%dx%d_bc%d_%s_prec%d_anis%d", L->Lx, L->Ly, L->Lz, L->bc,
+             L->E.prec == 0 ? "fp64" : "fp32", L->E.precession, L->E.anis);
+    return buf;
+}
+
+extern "C" lll_status lll_autotune(lll_lattice* L, const lll_params* p, const char* cache_path,
+                                   int32_t* chosen_variant, int32_t* chosen_bz) {
+    if (!L) return set_err(LLL_EINVAL, "lattice is NULL");
+    lll_status s = lattice_params(L, p, false);
+    if (s != LLL_OK) return s;
+    Engine& E = L->E;
+    const std::string key = tune_key(L);
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "r");
+        if (f) {
+            char k[160];
+            int v, b;
+            bool found = false;
+            while (fscanf(f, "%159s %d %d", k, &v, &b) == 3) {
+                if (key == k && v >= 0 && v <= fused_variant_count(E.prec) && b >= 0) {
+                    E.variant = v;
+                    E.bz = b;
+                    found = true;
+                }
+            }
+            fclose(f);
+            if (found) {
+                if (chosen_variant) *chosen_variant = E.variant;
+                if (chosen_bz) *chosen_bz = E.bz;
+                return LLL_OK;
+            }
+        }
+    }
+    if ((s = settle(E)) != LLL_OK) return s;
+    // save the state
+    State save{};
+    if ((s = alloc_state(E, save)) != LLL_OK) return s;
+    HIP_TRY(launch_copy(E.prec, save, E.s, E.nsites, E.st));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    std::vector<std::pair<int, int>> cands;
+    cands.push_back({0, 0});
+    const int Lz = L->Lz;
+    for (int v = 1; v <= fused_variant_count(E.prec); ++v) {
+        const int bzs[] = {4, 8, 12, 16, 24, 32, 48, 64};
+        for (int b : bzs)
+            if (b <= std::max(Lz, 4)) cands.push_back({v, b});
+    }
+    double best = 1e30;
+    int bv = E.variant, bb = E.bz;
+    const int reps = 6;
+    for (auto& c : cands) {
+        E.variant = c.first;
+        E.bz = c.second;
+        if ((s = do_steps(E, 2, false, 0, -1.0)) != LLL_OK) break;  // warm-up
+        if ((s = settle(E)) != LLL_OK) break;
+        HIP_TRY(hipEventRecord(e0, E.st));
+        if ((s = do_steps(E, reps, false, 0, -1.0)) != LLL_OK) break;
+        HIP_TRY(hipEventRecord(e1, E.st));
+        if ((s = settle(E)) != LLL_OK) break;
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            bv = c.first;
+            bb = c.second;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    E.variant = bv;
+    E.bz = bb;
+    hipError_t ce = launch_copy(E.prec, E.s, save, E.nsites, E.st);
+    (void)hipStreamSynchronize(E.st);
+    (void)hipFree(save.x); (void)hipFree(save.y); (void)hipFree(save.z);
+    if (s != LLL_OK) return s;
+    if (ce != hipSuccess) return set_err(LLL_EDEVICE, "restore failed");
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d\n", key.c_str(), bv, bb);
+            fclose(f);
+        }
+    }
+    if (chosen_variant) *chosen_variant = bv;
+    if (chosen_bz) *chosen_bz = bb;
+    return LLL_OK;
+}
+
+// --------------------------------------------------------------- batch -----
+struct lll_batch {
+    Engine E;
+    double dt = 0, Dt = 0;
+    int64_t n = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    uint64_t g_first = 0;
+    int64_t g_npulses = -1;
+    int32_t g_obs_every = -1;
+    ~lll_batch() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+extern "C" lll_status lll_batch_create(int32_t n_rep, const lll_replica_desc* reps,
+                                       lll_precision prec, double dt, double Dt,
+                                       int32_t precession, void* hip_stream, lll_batch** out) {
+    if (!out) return set_err(LLL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_rep < 1 || !reps) return set_err(LLL_EINVAL, "need at least one replica");
+    if (prec != LLL_FP64 && prec != LLL_FP32) return set_err(LLL_EINVAL, "bad precision");
+    int64_t n;
+    lll_status s = steps_per_interval(dt, Dt, &n);
+    if (s != LLL_OK) return s;
+    lll_batch* B = new lll_batch();
+    Engine& E = B->E;
+    E.prec = prec == LLL_FP64 ? 0 : 1;
+    E.esz = E.prec == 0 ? 8 : 4;
+    E.st = (hipStream_t)hip_stream;
+    E.nrep = n_rep;
+    E.hreps.assign(n_rep, RepDev{});
+    E.precession = precession ? 1 : 0;
+    int anis = ANIS_NONE;
+    int64_t total = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        const lll_replica_desc& d = reps[r];
+        if (d.Lx < 1 || d.Ly < 1 || d.Lz < 1) { delete B; return set_err(LLL_EINVAL, "replica %d: bad size", r); }
+        if (d.bc != LLL_BC_PERIODIC && d.bc != LLL_BC_FREE) { delete B; return set_err(LLL_EINVAL, "replica %d: bad bc", r); }
+        total += (int64_t)d.Lx * d.Ly * d.Lz;
+        Phys ph{};
+        ph.J = d.J;
+        for (int c = 0; c < 3; ++c) { ph.H[c] = d.H[c]; ph.e[c] = d.e[c]; }
+        ph.D = d.D;
+        ph.lambda = d.lambda;
+        ph.T = d.T;
+        if ((s = check_phys(ph)) != LLL_OK) { delete B; return s; }
+        RepDev& R = E.hreps[r];
+        memset(&R, 0, sizeof R);
+        R.Lx = d.Lx; R.Ly = d.Ly; R.Lz = d.Lz; R.bc = d.bc;
+        R.init = d.init == LLL_INIT_DIRECTION ? 1 : 0;
+        fill_physics(R, ph, dt, Dt, E.precession, d.seed, d.replica);
+        const int a = anis_mode_of(ph);
+        if (a == ANIS_AXIS || (a == ANIS_Z && anis == ANIS_NONE)) anis = std::max(anis, a);
+    }
+    if (total > 0x7FFFFFFFLL) { delete B; return set_err(LLL_EINVAL, "too many sites in the batch"); }
+    E.anis = anis;
+    B->dt = dt;
+    B->Dt = Dt;
+    B->n = n;
+    if ((s = build_tables(E)) != LLL_OK) { delete B; return s; }
+    E.own_s = true;
+    if ((s = alloc_state(E, E.s)) != LLL_OK) { delete B; return s; }
+    if ((s = upload_reps(E)) != LLL_OK) { delete B; return s; }
+    hipError_t e = launch_init(E.prec, E.dreps, E.d_blk_rep, E.nblk, E.s, 0, 0.0, 0.0, 1.0, E.st);
+    if (e != hipSuccess) { delete B; return set_err(LLL_EDEVICE, "init failed"); }
+    E.variant = fused_variant_count(E.prec) > 0 ? 1 : 0;
+    E.bz = 0;
+    *out = B;
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t n_pulses,
+                                    int32_t obs_every, lll_obs* trace) {
+    if (!B) return set_err(LLL_EINVAL, "batch is NULL");
+    if (n_pulses < 0 || obs_every < 0) return set_err(LLL_EINVAL, "bad counts");
+    Engine& E = B->E;
+    const int64_t nmeas = obs_every > 0 ? n_pulses / obs_every : 0;
+    lll_status s;
+    if (nmeas > 0 && (s = ensure_trace(E, (size_t)nmeas * 8 * E.nrep)) != LLL_OK) return s;
+    if ((s = settle(E)) != LLL_OK) return s;
+    // Tables must exist before capture (their uploads synchronise).
+    if (E.variant == 0 || E.anis == ANIS_SITE) {
+        if ((s = ensure_unfused_scratch(E)) != LLL_OK) return s;
+    } else {
+        if ((s = alloc_state(E, E.alt)) != LLL_OK) return s;
+        if ((s = ensure_tiles(E)) != LLL_OK) return s;
+    }
+    const bool reuse = B->gexec && B->g_first == first_pulse && B->g_npulses == n_pulses &&
+                       B->g_obs_every == obs_every;
+    if (!reuse) {
+        if (B->gexec) { (void)hipGraphExecDestroy(B->gexec); B->gexec = nullptr; }
+        if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
+        hipStream_t cs = E.st;
+        bool made_stream = false;
+        if (!cs) {
+            HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            made_stream = true;
+        }
+        hipStream_t saved = E.st;
+        E.st = cs;
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        int64_t m = 0;
+        lll_status cap = LLL_OK;
+        for (int64_t q = 0; q < n_pulses && cap == LLL_OK; ++q) {
+            cap = do_interval(E, B->n, first_pulse + (uint64_t)q, -1.0);
+            if (cap == LLL_OK && obs_every > 0 && (q + 1) % obs_every == 0) {
+                cap = do_obs(E, E.d_trace + (size_t)8 * E.nrep * m, 1);
+                ++m;
+            }
+        }
+        if (cap == LLL_OK) cap = settle(E);
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(cs, &g);
+        E.st = saved;
+        if (cap != LLL_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            if (made_stream) (void)hipStreamDestroy(cs);
+            return cap;
+        }
+        if (ee != hipSuccess) {
+            if (made_stream) (void)hipStreamDestroy(cs);
+            return set_err(LLL_EDEVICE, "graph capture failed: %s", hipGetErrorString(ee));
+        }
+        if (made_stream) (void)hipStreamDestroy(cs);
+        B->graph = g;
+        HIP_TRY(hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
+        B->g_first = first_pulse;
+        B->g_npulses = n_pulses;
+        B->g_obs_every = obs_every;
+    }
+    HIP_TRY(hipGraphLaunch(B->gexec, E.st));
+    if (trace && nmeas > 0) {
+        std::vector<double> h((size_t)nmeas * 8 * E.nrep);
+        HIP_TRY(hipMemcpyAsync(h.data(), E.d_trace, sizeof(double) * h.size(),
+                               hipMemcpyDeviceToHost, E.st));
+        HIP_TRY(hipStreamSynchronize(E.st));
+        bool fin = true;
+        for (size_t j = 0; j < (size_t)nmeas * E.nrep; ++j) {
+            obs_from(&h[8 * j], &trace[j]);
+            fin = fin && obs_finite(&h[8 * j]);
+        }
+        if (!fin) return set_err(LLL_ENONFINITE, "a replica became NaN or Inf");
+    }
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_batch_observables(lll_batch* B, lll_obs* out) {
+    if (!B || !out) return set_err(LLL_EINVAL, "NULL argument");
+    Engine& E = B->E;
+    lll_status s;
+    if ((s = settle(E)) != LLL_OK) return s;
+    if ((s = do_obs(E, E.d_result, 0)) != LLL_OK) return s;
+    std::vector<double> h((size_t)8 * E.nrep);
+    HIP_TRY(hipMemcpyAsync(h.data(), E.d_result, sizeof(double) * h.size(), hipMemcpyDeviceToHost, E.st));
+    HIP_TRY(hipStreamSynchronize(E.st));
+    bool fin = true;
+    for (int r = 0; r < E.nrep; ++r) {
+        obs_from(&h[8 * r], &out[r]);
+        fin = fin && obs_finite(&h[8 * r]);
+    }
+    if (!fin) return set_err(LLL_ENONFINITE, "a replica holds NaN or Inf");
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_batch_state(lll_batch* B, int32_t rep, void** sx, void** sy, void** sz) {
+    if (!B || !sx || !sy || !sz) return set_err(LLL_EINVAL, "NULL argument");
+    if (rep < 0 || rep >= B->E.nrep) return set_err(LLL_EINVAL, "replica out of range");
+    const int64_t off = B->E.hreps[rep].off;
+    *sx = (char*)B->E.s.x + off * B->E.esz;
+    *sy = (char*)B->E.s.y + off * B->E.esz;
+    *sz = (char*)B->E.s.z + off * B->E.esz;
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_batch_accumulators(lll_batch* B, double* out, int32_t reset) {
+    if (!B || !out) return set_err(LLL_EINVAL, "NULL argument");
+    Engine& E = B->E;
+    HIP_TRY(hipMemcpyAsync(out, E.d_accum, sizeof(double) * 8 * E.nrep, hipMemcpyDeviceToHost, E.st));
+    HIP_TRY(hipStreamSynchronize(E.st));
+    if (reset) {
+        HIP_TRY(hipMemsetAsync(E.d_accum, 0, sizeof(double) * 8 * E.nrep, E.st));
+        HIP_TRY(hipStreamSynchronize(E.st));
+    }
+    return LLL_OK;
+}
+
+extern "C" void lll_batch_destroy(lll_batch* B) {
+    if (!B) return;
+    if (B->E.st) (void)hipStreamSynchronize(B->E.st);
+    else (void)hipDeviceSynchronize();
+    delete B;
+}

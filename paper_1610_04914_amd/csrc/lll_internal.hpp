@@ -1,0 +1,74 @@
+// Internal definitions shared by the host runtime and the kernel translation
+// units of liblll (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lll {
+
+enum AnisMode : int32_t { ANIS_NONE = 0, ANIS_Z = 1, ANIS_AXIS = 2, ANIS_SITE = 3 };
+
+// One replica (a single lattice is a batch of one).  Lives in device memory;
+// every kernel reads the descriptor of the replica it works on.
+struct RepDev {
+    int32_t Lx, Ly, Lz, bc;       // shape, boundary (0 periodic, 1 free)
+    int64_t off;                  // first site of this replica in the packed SoA arrays
+    int32_t tx, ty, tz, tile0;    // fused-kernel tiles per axis and first tile id
+    int32_t ob0, nob;             // observables: first partial block and block count
+    int32_t sb0, nsb;             // per-site kernels: first 256-site block and block count
+    // Stage coefficients.  Precessional case: k = s x (h~ - lam (s x h~)),
+    // h~ = dt h.  Slow equation: k = s x (s x h~), h~ = -lambda dt h.
+    // h~ = cJ * sum_nn s + cH + cD * (s.e) e   (ANIS_SITE: cD * D_i (s.e_i) e_i).
+    double cJ, cH[3], cD, e[3], lam;
+    // Physics for the observables (e normalised).
+    double J, H[3], D, pad2;
+    double sigma;                 // default kick scale sqrt(2 lambda T Dt)
+    double lambda, Dt;            // to rescale sigma for a per-pulse temperature
+    uint64_t seed;
+    uint32_t rid;                 // Philox counter word 2
+    int32_t init;                 // initial state: 0 random sphere, 1 along the init direction
+    const void* D_site;           // ANIS_SITE: [N] of the state precision
+    const void* e_site;           // ANIS_SITE: [3N] of the state precision
+};
+
+struct State {
+    void* x;
+    void* y;
+    void* z;
+};
+
+// Kernel launchers (defined in the .hip translation units).  prec: 0 fp64, 1 fp32.
+hipError_t launch_philox_words(uint64_t seed, uint32_t i0, int64_t n, uint32_t c1, uint32_t c2,
+                               uint32_t c3, uint32_t* out, hipStream_t st);
+hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
+                       int mode, double dx, double dy, double dz, hipStream_t st);
+// sigma_override >= 0 replaces every replica's kick scale (per-pulse temperature).
+hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
+                       uint64_t k, double sigma_override, unsigned long long* kickdev,
+                       hipStream_t st);
+hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
+                      int nobblk, int nrep, State s, double* partials, double* result,
+                      double* accum, int accumulate, hipStream_t st);
+// Unfused RK4 step: four stage launches; scratch yA, yB, acc of the same shape.
+hipError_t launch_step_unfused(int prec, int precession, int anis, const RepDev* reps,
+                               const int32_t* blk_rep, int nblk, State s, State yA, State yB,
+                               State acc, hipStream_t st);
+hipError_t launch_copy(int prec, State dst, State src, int64_t n, hipStream_t st);
+
+// Fused RK4 step (one launch per step, z-marching LDS tiles).
+struct FusedInfo {
+    int bx, by, threads, lds_bytes;
+};
+int fused_variant_count(int prec);
+bool fused_variant_info(int prec, int variant, FusedInfo* out);
+// kick != 0: apply kick number k to the step's output (epilogue);
+// sigma_override >= 0 replaces every replica's kick scale.
+hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz,
+                             const RepDev* reps, const int4* tiles, int ntiles, State in,
+                             State out, int kick, uint64_t k, double sigma_override,
+                             unsigned long long* kickdev, hipStream_t st);
+
+// Adjoint kernels.
+struct AdjBuffers;
+}  // namespace lll

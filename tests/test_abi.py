@@ -1,0 +1,139 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/lll.h, its structs have the layout the
+Python binding marshals, and argument validation that happens before any
+device call returns the documented status codes."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lll.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:lll_status|void|const char\s*\*)\s*(lll_\w+)\s*\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1610_04914_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.fail("liblll.so is not built (run __graft_entry__.build())")
+    P.lib()
+    return P
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for req in ("lll_init_lattice", "lll_step_conservative", "lll_noise_pulse", "lll_observables",
+                "lll_run", "lll_destroy", "lll_last_error", "lll_batch_create", "lll_batch_run",
+                "lll_adjoint", "lll_autotune", "lll_philox4x32_10"):
+        assert req in names
+
+
+def test_library_exports_every_declared_symbol(P):
+    L = P.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(ln.split()[-1] for ln in out.splitlines() if ln.strip())
+    assert set(declared_functions()) <= exported
+
+
+def test_struct_layout_matches_binding(P):
+    """sizeof/offsetof of the public structs as gcc sees include/lll.h equal
+    what the ctypes binding uses."""
+    src = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "lll.h"
+#define F(T, m) printf("%s.%s %zu\n", #T, #m, offsetof(T, m));
+int main(void) {
+  printf("lll_params %zu\nlll_obs %zu\nlll_replica_desc %zu\n", sizeof(lll_params), sizeof(lll_obs),
+         sizeof(lll_replica_desc));
+  F(lll_params, D_site) F(lll_params, lambda) F(lll_params, precession) F(lll_params, seed)
+  F(lll_obs, m) F(lll_obs, max_norm_dev)
+  F(lll_replica_desc, lambda) F(lll_replica_desc, seed) F(lll_replica_desc, replica)
+  F(lll_replica_desc, init)
+  return 0;
+}
+"""
+    d = tempfile.mkdtemp()
+    cfile = os.path.join(d, "layout.c")
+    exe = os.path.join(d, "layout")
+    open(cfile, "w").write(src)
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), "-o", exe, cfile])
+    lines = dict(ln.rsplit(" ", 1) for ln in subprocess.check_output([exe], text=True).splitlines())
+    lay = {k: int(v) for k, v in lines.items()}
+    assert lay["lll_params"] == C.sizeof(P.lll_params)
+    assert lay["lll_obs"] == C.sizeof(P.lll_obs)
+    assert lay["lll_replica_desc"] == C.sizeof(P.lll_replica_desc)
+    assert lay["lll_params.D_site"] == P.lll_params.D_site.offset
+    assert lay["lll_params.lambda"] == P.lll_params.lambda_.offset
+    assert lay["lll_params.precession"] == P.lll_params.precession.offset
+    assert lay["lll_params.seed"] == P.lll_params.seed.offset
+    assert lay["lll_obs.m"] == P.lll_obs.m.offset
+    assert lay["lll_obs.max_norm_dev"] == P.lll_obs.max_norm_dev.offset
+    assert lay["lll_replica_desc.lambda"] == P.lll_replica_desc.lambda_.offset
+    assert lay["lll_replica_desc.seed"] == P.lll_replica_desc.seed.offset
+    assert lay["lll_replica_desc.replica"] == P.lll_replica_desc.replica.offset
+    assert lay["lll_replica_desc.init"] == P.lll_replica_desc.init.offset
+
+
+def test_validation_before_device_use(P):
+    L = P.lib()
+    h = C.c_void_p()
+    st = L.lll_init_lattice(0, 4, 4, 0, 1, 0, None, 0, None, None, None, None, C.byref(h))
+    assert st == P.LLL_EINVAL and b"sizes" in L.lll_last_error()
+    st = L.lll_init_lattice(4, 4, 4, 7, 1, 0, None, 0, None, None, None, None, C.byref(h))
+    assert st == P.LLL_EINVAL
+    st = L.lll_init_lattice(4, 4, 4, 0, 9, 0, None, 0, None, None, None, None, C.byref(h))
+    assert st == P.LLL_EINVAL
+    st = L.lll_init_lattice(4, 4, 4, 0, 1, 0, None, 0, C.c_void_p(16), None, None, None, C.byref(h))
+    assert st == P.LLL_EINVAL and b"all three" in L.lll_last_error()
+    st = L.lll_init_lattice(4, 4, 4, 0, 1, P.LLL_INIT_KEEP, None, 0, None, None, None, None, C.byref(h))
+    assert st == P.LLL_EINVAL
+    st = L.lll_init_lattice(4, 4, 4, 0, 1, P.LLL_INIT_DIRECTION, None, 0, None, None, None, None,
+                            C.byref(h))
+    assert st == P.LLL_EINVAL
+    assert L.lll_init_lattice(4, 4, 4, 0, 1, 0, None, 0, None, None, None, None, None) == P.LLL_EINVAL
+    assert L.lll_step_conservative(None, None, 1) == P.LLL_EINVAL
+    assert L.lll_run(None, None, 0, 1, None, 0, None) == P.LLL_EINVAL
+    assert L.lll_philox4x32_10(0, 0, -1, 0, 0, 0, None, None) == P.LLL_EINVAL
+    assert L.lll_philox4x32_10(0, 0, 0, 0, 0, 0, None, None) == P.LLL_OK
+    assert L.lll_batch_create(0, None, 1, 0.1, 1.0, 1, None, C.byref(h)) == P.LLL_EINVAL
+    desc = (P.lll_replica_desc * 1)()
+    desc[0].Lx = desc[0].Ly = desc[0].Lz = 4
+    desc[0].lambda_ = 0.01
+    desc[0].T = 1.0
+    assert L.lll_batch_create(1, desc, 1, 0.3, 1.0, 1, None, C.byref(h)) == P.LLL_EINVAL
+    assert b"not a positive integer" in L.lll_last_error()
+
+
+def test_variant_table(P):
+    for prec in ("fp32", "fp64"):
+        vs = P.step_variants(prec)
+        assert vs[0] == 0 and len(vs) >= 3
+        for v in vs[1:]:
+            info = P.step_variant_info(prec, v)
+            es = 8 if prec == "fp64" else 4
+            bx, by = info["bx"], info["by"]
+            r = sum((bx + 2 * q) * (by + 2 * q) for q in range(1, 5))
+            assert info["lds_bytes"] == 6 * es * r
+            assert info["lds_bytes"] <= 160 * 1024
+            assert info["threads"] % 64 == 0 and info["threads"] <= 1024
+
+
+def test_binding_fails_loudly_without_gpu(P):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        P.Lattice((4, 4, 4))

@@ -1,0 +1,344 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (max abs difference per spin component; spins are unit vectors,
+so absolute = relative): 1e-12 for fp64, 1e-5 for fp32, per step-segment,
+starting the oracle from the GPU's own state (chaotic dynamics forbids whole
+trajectory comparisons).  Random words and the sphere's z component are
+compared bit for bit.  Observables: relative 1e-12 (fp64 reductions).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1610_04914_amd as P
+    P.lib()
+    assert torch.cuda.is_available()
+    return P
+
+
+def np_state(lat):
+    torch.cuda.synchronize()
+    return lat.state.double().cpu().numpy()
+
+
+def make_lattice(P, shape, bc, prec, s0):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    t = torch.tensor(np.asarray(s0), dtype=dt, device="cuda")
+    return P.Lattice(shape, bc=bc, precision=prec, state=t)
+
+
+def rounded(s, prec):
+    return s.astype(np.float32).astype(np.float64) if prec == "fp32" else s.copy()
+
+
+PHYS = {
+    "axis": dict(J=1.0, H=(0.1, -0.2, 0.3), D=0.4, e=(1.0, 2.0, 2.0), lam=0.05, T=0.7),
+    "zaxis": dict(J=1.0, H=(0.0, 0.0, 0.1), D=0.05, e=(0.0, 0.0, 1.0), lam=0.01, T=1.0),
+    "none": dict(J=0.8, H=(0.0, 0.3, 0.0), D=0.0, lam=0.02, T=0.5),
+}
+
+
+def both_params(kind, dt=0.1, Dt=0.4, precession=True, seed=11, **over):
+    kw = dict(PHYS[kind])
+    kw.update(over)
+    gp = dict(kw, dt=dt, Dt=Dt, precession=precession)
+    return orc.Params(**gp), __import__("paper_1610_04914_amd").Params(seed=seed, **gp)
+
+
+def variants(P, prec):
+    return P.step_variants(prec)
+
+
+# ------------------------------------------------------------------- RNG ----
+@pytest.mark.parametrize("seed,i0,c1,c2,c3", [(0, 0, 0, 0, 0), (12345, 7, 3, 2, 1),
+                                              (2**64 - 1, 2**32 - 100, 2**32 - 1, 5, 1),
+                                              (0xDEADBEEFCAFEF00D, 1000, 17, 95, 0)])
+def test_philox_words_bitexact(P, seed, i0, c1, c2, c3):
+    n = 5000
+    out = torch.zeros(4 * n, dtype=torch.int32, device="cuda")
+    P.lll_philox4x32_10(seed, i0, n, c1, c2, c3, out.data_ptr(), P._stream())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32).reshape(n, 4)
+    want = orc.philox_stream(seed, i0, n, c1, c2, c3)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (7, 5, 3)])
+def test_init_random_sphere(P, prec, shape):
+    lat = P.Lattice(shape, precision=prec, init="random", seed=42)
+    got = np_state(lat)
+    want = orc.init_random_sphere(orc.geom(shape), 42, 0)
+    if prec == "fp64":
+        assert np.array_equal(got[2], want[2])            # z = 2u - 1 is exact
+        np.testing.assert_allclose(got[:2], want[:2], rtol=0, atol=4e-16)
+    else:
+        np.testing.assert_allclose(got, want, rtol=0, atol=1.5e-7)
+    lat2 = P.Lattice(shape, precision=prec, init="direction", direction=(1.0, 2.0, 2.0))
+    np.testing.assert_allclose(np_state(lat2), np.array([[1 / 3], [2 / 3], [2 / 3]]) * np.ones((1, lat2.N)),
+                               atol=1e-7)
+
+
+# ------------------------------------------------------------------ steps ---
+STEP_SHAPES = [((40, 24, 20), "periodic", 7), ((40, 24, 20), "free", 0), ((17, 5, 3), "periodic", 0),
+               ((3, 3, 3), "periodic", 0), ((2, 3, 5), "free", 2), ((1, 1, 1), "periodic", 0),
+               ((2, 2, 2), "periodic", 0), ((33, 17, 9), "periodic", 4)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind,precession", [("axis", True), ("zaxis", True), ("none", True),
+                                             ("zaxis", False)])
+def test_step_parity_all_variants(P, prec, kind, precession):
+    op, gp = both_params(kind, precession=precession)
+    for shape, bc, bz in STEP_SHAPES:
+        N = int(np.prod(shape))
+        s0 = rounded(inputs.unit_spins(N, 100 + N), prec)
+        want = orc.step(orc.geom(shape, bc), op, s0, 3)
+        for v in variants(P, prec):
+            lat = make_lattice(P, shape, bc, prec, s0)
+            lat.set_step_config(v, bz)
+            lat.step(gp, 3)
+            got = np_state(lat)
+            err = np.max(np.abs(got - want))
+            assert err < TOL[prec], (shape, bc, v, bz, err)
+            lat.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_step_site_anisotropy(P, prec):
+    shape = (12, 10, 9)
+    N = 1080
+    D, e = inputs.site_anisotropy(N, 5)
+    s0 = rounded(inputs.unit_spins(N, 6), prec)
+    Dr, er = rounded(D[None, :], prec)[0], rounded(e, prec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Dt_ = torch.tensor(Dr, dtype=dt, device="cuda")
+    et = torch.tensor(er, dtype=dt, device="cuda")
+    op = orc.Params(J=1.0, H=(0, 0, 0.2), lam=0.01, T=0.5, dt=0.1, Dt=0.2, D_site=Dr, e_site=er)
+    gp = P.Params(J=1.0, H=(0, 0, 0.2), lam=0.01, T=0.5, dt=0.1, Dt=0.2, D_site=Dt_, e_site=et,
+                  seed=3)
+    lat = make_lattice(P, shape, "periodic", prec, s0)
+    lat.run(gp, first_pulse=0, n_pulses=2)
+    want, _, _ = orc.run(orc.geom(shape), op, s0, seed=3, n_pulses=1)
+    want, _, _ = orc.run(orc.geom(shape), op, want, seed=3, first_pulse=1, n_pulses=1)
+    # two intervals of two steps: still one short segment
+    assert np.max(np.abs(np_state(lat) - want)) < 4 * TOL[prec]
+
+
+# ------------------------------------------------------------------ kicks ---
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_kick_parity(P, prec):
+    shape = (20, 12, 9)
+    N = int(np.prod(shape))
+    s0 = inputs.unit_spins(N, 8) * (1 + 0.01 * inputs.rng(9).random(N))[None, :]
+    s0 = rounded(s0, prec)
+    op, gp = both_params("zaxis", Dt=10.0, dt=0.25, seed=77)
+    lat = make_lattice(P, shape, "periodic", prec, s0)
+    lat.kick_norm_dev(reset=True)
+    lat.pulse(gp, 123)
+    want, dev = orc.kick(orc.geom(shape), op, s0, op.T, seed=77, r=0, k=123)
+    got = np_state(lat)
+    assert np.max(np.abs(got - want)) < TOL[prec]
+    assert lat.kick_norm_dev() == pytest.approx(dev, rel=1e-5 if prec == "fp32" else 1e-10)
+    # T = 0: pure renormalisation
+    lat2 = make_lattice(P, shape, "periodic", prec, s0)
+    op0, gp0 = both_params("zaxis", Dt=10.0, dt=0.25, seed=77, T=0.0)
+    lat2.pulse(gp0, 5)
+    np.testing.assert_allclose(np_state(lat2), s0 / np.linalg.norm(s0, axis=0), atol=TOL[prec] * 0.1)
+
+
+# ------------------------------------------------------------ observables ---
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["axis", "zaxis", "none"])
+@pytest.mark.parametrize("shape,bc", [((40, 24, 20), "periodic"), ((17, 5, 3), "free"),
+                                      ((1, 1, 1), "periodic"), ((2, 2, 2), "periodic")])
+def test_observables_parity(P, prec, kind, shape, bc):
+    N = int(np.prod(shape))
+    s0 = rounded(inputs.unit_spins(N, 21) * 1.001, prec)
+    op, gp = both_params(kind)
+    lat = make_lattice(P, shape, bc, prec, s0)
+    got = lat.observables(gp)
+    want = orc.observables(orc.geom(shape, bc), op, s0)
+    for k in ("E_total", "E_exch", "E_zeeman", "E_anis"):
+        assert got[k] == pytest.approx(want[k], rel=1e-12, abs=1e-13 * N), k
+    np.testing.assert_allclose(got["m"], want["m"], rtol=1e-12, atol=1e-15)
+    assert got["max_norm_dev"] == pytest.approx(want["max_norm_dev"], rel=1e-12, abs=1e-16)
+
+
+def test_observables_nonfinite(P):
+    shape = (8, 8, 8)
+    s0 = inputs.unit_spins(512, 1)
+    lat = make_lattice(P, shape, "periodic", "fp32", s0)
+    lat.state[1, 77] = float("nan")
+    _, gp = both_params("zaxis")
+    with pytest.raises(P.LLLError) as ei:
+        lat.observables(gp)
+    assert ei.value.status == P.LLL_ENONFINITE
+
+
+# ------------------------------------------------------------- schedule -----
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dt,Dt", [(0.1, 0.4), (0.1, 0.3), (0.2, 0.2)])
+def test_run_per_segment(P, prec, dt, Dt):
+    """Each interval (n1 steps, kick, n2 steps) of lll_run against the oracle
+    started from the GPU's state before that interval."""
+    shape = (40, 24, 20)
+    N = int(np.prod(shape))
+    op, gp = both_params("zaxis", dt=dt, Dt=Dt, seed=5)
+    g = orc.geom(shape)
+    for v in variants(P, prec):
+        lat = P.Lattice(shape, precision=prec, init="random", seed=9)
+        lat.set_step_config(v, 0)
+        prev = np_state(lat)
+        for q in range(3):
+            tr = lat.run(gp, first_pulse=10 + q, n_pulses=1, obs_every=1)
+            cur = np_state(lat)
+            want, otr, _ = orc.run(g, op, prev, seed=5, first_pulse=10 + q, n_pulses=1, obs_every=1)
+            err = np.max(np.abs(cur - want))
+            assert err < TOL[prec], (v, q, err)
+            o = orc.observables(g, op, cur)
+            assert tr[0]["E_total"] == pytest.approx(o["E_total"], rel=1e-12, abs=1e-13 * N)
+            np.testing.assert_allclose(tr[0]["m"], o["m"], rtol=1e-12, atol=1e-15)
+            prev = cur
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_schedule_identity_bitexact(P, prec):
+    """lll_run(K) == step(n1), pulse(k), step(n2) repeated == run(1) + run(K-1),
+    bit for bit (the noise is a function of the pulse index only)."""
+    shape = (40, 24, 20)
+    _, gp = both_params("axis", dt=0.1, Dt=0.5, seed=8)
+    for v in variants(P, prec):
+        a = P.Lattice(shape, precision=prec, seed=3)
+        b = P.Lattice(shape, precision=prec, seed=3)
+        c = P.Lattice(shape, precision=prec, seed=3)
+        for L in (a, b, c):
+            L.set_step_config(v, 0)
+        a.run(gp, first_pulse=20, n_pulses=3)
+        for k in range(20, 23):
+            b.step(gp, 2)
+            b.pulse(gp, k)
+            b.step(gp, 3)
+        c.run(gp, first_pulse=20, n_pulses=1)
+        c.run(gp, first_pulse=21, n_pulses=2)
+        torch.cuda.synchronize()
+        assert torch.equal(a.state, b.state), v
+        assert torch.equal(a.state, c.state), v
+        # run-to-run determinism
+        d = P.Lattice(shape, precision=prec, seed=3)
+        d.set_step_config(v, 0)
+        d.run(gp, first_pulse=20, n_pulses=3)
+        torch.cuda.synchronize()
+        assert torch.equal(a.state, d.state)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_temperature_ramp(P, prec):
+    shape = (17, 9, 11)
+    op, gp = both_params("zaxis", dt=0.2, Dt=0.2, lam=0.1, seed=4, precession=False)
+    Ts = [2.0, 1.5, 1.0, 0.5]
+    lat = P.Lattice(shape, precision=prec, seed=1)
+    prev = np_state(lat)
+    g = orc.geom(shape)
+    for q, T in enumerate(Ts):
+        lat.run(gp, first_pulse=q, n_pulses=1, T_per_pulse=[T])
+        cur = np_state(lat)
+        want, _, _ = orc.run(g, op, prev, seed=4, first_pulse=q, n_pulses=1, T_per_pulse=[T])
+        assert np.max(np.abs(cur - want)) < TOL[prec]
+        prev = cur
+
+
+# --------------------------------------------------- full-size, sampled -----
+def _cutout(s, shape, centre, rad):
+    """(3, (2rad+1)^3) periodic cut-out around centre and its global site ids."""
+    Lx, Ly, Lz = shape
+    cx, cy, cz = centre
+    r = np.arange(-rad, rad + 1)
+    xs = (cx + r) % Lx
+    ys = (cy + r) % Ly
+    zs = (cz + r) % Lz
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    ids = (X + Lx * (Y + Ly * Z)).ravel()
+    return s[:, ids], ids.astype(np.uint32)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_full_size_sampled(P, prec):
+    """128^3 headline lattice in the benchmark's launch configuration: one
+    interval of two steps (step with the fused kick epilogue, then a step);
+    sampled sites are recomputed by the oracle on a free-boundary cut-out of
+    radius 8 with the sites' global noise counters."""
+    shape = (128, 128, 128)
+    import bench
+    op, gp = both_params("zaxis", dt=0.2, Dt=0.4, seed=0)
+    lat = P.Lattice(shape, precision=prec, init="random", seed=0)
+    bench.configure_lattice(lat, prec, shape)
+    s0 = np_state(lat)
+    lat.run(gp, first_pulse=7, n_pulses=1)
+    s1 = np_state(lat)
+    rng = np.random.default_rng(2)
+    cen = [tuple(c) for c in rng.integers(0, 128, size=(24, 3))] + [(0, 0, 0), (127, 127, 127),
+                                                                      (31, 15, 64), (32, 16, 0)]
+    rad = 8
+    n = 2 * rad + 1
+    gc = orc.geom((n, n, n), "free")
+    mid = (n**3) // 2
+    for c in cen:
+        cut, ids = _cutout(s0, shape, c, rad)
+        st = orc.step(gc, op, cut, 1)
+        st, _ = orc.kick_indexed(gc, op, st, op.T, seed=0, r=0, k=7, site_id=ids)
+        st = orc.step(gc, op, st, 1)
+        i = c[0] + 128 * (c[1] + 128 * c[2])
+        err = np.max(np.abs(st[:, mid] - s1[:, i]))
+        assert err < TOL[prec], (c, err)
+    # observables at full size
+    got = lat.observables(gp)
+    want = orc.observables(orc.geom(shape), op, s1)
+    assert got["E_total"] == pytest.approx(want["E_total"], rel=1e-12, abs=1e-13 * 128**3)
+    np.testing.assert_allclose(got["m"], want["m"], rtol=1e-11, atol=1e-14)
+
+
+# ------------------------------------------------------------------ batch ---
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_matches_oracle(P, prec):
+    reps = [dict(L=(8, 8, 8), T=0.5, lam=0.02, seed=11, replica=0),
+            dict(L=(12, 12, 12), T=1.5, lam=0.005, seed=12, replica=1),
+            dict(L=(5, 6, 7), T=1.0, lam=0.05, seed=13, replica=2, H=(0, 0, 0.2)),
+            dict(L=(24, 24, 24), T=0.3, lam=0.01, seed=14, replica=3, D=0.05),
+            dict(L=(17, 9, 3), T=2.0, lam=0.03, seed=15, replica=4, bc="free")]
+    dt, Dt = 0.1, 0.4
+    B = P.Batch(reps, precision=prec, dt=dt, Dt=Dt)
+    prev = []
+    for r, d in enumerate(reps):
+        g = orc.geom(d["L"], d.get("bc", "periodic"))
+        want = orc.init_random_sphere(g, d["seed"], d["replica"])
+        got = B.state(r).double().cpu().numpy()
+        np.testing.assert_allclose(got, want, atol=1.5e-7 if prec == "fp32" else 4e-16)
+        prev.append(got)
+    for q in range(2):
+        tr = B.run(first_pulse=q, n_pulses=1, obs_every=1)
+        for r, d in enumerate(reps):
+            g = orc.geom(d["L"], d.get("bc", "periodic"))
+            op = orc.Params(J=1.0, H=d.get("H", (0, 0, 0)), D=d.get("D", 0.0), lam=d["lam"], T=d["T"],
+                            dt=dt, Dt=Dt)
+            cur = B.state(r).double().cpu().numpy()
+            want, _, _ = orc.run(g, op, prev[r], seed=d["seed"], r=d["replica"], first_pulse=q,
+                                 n_pulses=1)
+            assert np.max(np.abs(cur - want)) < TOL[prec], (q, r)
+            o = orc.observables(g, op, cur)
+            assert tr[0][r]["E_total"] == pytest.approx(o["E_total"], rel=1e-12, abs=1e-12)
+            prev[r] = cur
+    acc = B.accumulators()
+    assert all(a[0] == 2 for a in acc)
+    B.close()

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(kSiteBlock)
         const double sc = 2.3283064365386963e-10;
         z = 2.0 * (((double)w.x + 0.5) * sc) - 1.0;
         const double ph = 6.283185307179586 * (((double)w.y + 0.5) * sc);
-        const double rho = sqrt(1.0 - z * z);
+        const double rho = sqrt(1.0 - __dmul_rn(z, z));  // z*z rounded, as in the definition
         double sn, cs;
         sincos(ph, &sn, &cs);
         x = rho * cs;

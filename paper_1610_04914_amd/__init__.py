@@ -231,6 +231,7 @@ class Lattice:
         self.shape = tuple(int(v) for v in shape)
         self.N = self.shape[0] * self.shape[1] * self.shape[2]
         self.precision = precision
+        self.bc = bc
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         if state is None:
             state = torch.empty((3, self.N), dtype=self.dtype, device="cuda")
@@ -316,6 +317,68 @@ class Lattice:
                "lll_adjoint")
         return {"loss": loss.value, "g_H": list(gH), "g_J": gJ.value,
                 "g_D": gD if gD is not None else gDh.value, "g_s0": gs0}
+
+
+def _loss_function():
+    torch = _torch()
+
+    class LLLLoss(torch.autograd.Function):
+        """L = wE * E(s_T) + wm . m(s_T) after n_pulses intervals of the schedule
+        from the lattice's current state (which the forward advances to s_T).
+        Differentiable in H (3-vector), J (scalar) and D (scalar uniform D, or
+        an (N,) device tensor of per-site D_i of the lattice dtype).  The
+        backward runs the library's adjoint from the saved initial state with a
+        checkpoint every ckpt_every RK4 steps."""
+
+        @staticmethod
+        def forward(ctx, H, J, D, lat, base, first_pulse, n_pulses, ckpt_every, wE, wm):
+            from dataclasses import replace
+            p = replace(base, H=tuple(float(v) for v in H.detach().cpu().tolist()),
+                        J=float(J.detach().cpu()))
+            if D.dim() == 0:
+                p = replace(p, D=float(D.detach().cpu()), D_site=None)
+            else:
+                p = replace(p, D_site=D.detach())
+            s0 = lat.state.clone()
+            lat.run(p, first_pulse=first_pulse, n_pulses=n_pulses)
+            o = lat.observables(p)
+            val = wE * o["E_total"] + sum(w * m for w, m in zip(wm, o["m"]))
+            ctx.lat_meta = (lat.shape, lat.bc, lat.precision)
+            ctx.args = (p, first_pulse, n_pulses, ckpt_every, wE, tuple(wm))
+            ctx.D_shape = D.shape
+            ctx.save_for_backward(s0, H, J, D)
+            return torch.tensor(val, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            s0, H, J, D = ctx.saved_tensors
+            shape, bc, prec = ctx.lat_meta
+            p, first_pulse, n_pulses, ckpt_every, wE, wm = ctx.args
+            tmp = Lattice(shape, bc=bc, precision=prec, state=s0.clone())
+            r = tmp.adjoint(p, first_pulse, n_pulses, ckpt_every=ckpt_every, wE=wE, wm=wm)
+            tmp.close()
+            g = float(gout)
+            gH = torch.tensor(r["g_H"], dtype=H.dtype, device=H.device) * g
+            gJ = torch.tensor(r["g_J"], dtype=J.dtype, device=J.device) * g
+            if D.dim() == 0:
+                gD = torch.tensor(r["g_D"], dtype=D.dtype, device=D.device) * g
+            else:
+                gD = r["g_D"].to(dtype=D.dtype, device=D.device) * g
+            return gH, gJ, gD, None, None, None, None, None, None, None
+
+    return LLLLoss
+
+
+_LLLLoss = None
+
+
+def lll_loss(H, J, D, lat: "Lattice", base: Params, first_pulse: int, n_pulses: int,
+             ckpt_every: int = 10, wE: float = 1.0, wm=(0.0, 0.0, 1.0)):
+    """Differentiable loss of a pulse-noise run (see LLLLoss)."""
+    global _LLLLoss
+    if _LLLLoss is None:
+        _LLLLoss = _loss_function()
+    return _LLLLoss.apply(H, J, D, lat, base, first_pulse, n_pulses, ckpt_every, wE, wm)
 
 
 def step_variant_info(precision: str, variant: int):

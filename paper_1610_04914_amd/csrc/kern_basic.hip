@@ -439,6 +439,44 @@ hipError_t launch_step_unfused(int prec, int precession, int anis, const RepDev*
                       : step_unfused_p<float, false>(anis, reps, blk_rep, nblk, s, yA, yB, acc, st);
 }
 
+// RK4 step that keeps its stage inputs: y2, y3, y4 and the result xnext are
+// separate buffers (the adjoint stores them); acc is scratch.
+template <typename T, bool PREC, int ANIS>
+static hipError_t stages_t(const RepDev* reps, const int32_t* blk_rep, int nblk, State x, State y2,
+                           State y3, State y4, State acc, State xnext, hipStream_t st) {
+    const State ins[4] = {x, y2, y3, y4};
+    const State outs[4] = {y2, y3, y4, xnext};
+    for (int q = 0; q < 4; ++q) {
+        hipLaunchKernelGGL((stage_kernel<T, PREC, ANIS>), dim3(nblk), dim3(kSiteBlock), 0, st, reps,
+                           blk_rep, ins[q], x, acc, outs[q], q + 1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T, bool PREC>
+static hipError_t stages_p(int anis, const RepDev* reps, const int32_t* blk, int nblk, State x,
+                           State y2, State y3, State y4, State acc, State xn, hipStream_t st) {
+    switch (anis) {
+        case ANIS_NONE: return stages_t<T, PREC, ANIS_NONE>(reps, blk, nblk, x, y2, y3, y4, acc, xn, st);
+        case ANIS_Z: return stages_t<T, PREC, ANIS_Z>(reps, blk, nblk, x, y2, y3, y4, acc, xn, st);
+        case ANIS_AXIS: return stages_t<T, PREC, ANIS_AXIS>(reps, blk, nblk, x, y2, y3, y4, acc, xn, st);
+        default: return stages_t<T, PREC, ANIS_SITE>(reps, blk, nblk, x, y2, y3, y4, acc, xn, st);
+    }
+}
+
+hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* reps,
+                             const int32_t* blk_rep, int nblk, State x, State y2, State y3,
+                             State y4, State acc, State xnext, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    if (prec == 0)
+        return precession ? stages_p<double, true>(anis, reps, blk_rep, nblk, x, y2, y3, y4, acc, xnext, st)
+                          : stages_p<double, false>(anis, reps, blk_rep, nblk, x, y2, y3, y4, acc, xnext, st);
+    return precession ? stages_p<float, true>(anis, reps, blk_rep, nblk, x, y2, y3, y4, acc, xnext, st)
+                      : stages_p<float, false>(anis, reps, blk_rep, nblk, x, y2, y3, y4, acc, xnext, st);
+}
+
 // ------------------------------------------------------------------ copy ---
 template <typename T>
 __global__ void __launch_bounds__(256) copy_kernel(State dst, State src, int64_t n) {

@@ -768,6 +768,139 @@ extern "C" lll_status lll_autotune(lll_lattice* L, const lll_params* p, const ch
     return LLL_OK;
 }
 
+// ------------------------------------------------------------- adjoint ----
+// Reverse mode of the schedule: the forward pass stores the state before
+// every ckpt_every-th operation (an operation is one RK4 step or one kick);
+// the backward pass walks the checkpoint blocks in reverse, recomputes each
+// block while keeping the stage inputs of every step, and runs the reverse
+// stages and kick reverses.
+namespace {
+struct TmpAlloc {
+    std::vector<void*> ptrs;
+    ~TmpAlloc() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    void* get(size_t bytes) {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return p;
+    }
+};
+
+State state_at(void* base, size_t comp_bytes, int64_t idx) {
+    char* b = (char*)base + (size_t)idx * 3 * comp_bytes;
+    return State{b, b + comp_bytes, b + 2 * comp_bytes};
+}
+}  // namespace
+
+extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t first_pulse,
+                                  int64_t n_pulses, int32_t ckpt_every, double wE,
+                                  const double wm[3], double* loss, double* g_H, double* g_J,
+                                  void* g_D, void* g_s0) {
+    if (!L || !loss || !g_H || !g_J || !g_D || !wm) return set_err(LLL_EINVAL, "NULL argument");
+    if (n_pulses < 0 || ckpt_every < 1) return set_err(LLL_EINVAL, "bad n_pulses or ckpt_every");
+    lll_status s = lattice_params(L, p, true);
+    if (s != LLL_OK) return s;
+    Engine& E = L->E;
+    if ((s = settle(E)) != LLL_OK) return s;
+    int64_t n;
+    if ((s = steps_per_interval(p->dt, p->Dt, &n)) != LLL_OK) return s;
+    const int64_t n1 = n / 2, n2 = n - n1;
+    std::vector<int> op;          // 0 = RK4 step, 1 = kick
+    std::vector<uint64_t> opk;
+    for (int64_t q = 0; q < n_pulses; ++q) {
+        const uint64_t k = first_pulse + (uint64_t)q;
+        for (int64_t a = 0; a < n1; ++a) { op.push_back(0); opk.push_back(k); }
+        op.push_back(1); opk.push_back(k);
+        for (int64_t a = 0; a < n2; ++a) { op.push_back(0); opk.push_back(k); }
+    }
+    const int64_t nops = (int64_t)op.size();
+    const int64_t K = ckpt_every;
+    const int64_t nblocks = (nops + K - 1) / K;
+    const size_t cb = (size_t)E.nsites * E.esz;
+    TmpAlloc T;
+    void* ck = T.get(3 * cb * (size_t)std::max<int64_t>(nblocks, 1));
+    void* bb = T.get(3 * cb * (size_t)(4 * K + 1));
+    void* sc = T.get(3 * cb * 8);
+    double* part = (double*)T.get(sizeof(double) * 5 * E.nblk);
+    double* acc5 = (double*)T.get(sizeof(double) * 5);
+    if (!ck || !bb || !sc || !part || !acc5) return set_err(LLL_ENOMEM, "adjoint buffers");
+    State cur = state_at(sc, cb, 0), nxt = state_at(sc, cb, 1), accb = state_at(sc, cb, 2);
+    State sbar = state_at(sc, cb, 3), xbar = state_at(sc, cb, 4), kb = state_at(sc, cb, 5);
+    State q = state_at(sc, cb, 6), loc = state_at(sc, cb, 7);
+    // block buffer: slot j holds x, y2, y3, y4 of operation j of the block
+    auto slot = [&](int64_t j, int c) { return state_at(bb, cb, 4 * j + c); };
+    const bool site = p->D_site != nullptr;
+    double* gD = site ? (double*)g_D : nullptr;
+    HIP_TRY(hipMemsetAsync(acc5, 0, sizeof(double) * 5, E.st));
+    if (site) HIP_TRY(hipMemsetAsync(gD, 0, sizeof(double) * E.nsites, E.st));
+    const int pr = E.prec, pc = E.precession, an = E.anis;
+    // forward with checkpoints
+    HIP_TRY(launch_copy(pr, cur, E.s, E.nsites, E.st));
+    for (int64_t j = 0; j < nops; ++j) {
+        if (j % K == 0) HIP_TRY(launch_copy(pr, state_at(ck, cb, j / K), cur, E.nsites, E.st));
+        if (op[j] == 0) {
+            HIP_TRY(launch_rk4_stages(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, cur, slot(0, 1),
+                                      slot(0, 2), slot(0, 3), accb, nxt, E.st));
+            std::swap(cur, nxt);
+        } else {
+            HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, cur, opk[j], -1.0, E.d_kickdev, E.st));
+        }
+    }
+    // loss and its cotangent
+    HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, cur, E.d_partials, E.d_result,
+                       E.d_accum, 0, E.st));
+    HIP_TRY(launch_adj_loss(pr, an, E.dreps, E.d_blk_rep, E.nblk, cur, sbar, wE, wm, gD, part, acc5,
+                            E.st));
+    // backward
+    const double dt = p->dt;
+    for (int64_t b = nblocks - 1; b >= 0; --b) {
+        const int64_t j0 = b * K, j1 = std::min(j0 + K, nops);
+        HIP_TRY(launch_copy(pr, slot(0, 0), state_at(ck, cb, b), E.nsites, E.st));
+        for (int64_t j = j0; j < j1; ++j) {
+            const int64_t sl = j - j0;
+            State nx = slot(sl + 1, 0);
+            if (op[j] == 0) {
+                HIP_TRY(launch_rk4_stages(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, slot(sl, 0),
+                                          slot(sl, 1), slot(sl, 2), slot(sl, 3), accb, nx, E.st));
+            } else {
+                HIP_TRY(launch_copy(pr, nx, slot(sl, 0), E.nsites, E.st));
+                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, opk[j], -1.0,
+                                    E.d_kickdev, E.st));
+            }
+        }
+        for (int64_t j = j1 - 1; j >= j0; --j) {
+            const int64_t sl = j - j0;
+            if (op[j] == 0) {
+                const State y[4] = {slot(sl, 0), slot(sl, 1), slot(sl, 2), slot(sl, 3)};
+                HIP_TRY(launch_adj_step(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, y, dt, sbar, xbar,
+                                        kb, q, loc, gD, part, acc5, E.st));
+                std::swap(sbar, xbar);
+            } else {
+                HIP_TRY(launch_adj_kick(pr, E.dreps, E.d_blk_rep, E.nblk, slot(sl, 0), sbar, opk[j],
+                                        -1.0, E.st));
+            }
+        }
+    }
+    if (g_s0) {
+        State dst{g_s0, (char*)g_s0 + cb, (char*)g_s0 + 2 * cb};
+        HIP_TRY(launch_copy(pr, dst, sbar, E.nsites, E.st));
+    }
+    double h5[5], r[8];
+    HIP_TRY(hipMemcpyAsync(h5, acc5, sizeof h5, hipMemcpyDeviceToHost, E.st));
+    HIP_TRY(hipMemcpyAsync(r, E.d_result, sizeof r, hipMemcpyDeviceToHost, E.st));
+    HIP_TRY(hipStreamSynchronize(E.st));
+    *loss = wE * r[0] + wm[0] * r[4] + wm[1] * r[5] + wm[2] * r[6];
+    g_H[0] = h5[0];
+    g_H[1] = h5[1];
+    g_H[2] = h5[2];
+    *g_J = h5[3];
+    if (!site) *(double*)g_D = h5[4];
+    if (!obs_finite(r)) return set_err(LLL_ENONFINITE, "forward state became NaN or Inf");
+    return LLL_OK;
+}
+
 // --------------------------------------------------------------- batch -----
 struct lll_batch {
     Engine E;

@@ -69,6 +69,21 @@ hipError_t launch_step_fused(int prec, int precession, int anis, int variant, in
                              State out, int kick, uint64_t k, double sigma_override,
                              unsigned long long* kickdev, hipStream_t st);
 
-// Adjoint kernels.
-struct AdjBuffers;
+// RK4 step keeping the stage inputs y2, y3, y4 (per-stage launches).
+hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* reps,
+                             const int32_t* blk_rep, int nblk, State x, State y2, State y3,
+                             State y4, State acc, State xnext, hipStream_t st);
+
+// Adjoint kernels (256-site blocks, the same block table as the per-site kernels).
+// part: [nblk][5] fp64 partials; acc: [5] fp64 {Hbar x3, Jbar, Dbar}; gD: per-site
+// fp64 Dbar_i (per-site anisotropy) or unused.
+hipError_t launch_adj_loss(int prec, int anis, const RepDev* reps, const int32_t* blk, int nblk,
+                           State s, State sbar, double wE, const double wm[3], double* gD,
+                           double* part, double* acc, hipStream_t st);
+hipError_t launch_adj_step(int prec, int precession, int anis, const RepDev* reps,
+                           const int32_t* blk, int nblk, const State y[4], double dt, State sbar,
+                           State xbar, State kb, State q, State loc, double* gD, double* part,
+                           double* acc, hipStream_t st);
+hipError_t launch_adj_kick(int prec, const RepDev* reps, const int32_t* blk, int nblk, State spre,
+                           State sbar, uint64_t k, double sigma_override, hipStream_t st);
 }  // namespace lll

@@ -1,0 +1,158 @@
+"""GPU adjoint (reverse-mode RK4 + kick reverse with checkpointing) against
+the oracle's FP64 adjoint and central finite differences of the GPU forward.
+
+Bars: fp64 gradients within 1e-10 relative (to the largest component) of
+the oracle, fp32 within 1e-3; the loss itself within 1e-12 (fp64)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+GTOL = {"fp64": 1e-10, "fp32": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1610_04914_amd as P
+    P.lib()
+    return P
+
+
+def _dev(a, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    return torch.tensor(np.asarray(a), dtype=dt, device="cuda")
+
+
+def _rel(got, want):
+    got = np.atleast_1d(np.asarray(got, dtype=np.float64))
+    want = np.atleast_1d(np.asarray(want, dtype=np.float64))
+    return float(np.max(np.abs(got - want)) / max(np.max(np.abs(want)), 1e-300))
+
+
+def _rounded(a, prec):
+    return np.asarray(a, dtype=np.float32).astype(np.float64) if prec == "fp32" else np.asarray(a, dtype=np.float64)
+
+
+CASES = [
+    # shape, bc, precession, site anisotropy, dt, Dt, n_pulses, ckpt
+    ((6, 5, 4), "periodic", True, True, 0.1, 0.4, 2, 3),
+    ((7, 3, 5), "free", True, False, 0.1, 0.3, 2, 4),
+    ((5, 5, 5), "periodic", False, True, 0.2, 0.4, 3, 5),
+    ((4, 4, 4), "periodic", True, False, 0.1, 0.1, 3, 1),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES)
+def test_adjoint_vs_oracle(P, prec, case):
+    shape, bc, precession, site, dt, Dt, npl, ck = case
+    N = int(np.prod(shape))
+    s0 = _rounded(inputs.near_ordered_spins(N, 31), prec)
+    D, e = inputs.site_anisotropy(N, 32)
+    D, e = _rounded(D, prec), _rounded(e, prec)
+    kw = dict(J=1.1, H=(0.05, -0.02, 0.2), lam=0.05, T=0.5, dt=dt, Dt=Dt, precession=precession)
+    if site:
+        op = orc.Params(D_site=D, e_site=e, **kw)
+        gp = P.Params(D_site=_dev(D, prec), e_site=_dev(e, prec), seed=6, **kw)
+    else:
+        op = orc.Params(D=0.1, e=(1.0, 0.0, 1.0), **kw)
+        gp = P.Params(D=0.1, e=(1.0, 0.0, 1.0), seed=6, **kw)
+    wm = (0.0, 0.3, 1.0)
+    want = orc.adjoint(orc.geom(shape, bc), op, s0, seed=6, r=0, first_pulse=4, n_pulses=npl,
+                       wE=0.7, wm=wm)
+    lat = P.Lattice(shape, bc=bc, precision=prec, state=_dev(s0, prec))
+    got = lat.adjoint(gp, 4, npl, ckpt_every=ck, wE=0.7, wm=wm, want_g_s0=True)
+    # the adjoint leaves the state alone
+    torch.cuda.synchronize()
+    assert np.array_equal(lat.state.double().cpu().numpy(), s0)
+    tol = GTOL[prec]
+    assert got["loss"] == pytest.approx(want["loss"], rel=1e-12 if prec == "fp64" else 1e-5)
+    assert _rel(got["g_H"], want["g_H"]) < tol
+    assert _rel(got["g_J"], want["g_J"]) < tol
+    gD = got["g_D"].cpu().numpy() if site else got["g_D"]
+    assert _rel(gD, want["g_D"]) < tol
+    assert _rel(got["g_s0"].double().cpu().numpy(), want["g_s0"]) < tol
+
+
+def test_adjoint_finite_differences_gpu(P):
+    """dL/dH_z and dL/dJ of the fp64 GPU adjoint against central differences of
+    the GPU forward run."""
+    shape = (8, 8, 8)
+    N = 512
+    s0 = inputs.near_ordered_spins(N, 40)
+    base = dict(J=1.0, H=(0.0, 0.0, 0.2), D=0.1, lam=0.02, T=0.4, dt=0.1, Dt=0.6, seed=9)
+
+    def L(**over):
+        kw = dict(base)
+        kw.update(over)
+        lat = P.Lattice(shape, precision="fp64", state=_dev(s0, "fp64"))
+        p = P.Params(**kw)
+        lat.run(p, first_pulse=0, n_pulses=3)
+        o = lat.observables(p)
+        return o["E_total"] + o["m"][2]
+
+    lat = P.Lattice(shape, precision="fp64", state=_dev(s0, "fp64"))
+    g = lat.adjoint(P.Params(**base), 0, 3, ckpt_every=4, wE=1.0, wm=(0, 0, 1))
+    eps = 1e-6
+    fd = (L(H=(0, 0, 0.2 + eps)) - L(H=(0, 0, 0.2 - eps))) / (2 * eps)
+    assert abs(fd - g["g_H"][2]) < 1e-6 * max(1.0, abs(fd))
+    fd = (L(J=1.0 + eps) - L(J=1.0 - eps)) / (2 * eps)
+    assert abs(fd - g["g_J"]) < 1e-6 * max(1.0, abs(fd))
+    fd = (L(D=0.1 + eps) - L(D=0.1 - eps)) / (2 * eps)
+    assert abs(fd - g["g_D"]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_autograd_function(P):
+    """torch.autograd path: loss.backward() gives the adjoint's gradients."""
+    shape = (6, 6, 6)
+    N = 216
+    s0 = inputs.near_ordered_spins(N, 41)
+    D, e = inputs.site_anisotropy(N, 42)
+    base = P.Params(J=1.0, lam=0.01, T=0.5, dt=0.1, Dt=0.4, seed=2, e_site=_dev(e, "fp64"))
+    H = torch.tensor([0.0, 0.0, 0.2], dtype=torch.float64, requires_grad=True)
+    J = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    Dt_ = _dev(D, "fp64").requires_grad_(True)
+    lat = P.Lattice(shape, precision="fp64", state=_dev(s0, "fp64"))
+    loss = P.lll_loss(H, J, Dt_, lat, base, first_pulse=0, n_pulses=2, ckpt_every=3)
+    loss.backward()
+    want = orc.adjoint(orc.geom(shape), orc.Params(J=1.0, H=(0, 0, 0.2), lam=0.01, T=0.5, dt=0.1,
+                                                   Dt=0.4, D_site=D, e_site=e),
+                       s0, seed=2, n_pulses=2, wE=1.0, wm=(0, 0, 1))
+    assert float(loss) == pytest.approx(want["loss"], rel=1e-12)
+    assert _rel(H.grad.numpy(), want["g_H"]) < 1e-10
+    assert _rel(float(J.grad), want["g_J"]) < 1e-10
+    assert _rel(Dt_.grad.cpu().numpy(), want["g_D"]) < 1e-10
+
+
+@pytest.fixture(scope="module")
+def config4():
+    """The adjoint workload: 32^3, per-site D_i ~ N(0.1, 0.02^2) along random
+    easy axes, H = (0, 0, 0.2), lambda = 0.01, T = 0.5, ordered start along z,
+    three intervals of 100 RK4 steps (dt = 0.1, Dt = 10), loss = E + m_z."""
+    shape = (32, 32, 32)
+    N = 32**3
+    D, e = inputs.site_anisotropy(N, 4)
+    s0 = np.zeros((3, N))
+    s0[2] = 1.0
+    kw = dict(J=1.0, H=(0.0, 0.0, 0.2), lam=0.01, T=0.5, dt=0.1, Dt=10.0)
+    want = orc.adjoint(orc.geom(shape), orc.Params(D_site=D, e_site=e, **kw), s0, seed=0,
+                       n_pulses=3, wE=1.0, wm=(0, 0, 1))
+    return shape, D, e, s0, kw, want
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adjoint_full_workload(P, config4, prec):
+    shape, D, e, s0, kw, want = config4
+    Dr, er = _rounded(D, prec), _rounded(e, prec)
+    gp = P.Params(D_site=_dev(Dr, prec), e_site=_dev(er, prec), seed=0, **kw)
+    lat = P.Lattice(shape, precision=prec, init="direction", direction=(0, 0, 1))
+    got = lat.adjoint(gp, 0, 3, ckpt_every=10, wE=1.0, wm=(0, 0, 1))
+    tol = GTOL[prec]
+    assert got["loss"] == pytest.approx(want["loss"], rel=1e-12 if prec == "fp64" else 1e-5)
+    assert _rel(got["g_H"], want["g_H"]) < tol
+    assert _rel(got["g_J"], want["g_J"]) < tol
+    assert _rel(got["g_D"].cpu().numpy(), want["g_D"]) < tol

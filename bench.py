@@ -85,6 +85,119 @@ def cpu_baseline(steps: int = 4):
             "sample": f"{steps} RK4 steps of the 128^3 fp64 lattice ({el:.1f} s, one host thread)"}
 
 
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, r
+
+
+def extra_batched(n_pulses: int = 500):
+    """Uneven-replica workload: 32 each of 24^3, 48^3, 64^3, T uniform in
+    [0.3, 2], lambda log-uniform in [0.005, 0.05], J = 1, H = 0, dt = 0.1,
+    Dt = 1.0, random-sphere starts.  fp32 batch (one graph per run) vs the
+    plain fp64 single-lattice path on the same replicas one after another;
+    accuracy compared through each replica's time average of E/N."""
+    import numpy as np
+    import paper_1610_04914_amd as P
+    from tests import inputs
+    reps = inputs.batch_replicas(seed=0)
+    B = P.Batch([dict(r, J=1.0) for r in reps], precision="fp32", dt=0.1, Dt=1.0)
+    B.run(first_pulse=0, n_pulses=10)  # capture + warm-up
+    B.run(first_pulse=0, n_pulses=10)
+    el_b, tr_b = _timed(lambda: B.run(first_pulse=10, n_pulses=n_pulses, obs_every=1))
+    sites = sum(int(np.prod(r["L"])) for r in reps)
+    spin_steps = sites * 10 * n_pulses
+    Eb = np.array([[tr_b[m][r]["E_total"] for m in range(n_pulses)] for r in range(len(reps))])
+    B.close()
+
+    # fp64 single lattices started from the same replica states (the batch keys
+    # each random sphere by (seed, replica); a lone lattice uses replica 0)
+    B0 = P.Batch([dict(r, J=1.0) for r in reps], precision="fp64", dt=0.1, Dt=1.0)
+    lats = []
+    for i, r in enumerate(reps):
+        lat = P.Lattice(r["L"], precision="fp64", state=B0.state(i))
+        lats.append((lat, P.Params(J=1.0, lam=r["lam"], T=r["T"], dt=0.1, Dt=1.0, seed=r["seed"])))
+    B0.close()
+    for lat, p in lats:
+        lat.run(p, first_pulse=0, n_pulses=10)
+
+    def run_seq():
+        return [lat.run(p, first_pulse=10, n_pulses=n_pulses, obs_every=1) for lat, p in lats]
+    el_s, tr_s = _timed(run_seq)
+    Es = np.array([[t["E_total"] for t in tr] for tr in tr_s])
+    N = np.array([float(np.prod(r["L"])) for r in reps])
+    burn = n_pulses // 5
+    mb, ms = Eb[:, burn:].mean(1) / N, Es[:, burn:].mean(1) / N
+
+    def sem(x):
+        nb = 10
+        x = x[: len(x) // nb * nb].reshape(nb, -1).mean(1)
+        return x.std(ddof=1) / np.sqrt(nb)
+    sb = np.array([sem(Eb[r, burn:] / N[r]) for r in range(len(reps))])
+    ss = np.array([sem(Es[r, burn:] / N[r]) for r in range(len(reps))])
+    z = np.abs(mb - ms) / np.sqrt(sb**2 + ss**2)
+    for lat, _ in lats:
+        lat.close()
+    return {"workload": "96 replicas (32 x 24^3, 48^3, 64^3), fp32 batch vs fp64 single-lattice path",
+            "batched_fp32_spin_steps_per_s": spin_steps / el_b,
+            "sequential_fp64_spin_steps_per_s": spin_steps / el_s,
+            "speedup": el_s / el_b,
+            "replicas_within_2sigma": int(np.sum(z < 2.0)), "replicas": len(reps),
+            "max_z": float(z.max()), "pulses": n_pulses}
+
+
+def extra_adjoint():
+    """Adjoint workload (32^3, per-site anisotropy, 3 intervals of 100 steps):
+    (forward with checkpoints + backward with recompute) / plain forward."""
+    import numpy as np
+    import torch
+    import paper_1610_04914_amd as P
+    from tests import inputs
+    N = 32**3
+    D, e = inputs.site_anisotropy(N, 4)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        dt_ = torch.float64 if prec == "fp64" else torch.float32
+        Dt_ = torch.tensor(D, dtype=dt_, device="cuda")
+        et = torch.tensor(e, dtype=dt_, device="cuda")
+        p = P.Params(J=1.0, H=(0, 0, 0.2), lam=0.01, T=0.5, dt=0.1, Dt=10.0, D_site=Dt_, e_site=et,
+                     seed=0)
+        lat = P.Lattice((32, 32, 32), precision=prec, init="direction", direction=(0, 0, 1))
+        s0 = lat.state.clone()
+        lat.run(p, 0, 3)
+        lat.state.copy_(s0)
+        el_f, _ = _timed(lambda: (lat.run(p, 0, 3), lat.observables(p)))
+        lat.state.copy_(s0)
+        lat.adjoint(p, 0, 3, ckpt_every=10, wE=1.0, wm=(0, 0, 1))
+        el_a, _ = _timed(lambda: lat.adjoint(p, 0, 3, ckpt_every=10, wE=1.0, wm=(0, 0, 1)))
+        out[prec] = {"forward_s": el_f, "adjoint_s": el_a, "ratio": el_a / el_f}
+        lat.close()
+    return out
+
+
+def extra_overdamped(n_pulses: int = 5000):
+    """256^3, fp32, slow equation, J = 1, D = 0.02 z, lambda = 0.1, dt = Dt = 0.4
+    (pulse every step), T ramp 2.0 -> 0.5."""
+    import numpy as np
+    import paper_1610_04914_amd as P
+    lat = P.Lattice((256, 256, 256), precision="fp32", init="random", seed=0)
+    p = P.Params(J=1.0, D=0.02, e=(0, 0, 1), lam=0.1, T=2.0, dt=0.4, Dt=0.4,
+                 precession=False, seed=0)
+    lat.autotune(p, cache_path=TUNE_CACHE)
+    Ts = list(2.0 - 1.5 * np.arange(n_pulses) / (n_pulses - 1))
+    lat.run(p, 0, 10, T_per_pulse=Ts[:10])
+    el, tr = _timed(lambda: lat.run(p, 0, n_pulses, T_per_pulse=Ts, obs_every=100))
+    N = lat.N
+    lat.close()
+    return {"workload": "256^3 fp32 slow equation, T ramp 2.0->0.5", "pulses": n_pulses,
+            "spin_steps_per_s": N * n_pulses / el,
+            "hbm_frac_alg": N * n_pulses * 24 / el / (HBM_PEAK_GBS * 1e9),
+            "final_abs_m": float(np.linalg.norm(tr[-1]["m"]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +206,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the batched, adjoint and 256^3 overdamped workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -179,6 +294,9 @@ def main():
                      "avg_launch_ms": step_ms},
         "final_obs": trace[-1] if trace else None,
     }
+    if args.extras:
+        out["extras"] = {"batched": extra_batched(), "adjoint": extra_adjoint(),
+                         "overdamped_256": extra_overdamped()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out))

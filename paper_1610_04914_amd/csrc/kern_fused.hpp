@@ -55,27 +55,44 @@ __host__ __device__ inline void ring_decode(int idx, int& lx, int& ly) {
     }
 }
 
+// k of one stage at a point whose own values on the planes below/at/above
+// are zm, c, zp, with the four in-plane neighbours read from the LDS plane
+// (L0, L1, L2) of frame width W at offset o.
+template <typename T, bool PREC, int ANIS, int W>
+__device__ __forceinline__ void stage_at(const T* L0, const T* L1, const T* L2, int o, const T* c,
+                                         const T* zm, const T* zp, const Coef<T>& C, T Di, T ex,
+                                         T ey, T ez, T& kx, T& ky, T& kz) {
+    const T nx = (L0[o - 1] + L0[o + 1]) + (L0[o - W] + L0[o + W]) + (zm[0] + zp[0]);
+    const T ny = (L1[o - 1] + L1[o + 1]) + (L1[o - W] + L1[o + W]) + (zm[1] + zp[1]);
+    const T nz = (L2[o - 1] + L2[o + 1]) + (L2[o - W] + L2[o + W]) + (zm[2] + zp[2]);
+    stage_k<T, PREC, ANIS>(c[0], c[1], c[2], nx, ny, nz, C, Di, ex, ey, ez, kx, ky, kz);
+}
+
 template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, bool KICK>
 __global__ void __launch_bounds__(NT)
     rk4_fused_kernel(const RepDev* __restrict__ reps, const int4* __restrict__ tiles, State in,
                      State out, int bz_arg, uint64_t kpulse, double sigma_override,
                      unsigned long long* kickdev) {
-    constexpr int W0 = BX + 8, W1 = BX + 6, W2 = BX + 4, W3 = BX + 2;
+    // Region Rs = the tile grown by 4-s sites in x and y (R0: loaded points).
     constexpr int R0 = (BX + 8) * (BY + 8);
     constexpr int R1 = (BX + 6) * (BY + 6);
     constexpr int R2 = (BX + 4) * (BY + 4);
     constexpr int R3 = (BX + 2) * (BY + 2);
     constexpr int R4 = BX * BY;
     constexpr int NI = (R0 + NT - 1) / NT;
+    // LDS row pitches: the frame widths rounded up to odd, so that points of
+    // a ring column (one row apart) fall in distinct LDS banks.
+    constexpr int W0 = (BX + 8) | 1, W1 = (BX + 6) | 1, W2 = (BX + 4) | 1, W3 = (BX + 2) | 1;
 
     // Stage-input planes, double-buffered by plane parity: A1 = x on the
     // load region, A2 = y2 on R1, A3 = y3 on R2, A4 = y4 on R3.
-    __shared__ T sA1[2][3][R0];
-    __shared__ T sA2[2][3][R1];
-    __shared__ T sA3[2][3][R2];
-    __shared__ T sA4[2][3][R3];
+    __shared__ T sA1[2][3][W0 * (BY + 8)];
+    __shared__ T sA2[2][3][W1 * (BY + 6)];
+    __shared__ T sA3[2][3][W2 * (BY + 4)];
+    __shared__ T sA4[2][3][W3 * (BY + 2)];
 
     const int tid = threadIdx.x;
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // first thread of this wave
     const int4 tl = tiles[blockIdx.x];
     const RepDev& R = reps[tl.x];
     const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
@@ -84,7 +101,10 @@ __global__ void __launch_bounds__(NT)
     if (bzr > Lz) bzr = Lz;
     const int x0 = tl.y * BX, y0 = tl.z * BY, z0 = tl.w * bzr;
     const int zend = min(z0 + bzr, Lz);
+    // Planes z0-4 .. zend+3 are loaded; the trip count is padded to a multiple
+    // of four (the padding computes planes whose results are never stored).
     const int niter = (zend - z0) + 8;
+    const int niter4 = (niter + 3) & ~3;
     const int64_t plane = (int64_t)Lx * Ly;
     const int64_t N = plane * Lz;
     const T* __restrict__ ix = static_cast<const T*>(in.x) + R.off;
@@ -97,7 +117,11 @@ __global__ void __launch_bounds__(NT)
     const T* Dsite = static_cast<const T*>(R.D_site);
     const T* esite = static_cast<const T*>(R.e_site);
 
+    // Per point: LDS offsets of its own value in frames A1..A4 (written by the
+    // stage that produces it), read offsets (its own offset inside the stage's
+    // region, else a harmless interior point), global column, flags.
     int o1[NI], o2[NI], o3[NI], o4[NI];
+    int r1[NI], r2[NI], r3[NI], r4[NI];
     int col[NI];
     bool colok[NI], outok[NI];
 #pragma unroll
@@ -109,6 +133,10 @@ __global__ void __launch_bounds__(NT)
         o2[j] = (ly + 3) * W1 + (lx + 3);
         o3[j] = (ly + 2) * W2 + (lx + 2);
         o4[j] = (ly + 1) * W3 + (lx + 1);
+        r1[j] = idx < R1 ? o1[j] : W0 + 1;
+        r2[j] = idx < R2 ? o2[j] : W1 + 1;
+        r3[j] = idx < R3 ? o3[j] : W2 + 1;
+        r4[j] = idx < R4 ? o4[j] : W3 + 1;
         int gx = x0 + lx, gy = y0 + ly;
         bool ok = idx < R0;
         if (pbc) {
@@ -122,7 +150,14 @@ __global__ void __launch_bounds__(NT)
         outok[j] = idx < R4 && (x0 + lx) < Lx && (y0 + ly) < Ly;
     }
 
+    // Register FIFOs indexed by plane mod 4: x, stage inputs y2..y4, RK4 accumulator.
     T X[NI][4][3], Y2[NI][4][3], Y3[NI][4][3], Y4[NI][4][3], A[NI][4][3], XN[NI][3];
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) X[j][s][c] = Y2[j][s][c] = Y3[j][s][c] = Y4[j][s][c] = A[j][s][c] = T(0);
 
     auto load_plane = [&](int P) {
         bool zok = true;
@@ -172,193 +207,167 @@ __global__ void __launch_bounds__(NT)
     T sg = T(0);
     if constexpr (KICK) sg = (T)(sigma_override >= 0.0 ? sigma_override : R.sigma);
 
+    // Item j's points cover stage region Rs entirely (compile time), or this
+    // wave holds at least one of its points (wave-uniform).
+#define LLL_ITEM_WAVE_IN(j, Rs) (((j) + 1) * NT <= (Rs) || ((j) * NT + wbase) < (Rs))
+#define LLL_ITEM_LANE_IN(j, Rs) (((j) + 1) * NT <= (Rs) || ((j) * NT + tid) < (Rs))
+
     load_plane(z0 - 4);
 
-    for (int t0 = 0; t0 < niter; t0 += 4) {
+    for (int t0 = 0; t0 < niter4; t0 += 4) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int t = t0 + u;
-            if (t < niter) {
-                const int P = z0 - 4 + t;
-                constexpr int dummy = 0;
-                (void)dummy;
-                const int u1 = (u + 3) & 3, u2 = (u + 2) & 3, u3 = (u + 1) & 3;  // planes P-1, P-2, P-3
-                // ---- commit x(P), prefetch x(P+1)
+            const int P = z0 - 4 + t;
+            const int u1 = (u + 3) & 3, u2 = (u + 2) & 3, u3 = (u + 1) & 3;  // planes P-1, P-2, P-3
+            // ---- commit x(P), prefetch x(P+1)
 #pragma unroll
-                for (int j = 0; j < NI; ++j)
+            for (int j = 0; j < NI; ++j)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) X[j][u][c] = XN[j][c];
-                if (t + 1 < niter) load_plane(P + 1);
-                {
-                    const int sl = t & 1;
+                for (int c = 0; c < 3; ++c) X[j][u][c] = XN[j][c];
+            load_plane(P + 1);
+            {
+                const int sl = t & 1;
 #pragma unroll
-                    for (int j = 0; j < NI; ++j) {
-                        if (j * NT + tid < R0) {
-                            sA1[sl][0][o1[j]] = X[j][u][0];
-                            sA1[sl][1][o1[j]] = X[j][u][1];
-                            sA1[sl][2][o1[j]] = X[j][u][2];
-                        }
+                for (int j = 0; j < NI; ++j) {
+                    if (LLL_ITEM_LANE_IN(j, R0)) {
+                        sA1[sl][0][o1[j]] = X[j][u][0];
+                        sA1[sl][1][o1[j]] = X[j][u][1];
+                        sA1[sl][2][o1[j]] = X[j][u][2];
                     }
                 }
-                // ---- stage 1 on plane P-1 (region R1)
-                if (t >= 2) {
-                    const int sl = (t - 1) & 1;
-                    const T* Lxp = sA1[sl][0];
-                    const T* Lyp = sA1[sl][1];
-                    const T* Lzp = sA1[sl][2];
+            }
+            // ---- stage 1 on plane P-1 (region R1); k1, y2 = x + k1/2, acc = x + k1/6
+            {
+                const int sl = (t - 1) & 1;
 #pragma unroll
-                    for (int j = 0; j < NI; ++j) {
-                        if (j * NT >= R1) continue;
-                        if (j * NT + tid < R1) {
-                            const int o = o1[j];
-                            const T nx = (Lxp[o - 1] + Lxp[o + 1]) + (Lxp[o - W0] + Lxp[o + W0]) +
-                                         (X[j][u2][0] + X[j][u][0]);
-                            const T ny = (Lyp[o - 1] + Lyp[o + 1]) + (Lyp[o - W0] + Lyp[o + W0]) +
-                                         (X[j][u2][1] + X[j][u][1]);
-                            const T nz = (Lzp[o - 1] + Lzp[o + 1]) + (Lzp[o - W0] + Lzp[o + W0]) +
-                                         (X[j][u2][2] + X[j][u][2]);
-                            T Di, ex, ey, ez;
-                            site_aniso(j, P - 1, Di, ex, ey, ez);
-                            T kx, ky, kz;
-                            stage_k<T, PREC, ANIS>(X[j][u1][0], X[j][u1][1], X[j][u1][2], nx, ny, nz,
-                                                   C, Di, ex, ey, ez, kx, ky, kz);
-                            Y2[j][u1][0] = kx * c2 + X[j][u1][0];
-                            Y2[j][u1][1] = ky * c2 + X[j][u1][1];
-                            Y2[j][u1][2] = kz * c2 + X[j][u1][2];
+                for (int j = 0; j < NI; ++j) {
+                    if (j * NT >= R1) continue;
+                    if (LLL_ITEM_WAVE_IN(j, R1)) {
+                        T Di, ex, ey, ez, kx, ky, kz;
+                        site_aniso(j, P - 1, Di, ex, ey, ez);
+                        stage_at<T, PREC, ANIS, W0>(sA1[sl][0], sA1[sl][1], sA1[sl][2], r1[j], X[j][u1],
+                                                    X[j][u2], X[j][u], C, Di, ex, ey, ez, kx, ky, kz);
+                        Y2[j][u1][0] = kx * c2 + X[j][u1][0];
+                        Y2[j][u1][1] = ky * c2 + X[j][u1][1];
+                        Y2[j][u1][2] = kz * c2 + X[j][u1][2];
+                        if (j * NT < R4) {
+                            A[j][u1][0] = kx * c6 + X[j][u1][0];
+                            A[j][u1][1] = ky * c6 + X[j][u1][1];
+                            A[j][u1][2] = kz * c6 + X[j][u1][2];
+                        }
+                        if (LLL_ITEM_LANE_IN(j, R1)) {
                             sA2[sl][0][o2[j]] = Y2[j][u1][0];
                             sA2[sl][1][o2[j]] = Y2[j][u1][1];
                             sA2[sl][2][o2[j]] = Y2[j][u1][2];
-                            if (j * NT < R4) {
-                                A[j][u1][0] = kx * c6 + X[j][u1][0];
-                                A[j][u1][1] = ky * c6 + X[j][u1][1];
-                                A[j][u1][2] = kz * c6 + X[j][u1][2];
-                            }
                         }
                     }
                 }
-                // ---- stage 2 on plane P-2 (region R2)
-                if (t >= 4) {
-                    const int sl = (t - 2) & 1;
-                    const T* Lxp = sA2[sl][0];
-                    const T* Lyp = sA2[sl][1];
-                    const T* Lzp = sA2[sl][2];
+            }
+            // ---- stage 2 on plane P-2 (region R2); y3 = x + k2/2, acc += k2/3
+            {
+                const int sl = (t - 2) & 1;
 #pragma unroll
-                    for (int j = 0; j < NI; ++j) {
-                        if (j * NT >= R2) continue;
-                        if (j * NT + tid < R2) {
-                            const int o = o2[j];
-                            const T nx = (Lxp[o - 1] + Lxp[o + 1]) + (Lxp[o - W1] + Lxp[o + W1]) +
-                                         (Y2[j][u3][0] + Y2[j][u1][0]);
-                            const T ny = (Lyp[o - 1] + Lyp[o + 1]) + (Lyp[o - W1] + Lyp[o + W1]) +
-                                         (Y2[j][u3][1] + Y2[j][u1][1]);
-                            const T nz = (Lzp[o - 1] + Lzp[o + 1]) + (Lzp[o - W1] + Lzp[o + W1]) +
-                                         (Y2[j][u3][2] + Y2[j][u1][2]);
-                            T Di, ex, ey, ez;
-                            site_aniso(j, P - 2, Di, ex, ey, ez);
-                            T kx, ky, kz;
-                            stage_k<T, PREC, ANIS>(Y2[j][u2][0], Y2[j][u2][1], Y2[j][u2][2], nx, ny,
-                                                   nz, C, Di, ex, ey, ez, kx, ky, kz);
-                            Y3[j][u2][0] = kx * c2 + X[j][u2][0];
-                            Y3[j][u2][1] = ky * c2 + X[j][u2][1];
-                            Y3[j][u2][2] = kz * c2 + X[j][u2][2];
+                for (int j = 0; j < NI; ++j) {
+                    if (j * NT >= R2) continue;
+                    if (LLL_ITEM_WAVE_IN(j, R2)) {
+                        T Di, ex, ey, ez, kx, ky, kz;
+                        site_aniso(j, P - 2, Di, ex, ey, ez);
+                        stage_at<T, PREC, ANIS, W1>(sA2[sl][0], sA2[sl][1], sA2[sl][2], r2[j], Y2[j][u2],
+                                                    Y2[j][u3], Y2[j][u1], C, Di, ex, ey, ez, kx, ky, kz);
+                        Y3[j][u2][0] = kx * c2 + X[j][u2][0];
+                        Y3[j][u2][1] = ky * c2 + X[j][u2][1];
+                        Y3[j][u2][2] = kz * c2 + X[j][u2][2];
+                        if (j * NT < R4) {
+                            A[j][u2][0] = kx * c3 + A[j][u2][0];
+                            A[j][u2][1] = ky * c3 + A[j][u2][1];
+                            A[j][u2][2] = kz * c3 + A[j][u2][2];
+                        }
+                        if (LLL_ITEM_LANE_IN(j, R2)) {
                             sA3[sl][0][o3[j]] = Y3[j][u2][0];
                             sA3[sl][1][o3[j]] = Y3[j][u2][1];
                             sA3[sl][2][o3[j]] = Y3[j][u2][2];
-                            if (j * NT < R4) {
-                                A[j][u2][0] = kx * c3 + A[j][u2][0];
-                                A[j][u2][1] = ky * c3 + A[j][u2][1];
-                                A[j][u2][2] = kz * c3 + A[j][u2][2];
-                            }
                         }
                     }
                 }
-                // ---- stage 3 on plane P-3 (region R3)
-                if (t >= 6) {
-                    const int sl = (t - 3) & 1;
-                    const T* Lxp = sA3[sl][0];
-                    const T* Lyp = sA3[sl][1];
-                    const T* Lzp = sA3[sl][2];
+            }
+            // ---- stage 3 on plane P-3 (region R3); y4 = x + k3, acc += k3/3
+            {
+                const int sl = (t - 3) & 1;
 #pragma unroll
-                    for (int j = 0; j < NI; ++j) {
-                        if (j * NT >= R3) continue;
-                        if (j * NT + tid < R3) {
-                            const int o = o3[j];
-                            const T nx = (Lxp[o - 1] + Lxp[o + 1]) + (Lxp[o - W2] + Lxp[o + W2]) +
-                                         (Y3[j][u][0] + Y3[j][u2][0]);
-                            const T ny = (Lyp[o - 1] + Lyp[o + 1]) + (Lyp[o - W2] + Lyp[o + W2]) +
-                                         (Y3[j][u][1] + Y3[j][u2][1]);
-                            const T nz = (Lzp[o - 1] + Lzp[o + 1]) + (Lzp[o - W2] + Lzp[o + W2]) +
-                                         (Y3[j][u][2] + Y3[j][u2][2]);
-                            T Di, ex, ey, ez;
-                            site_aniso(j, P - 3, Di, ex, ey, ez);
-                            T kx, ky, kz;
-                            stage_k<T, PREC, ANIS>(Y3[j][u3][0], Y3[j][u3][1], Y3[j][u3][2], nx, ny,
-                                                   nz, C, Di, ex, ey, ez, kx, ky, kz);
-                            Y4[j][u3][0] = kx + X[j][u3][0];
-                            Y4[j][u3][1] = ky + X[j][u3][1];
-                            Y4[j][u3][2] = kz + X[j][u3][2];
+                for (int j = 0; j < NI; ++j) {
+                    if (j * NT >= R3) continue;
+                    if (LLL_ITEM_WAVE_IN(j, R3)) {
+                        T Di, ex, ey, ez, kx, ky, kz;
+                        site_aniso(j, P - 3, Di, ex, ey, ez);
+                        stage_at<T, PREC, ANIS, W2>(sA3[sl][0], sA3[sl][1], sA3[sl][2], r3[j], Y3[j][u3],
+                                                    Y3[j][u], Y3[j][u2], C, Di, ex, ey, ez, kx, ky, kz);
+                        Y4[j][u3][0] = kx + X[j][u3][0];
+                        Y4[j][u3][1] = ky + X[j][u3][1];
+                        Y4[j][u3][2] = kz + X[j][u3][2];
+                        if (j * NT < R4) {
+                            A[j][u3][0] = kx * c3 + A[j][u3][0];
+                            A[j][u3][1] = ky * c3 + A[j][u3][1];
+                            A[j][u3][2] = kz * c3 + A[j][u3][2];
+                        }
+                        if (LLL_ITEM_LANE_IN(j, R3)) {
                             sA4[sl][0][o4[j]] = Y4[j][u3][0];
                             sA4[sl][1][o4[j]] = Y4[j][u3][1];
                             sA4[sl][2][o4[j]] = Y4[j][u3][2];
-                            if (j * NT < R4) {
-                                A[j][u3][0] = kx * c3 + A[j][u3][0];
-                                A[j][u3][1] = ky * c3 + A[j][u3][1];
-                                A[j][u3][2] = kz * c3 + A[j][u3][2];
-                            }
                         }
                     }
                 }
-                // ---- stage 4 on plane P-4 (core), store
-                if (t >= 8) {
-                    const int sl = (t - 4) & 1;
-                    const T* Lxp = sA4[sl][0];
-                    const T* Lyp = sA4[sl][1];
-                    const T* Lzp = sA4[sl][2];
-                    const int gz = P - 4;
-#pragma unroll
-                    for (int j = 0; j < NI; ++j) {
-                        if (j * NT >= R4) continue;
-                        if (j * NT + tid < R4) {
-                            const int o = o4[j];
-                            const T nx = (Lxp[o - 1] + Lxp[o + 1]) + (Lxp[o - W3] + Lxp[o + W3]) +
-                                         (Y4[j][u1][0] + Y4[j][u3][0]);
-                            const T ny = (Lyp[o - 1] + Lyp[o + 1]) + (Lyp[o - W3] + Lyp[o + W3]) +
-                                         (Y4[j][u1][1] + Y4[j][u3][1]);
-                            const T nz = (Lzp[o - 1] + Lzp[o + 1]) + (Lzp[o - W3] + Lzp[o + W3]) +
-                                         (Y4[j][u1][2] + Y4[j][u3][2]);
-                            T Di, ex, ey, ez;
-                            site_aniso(j, gz, Di, ex, ey, ez);
-                            T kx, ky, kz;
-                            stage_k<T, PREC, ANIS>(Y4[j][u][0], Y4[j][u][1], Y4[j][u][2], nx, ny, nz,
-                                                   C, Di, ex, ey, ez, kx, ky, kz);
-                            T rx = kx * c6 + A[j][u][0];
-                            T ry = ky * c6 + A[j][u][1];
-                            T rz = kz * c6 + A[j][u][2];
-                            if (outok[j]) {
-                                const int64_t g = (int64_t)col[j] + plane * gz;
-                                if constexpr (KICK) {
-                                    const uint4 w =
-                                        philox_site(R.seed, (uint32_t)g, (uint32_t)kpulse, R.rid, 0u);
-                                    const double d = kick_spin<T>(rx, ry, rz, w, sg);
-                                    kmax = (d > kmax || d != d) ? d : kmax;
-                                }
-                                ox[g] = rx;
-                                oy[g] = ry;
-                                oz[g] = rz;
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
             }
+            // ---- stage 4 on plane P-4 (core): x' = acc + k4/6, optional kick, store
+            {
+                const int sl = (t - 4) & 1;
+                const int gz = P - 4;
+                const bool zst = gz >= z0 && gz < zend;
+#pragma unroll
+                for (int j = 0; j < NI; ++j) {
+                    if (j * NT >= R4) continue;
+                    if (LLL_ITEM_WAVE_IN(j, R4)) {
+                        T Di, ex, ey, ez, kx, ky, kz;
+                        site_aniso(j, gz, Di, ex, ey, ez);
+                        stage_at<T, PREC, ANIS, W3>(sA4[sl][0], sA4[sl][1], sA4[sl][2], r4[j], Y4[j][u],
+                                                    Y4[j][u1], Y4[j][u3], C, Di, ex, ey, ez, kx, ky, kz);
+                        T rx = kx * c6 + A[j][u][0];
+                        T ry = ky * c6 + A[j][u][1];
+                        T rz = kz * c6 + A[j][u][2];
+                        if (zst && outok[j]) {
+                            const int64_t g = (int64_t)col[j] + plane * gz;
+                            if constexpr (KICK) {
+                                const uint4 w =
+                                    philox_site(R.seed, (uint32_t)g, (uint32_t)kpulse, R.rid, 0u);
+                                const double d = kick_spin<T>(rx, ry, rz, w, sg);
+                                kmax = (d > kmax || d != d) ? d : kmax;
+                            }
+                            ox[g] = rx;
+                            oy[g] = ry;
+                            oz[g] = rz;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
         }
     }
+#undef LLL_ITEM_WAVE_IN
+#undef LLL_ITEM_LANE_IN
     if constexpr (KICK) {
         // block max of the renormalisation deviation, one integer atomic per block
+        // (NT need not be a power of two: fold the top NT - P2 entries first)
+        constexpr int P2 = (NT >= 512) ? 512 : (NT >= 256) ? 256 : (NT >= 128) ? 128 : 64;
+        static_assert(NT >= 64 && NT <= 1024 && NT % 64 == 0, "threads per block");
         __shared__ double red[NT];
         red[tid] = kmax;
         __syncthreads();
-        for (int o = NT / 2; o > 0; o >>= 1) {
+        if (P2 < NT && tid < NT - P2) {
+            const double a = red[tid], b = red[tid + P2];
+            red[tid] = (b > a || b != b) ? b : a;
+        }
+        __syncthreads();
+        for (int o = P2 / 2; o > 0; o >>= 1) {
             if (tid < o) {
                 const double a = red[tid], b = red[tid + o];
                 red[tid] = (b > a || b != b) ? b : a;

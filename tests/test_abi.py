@@ -125,7 +125,7 @@ def test_variant_table(P):
             info = P.step_variant_info(prec, v)
             es = 8 if prec == "fp64" else 4
             bx, by = info["bx"], info["by"]
-            r = sum((bx + 2 * q) * (by + 2 * q) for q in range(1, 5))
+            r = sum(((bx + 2 * q) | 1) * (by + 2 * q) for q in range(1, 5))
             assert info["lds_bytes"] == 6 * es * r
             assert info["lds_bytes"] <= 160 * 1024
             assert info["threads"] % 64 == 0 and info["threads"] <= 1024

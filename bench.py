@@ -105,6 +105,7 @@ def extra_batched(n_pulses: int = 500):
     from tests import inputs
     reps = inputs.batch_replicas(seed=0)
     B = P.Batch([dict(r, J=1.0) for r in reps], precision="fp32", dt=0.1, Dt=1.0)
+    B.autotune(cache_path=TUNE_CACHE)
     B.run(first_pulse=0, n_pulses=10)  # capture + warm-up
     B.run(first_pulse=0, n_pulses=10)
     el_b, tr_b = _timed(lambda: B.run(first_pulse=10, n_pulses=n_pulses, obs_every=1))

@@ -206,6 +206,10 @@ lll_status lll_batch_observables(lll_batch* b, lll_obs* out_host /* [n_rep] */);
 lll_status lll_batch_state(lll_batch* b, int32_t rep, void** sx, void** sy, void** sz);
 /* FP64 running sums of every replica since creation: out_host[8*n_rep] as in lll_accumulators. */
 lll_status lll_batch_accumulators(lll_batch* b, double* out_host, int32_t reset);
+/* As lll_autotune, for the step kernel that advances all replicas together
+ * (one tile shape for every replica); the states are restored. */
+lll_status lll_batch_autotune(lll_batch* b, const char* cache_path, int32_t* chosen_variant,
+                              int32_t* chosen_bz);
 void lll_batch_destroy(lll_batch* b);
 
 /* ---------------------------------------------------------------- misc --- */

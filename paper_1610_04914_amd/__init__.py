@@ -103,6 +103,7 @@ def lib():
     L.lll_batch_observables.argtypes = [_P, C.POINTER(lll_obs)]
     L.lll_batch_state.argtypes = [_P, C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P)]
     L.lll_batch_accumulators.argtypes = [_P, C.POINTER(C.c_double), C.c_int32]
+    L.lll_batch_autotune.argtypes = [_P, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.lll_batch_destroy.argtypes = [_P]
     L.lll_batch_destroy.restype = None
     L.lll_philox4x32_10.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32, C.c_uint32,
@@ -457,6 +458,12 @@ class Batch:
         for c, p in enumerate((px, py, pz)):
             _hip_check(hipMemcpy(C.c_void_p(out[c].data_ptr()), p, C.c_size_t(N * es), 3))
         return out
+
+    def autotune(self, cache_path: Optional[str] = None):
+        v, b = C.c_int32(), C.c_int32()
+        _check(lib().lll_batch_autotune(self.h, cache_path.encode() if cache_path else None,
+                                        C.byref(v), C.byref(b)))
+        return v.value, b.value
 
     def accumulators(self, reset: bool = False):
         a = (C.c_double * (8 * self.n))()

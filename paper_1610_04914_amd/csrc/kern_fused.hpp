@@ -55,6 +55,55 @@ __host__ __device__ inline void ring_decode(int idx, int& lx, int& ly) {
     }
 }
 
+// Assignment of ring chunks to waves.  Workgroup waves are dealt to the four
+// SIMDs round-robin; the core waves evaluate all four stages, while a ring
+// chunk (64 consecutive ring points) evaluates between zero and three.  When
+// one point per thread covers the whole load region, the ring chunks are
+// handed to waves greedily (costliest chunk to the least loaded SIMD) so the
+// SIMDs carry equal work.
+template <int BX, int BY, int NT>
+struct WavePlan {
+    static constexpr int R4 = BX * BY;
+    static constexpr int R3 = (BX + 2) * (BY + 2);
+    static constexpr int R2 = (BX + 4) * (BY + 4);
+    static constexpr int R1 = (BX + 6) * (BY + 6);
+    static constexpr int R0 = (BX + 8) * (BY + 8);
+    static constexpr int NW = NT / 64;
+    static constexpr int NC = R4 / 64;
+    static constexpr bool ON = (R4 % 64 == 0) && (NT >= R0) && (NW > NC);
+    int chunk[16];
+    static constexpr int cost(int c) {
+        const int first = R4 + 64 * c;
+        return (first < R1 ? 1 : 0) + (first < R2 ? 1 : 0) + (first < R3 ? 1 : 0);
+    }
+    constexpr WavePlan() : chunk{} {
+        if (!ON) return;
+        int load[4] = {0, 0, 0, 0};
+        for (int w = 0; w < NC; ++w) load[w % 4] += 4;
+        const int nring = NW - NC;
+        bool used[16] = {};
+        bool taken[16] = {};
+        for (int pass = 0; pass < nring; ++pass) {
+            int bc = -1, bcost = -1;
+            for (int c = 0; c < nring; ++c)
+                if (!used[c] && cost(c) > bcost) {
+                    bcost = cost(c);
+                    bc = c;
+                }
+            int bk = -1, bload = 1 << 30;
+            for (int k = 0; k < nring; ++k)
+                if (!taken[k] && load[(NC + k) % 4] < bload) {
+                    bload = load[(NC + k) % 4];
+                    bk = k;
+                }
+            used[bc] = true;
+            taken[bk] = true;
+            chunk[bk] = bc;
+            load[(NC + bk) % 4] += bcost;
+        }
+    }
+};
+
 // k of one stage at a point whose own values on the planes below/at/above
 // are zm, c, zp, with the four in-plane neighbours read from the LDS plane
 // (L0, L1, L2) of frame width W at offset o.
@@ -120,13 +169,30 @@ __global__ void __launch_bounds__(NT)
     // Per point: LDS offsets of its own value in frames A1..A4 (written by the
     // stage that produces it), read offsets (its own offset inside the stage's
     // region, else a harmless interior point), global column, flags.
+    // pidx: point index of this thread's item j; pfirst: lowest point index of
+    // the wave's item j (wave-uniform).
+    using Plan = WavePlan<BX, BY, NT>;
+    constexpr Plan plan{};
+    int pidx[NI], pfirst[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+        pidx[j] = j * NT + tid;
+        pfirst[j] = j * NT + wbase;
+    }
+    if constexpr (Plan::ON) {
+        const int wave = wbase >> 6;
+        if (wave >= Plan::NC) {
+            pfirst[0] = R4 + 64 * plan.chunk[wave - Plan::NC];
+            pidx[0] = pfirst[0] + (tid & 63);
+        }
+    }
     int o1[NI], o2[NI], o3[NI], o4[NI];
     int r1[NI], r2[NI], r3[NI], r4[NI];
     int col[NI];
     bool colok[NI], outok[NI];
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
-        const int idx = j * NT + tid;
+        const int idx = pidx[j];
         int lx = 0, ly = 0;
         if (idx < R0) ring_decode<BX, BY>(idx, lx, ly);
         o1[j] = (ly + 4) * W0 + (lx + 4);
@@ -209,8 +275,8 @@ __global__ void __launch_bounds__(NT)
 
     // Item j's points cover stage region Rs entirely (compile time), or this
     // wave holds at least one of its points (wave-uniform).
-#define LLL_ITEM_WAVE_IN(j, Rs) (((j) + 1) * NT <= (Rs) || ((j) * NT + wbase) < (Rs))
-#define LLL_ITEM_LANE_IN(j, Rs) (((j) + 1) * NT <= (Rs) || ((j) * NT + tid) < (Rs))
+#define LLL_ITEM_WAVE_IN(j, Rs) (((j) + 1) * NT <= (Rs) || pfirst[j] < (Rs))
+#define LLL_ITEM_LANE_IN(j, Rs) (((j) + 1) * NT <= (Rs) || pidx[j] < (Rs))
 
     load_plane(z0 - 4);
 
@@ -220,12 +286,14 @@ __global__ void __launch_bounds__(NT)
             const int t = t0 + u;
             const int P = z0 - 4 + t;
             const int u1 = (u + 3) & 3, u2 = (u + 2) & 3, u3 = (u + 1) & 3;  // planes P-1, P-2, P-3
-            // ---- commit x(P), prefetch x(P+1)
+            // ---- commit x(P) (loaded one plane ago) to registers and LDS, then
+            // issue the loads of x(P+1); the scheduling barrier keeps the new
+            // loads behind the LDS stores, so the stores wait only for the
+            // previous plane's loads and the new ones stay in flight.
 #pragma unroll
             for (int j = 0; j < NI; ++j)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) X[j][u][c] = XN[j][c];
-            load_plane(P + 1);
             {
                 const int sl = t & 1;
 #pragma unroll
@@ -237,6 +305,8 @@ __global__ void __launch_bounds__(NT)
                     }
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
+            load_plane(P + 1);
             // ---- stage 1 on plane P-1 (region R1); k1, y2 = x + k1/2, acc = x + k1/6
             {
                 const int sl = (t - 1) & 1;

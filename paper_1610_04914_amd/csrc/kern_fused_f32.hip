@@ -9,9 +9,9 @@ struct VariantDesc {
 // Output tile (bx, by) and threads per workgroup.  LDS bytes = 6 * sizeof(T) *
 // sum over s = 0..3 of ((bx + 2(4-s)) | 1) (by + 2(4-s)) (double-buffered x, y,
 // z planes of the four stage inputs, rows padded to an odd pitch).
-static const VariantDesc kVar32[] = {{32, 16, 512}, {32, 16, 960}, {16, 16, 576}, {32, 8, 640},
-                                     {64, 8, 512}, {32, 32, 1024}};
-static const VariantDesc kVar64[] = {{16, 16, 256}, {16, 16, 576}, {32, 8, 640}, {32, 8, 256},
+static const VariantDesc kVar32[] = {{32, 16, 960}, {32, 16, 512}, {16, 16, 576}, {32, 8, 640},
+                                     {64, 8, 512}, {32, 16, 1024}};
+static const VariantDesc kVar64[] = {{32, 8, 640}, {16, 16, 576}, {16, 16, 256}, {32, 8, 256},
                                      {16, 8, 384}};
 
 static int lds_bytes(int bx, int by, int es) {
@@ -48,12 +48,12 @@ hipError_t launch_step_fused(int prec, int precession, int anis, int variant, in
         return launch_step_fused_f64(precession, anis, variant, bz, reps, tiles, ntiles, in, out,
                                      kick, k, so, kd, st);
     switch (variant) {
-        case 1: return launch_p<float, 32, 16, 512>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
-        case 2: return launch_p<float, 32, 16, 960>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+        case 1: return launch_p<float, 32, 16, 960>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+        case 2: return launch_p<float, 32, 16, 512>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
         case 3: return launch_p<float, 16, 16, 576>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
         case 4: return launch_p<float, 32, 8, 640>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
         case 5: return launch_p<float, 64, 8, 512>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
-        case 6: return launch_p<float, 32, 32, 1024>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+        case 6: return launch_p<float, 32, 16, 1024>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -154,15 +154,23 @@ lll_status lll_accumulators(lll_lattice* lat, double* out_host, int32_t reset);
  * lll_step_variant_info; bz = z-chunk of the fused kernel (0 = automatic). */
 lll_status lll_set_step_config(lll_lattice* lat, int32_t variant, int32_t bz);
 lll_status lll_get_step_config(lll_lattice* lat, int32_t* variant, int32_t* bz);
+/* Where the pulse-noise kick runs when the fused step is used: fused != 0 as
+ * the epilogue of the step that precedes it (default), else as a launch of its
+ * own.  Results are identical; only the timing differs.  No effect on the
+ * unfused step. */
+lll_status lll_set_kick_fusion(lll_lattice* lat, int32_t fused);
 /* Tile shape of a variant for a precision: out[0..3] = {bx, by, threads, lds_bytes};
  * LLL_EINVAL past the last variant. */
 lll_status lll_step_variant_info(lll_precision prec, int32_t variant, int32_t* out4);
 
 /* Times every step configuration on this lattice (RK4 steps with params,
- * restoring the state afterwards) and selects the fastest.  cache_path
- * (optional) is a text file of "key variant bz" lines that is read first and
- * updated; the key is the shape, precision, boundary, precession and
- * anisotropy mode.  *chosen_variant and *chosen_bz may be NULL. */
+ * restoring the state afterwards) and selects the fastest, then the faster
+ * kick placement (lll_set_kick_fusion) over whole noise intervals.  The state
+ * and the kick-deviation maximum are restored.  cache_path (optional) is a
+ * text file of "key variant bz kick_fused" lines (a missing fourth field means
+ * fused) that is read first and updated; the key is the shape, precision,
+ * boundary, precession and anisotropy mode.  *chosen_variant and *chosen_bz
+ * may be NULL. */
 lll_status lll_autotune(lll_lattice* lat, const lll_params* params, const char* cache_path,
                         int32_t* chosen_variant, int32_t* chosen_bz);
 

@@ -90,6 +90,7 @@ def lib():
     L.lll_accumulators.argtypes = [_P, C.POINTER(C.c_double), C.c_int32]
     L.lll_set_step_config.argtypes = [_P, C.c_int32, C.c_int32]
     L.lll_get_step_config.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.lll_set_kick_fusion.argtypes = [_P, C.c_int32]
     L.lll_step_variant_info.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     L.lll_autotune.argtypes = [_P, pp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.lll_adjoint.argtypes = [_P, pp, C.c_uint64, C.c_int64, C.c_int32, C.c_double,
@@ -283,6 +284,10 @@ class Lattice:
 
     def set_step_config(self, variant: int, bz: int = 0):
         _check(lib().lll_set_step_config(self.h, variant, bz))
+
+    def set_kick_fusion(self, fused: bool):
+        """Kick as the fused step's epilogue (True) or as its own launch."""
+        _check(lib().lll_set_kick_fusion(self.h, 1 if fused else 0))
 
     def step_config(self):
         v, b = C.c_int32(), C.c_int32()

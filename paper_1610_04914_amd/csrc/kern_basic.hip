@@ -94,9 +94,10 @@ hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int
 }
 
 // ------------------------------------------------------------------ kick ---
-// Block-wide max of a non-negative double, then one integer atomic on its bit
-// pattern (order-independent, so deterministic; a NaN compares above all).
-__device__ __forceinline__ void block_max_to(double v, unsigned long long* dst) {
+// Block-wide max of a non-negative double (a NaN compares above all) into
+// part[blockIdx.x]; kickmax_reduce folds the parts of every replica into its
+// running maximum (one writer per replica, no atomics).
+__device__ __forceinline__ void block_max_part(double v, double* part) {
     __shared__ double red[kSiteBlock];
     red[threadIdx.x] = v;
     __syncthreads();
@@ -107,13 +108,50 @@ __device__ __forceinline__ void block_max_to(double v, unsigned long long* dst) 
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(dst, (unsigned long long)__double_as_longlong(red[0]));
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Block r: maximum over the parts of replica r (its per-site blocks, or its
+// fused-step tiles in tile order) folded into kickdev[r].
+__global__ void __launch_bounds__(256)
+    kickmax_reduce(const RepDev* reps, const double* part, int by_tiles,
+                   unsigned long long* kickdev) {
+    const RepDev& R = reps[blockIdx.x];
+    const int p0 = by_tiles ? R.tile0 : R.sb0;
+    const int np = by_tiles ? R.tx * R.ty * R.tz : R.nsb;
+    double m = 0.0;
+    for (int q = threadIdx.x; q < np; q += 256) {
+        const double d = part[p0 + q];
+        m = (d > m || d != d) ? d : m;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double a = red[threadIdx.x], b = red[threadIdx.x + o];
+            red[threadIdx.x] = (b > a || b != b) ? b : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double old = __longlong_as_double((long long)kickdev[blockIdx.x]);
+        const double nw = red[0];
+        if (nw > old || nw != nw) kickdev[blockIdx.x] = (unsigned long long)__double_as_longlong(nw);
+    }
+}
+
+hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part, int by_tiles,
+                                 unsigned long long* kickdev, hipStream_t st) {
+    if (nrep <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kickmax_reduce, dim3(nrep), dim3(256), 0, st, reps, part, by_tiles, kickdev);
+    return hipGetLastError();
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kSiteBlock)
     kick_kernel(const RepDev* reps, const int32_t* blk_rep, State s, uint64_t k,
-                double sigma_override, unsigned long long* kickdev) {
+                double sigma_override, double* kickpart) {
     SiteCtx c;
     const bool live = site_of_thread(reps, blk_rep, c);
     double dev = 0.0;
@@ -130,20 +168,22 @@ __global__ void __launch_bounds__(kSiteBlock)
         py[c.gi] = y;
         pz[c.gi] = z;
     }
-    block_max_to(dev, kickdev + blk_rep[blockIdx.x]);
+    block_max_part(dev, kickpart);
 }
 
-hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
-                       uint64_t k, double sigma_override, unsigned long long* kickdev,
-                       hipStream_t st) {
+hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, int nrep,
+                       State s, uint64_t k, double sigma_override, double* kickpart,
+                       unsigned long long* kickdev, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
     if (prec == 0)
         hipLaunchKernelGGL(kick_kernel<double>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
-                           s, k, sigma_override, kickdev);
+                           s, k, sigma_override, kickpart);
     else
         hipLaunchKernelGGL(kick_kernel<float>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
-                           s, k, sigma_override, kickdev);
-    return hipGetLastError();
+                           s, k, sigma_override, kickpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_kickmax_reduce(reps, nrep, kickpart, 0, kickdev, st);
 }
 
 // ----------------------------------------------------------- observables ---

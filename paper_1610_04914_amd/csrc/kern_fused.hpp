@@ -121,7 +121,7 @@ template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, bool KICK>
 __global__ void __launch_bounds__(NT)
     rk4_fused_kernel(const RepDev* __restrict__ reps, const int4* __restrict__ tiles, State in,
                      State out, int bz_arg, uint64_t kpulse, double sigma_override,
-                     unsigned long long* kickdev) {
+                     double* kickpart) {
     // Region Rs = the tile grown by 4-s sites in x and y (R0: loaded points).
     constexpr int R0 = (BX + 8) * (BY + 8);
     constexpr int R1 = (BX + 6) * (BY + 6);
@@ -444,13 +444,13 @@ __global__ void __launch_bounds__(NT)
             }
             __syncthreads();
         }
-        if (tid == 0) atomicMax(kickdev + tl.x, (unsigned long long)__double_as_longlong(red[0]));
+        if (tid == 0) kickpart[R.tile0 + tl.y + R.tx * (tl.z + R.ty * tl.w)] = red[0];
     }
 }
 
 template <typename T, int BX, int BY, int NT, bool PREC, int ANIS>
 inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, State in, State out,
-                           int bz, int kick, uint64_t k, double so, unsigned long long* kd,
+                           int bz, int kick, uint64_t k, double so, double* kd,
                            hipStream_t st) {
     if (kick)
         hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, true>), dim3(ntiles), dim3(NT),
@@ -464,7 +464,7 @@ inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, St
 template <typename T, int BX, int BY, int NT, bool PREC>
 inline hipError_t launch_a(int anis, const RepDev* reps, const int4* tiles, int ntiles, State in,
                            State out, int bz, int kick, uint64_t k, double so,
-                           unsigned long long* kd, hipStream_t st) {
+                           double* kd, hipStream_t st) {
     switch (anis) {
         case ANIS_NONE: return launch_v<T, BX, BY, NT, PREC, ANIS_NONE>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
         case ANIS_Z: return launch_v<T, BX, BY, NT, PREC, ANIS_Z>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
@@ -476,7 +476,7 @@ inline hipError_t launch_a(int anis, const RepDev* reps, const int4* tiles, int 
 template <typename T, int BX, int BY, int NT>
 inline hipError_t launch_p(int precession, int anis, const RepDev* reps, const int4* tiles,
                            int ntiles, State in, State out, int bz, int kick, uint64_t k,
-                           double so, unsigned long long* kd, hipStream_t st) {
+                           double so, double* kd, hipStream_t st) {
     if (precession)
         return launch_a<T, BX, BY, NT, true>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
     return launch_a<T, BX, BY, NT, false>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);

@@ -37,12 +37,12 @@ bool fused_variant_info(int prec, int variant, FusedInfo* out) {
 
 hipError_t launch_step_fused_f64(int precession, int anis, int variant, int bz, const RepDev* reps,
                                  const int4* tiles, int ntiles, State in, State out, int kick,
-                                 uint64_t k, double so, unsigned long long* kd, hipStream_t st);
+                                 uint64_t k, double so, double* kd, hipStream_t st);
 
 hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz,
                              const RepDev* reps, const int4* tiles, int ntiles, State in,
                              State out, int kick, uint64_t k, double so,
-                             unsigned long long* kd, hipStream_t st) {
+                             double* kd, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     if (prec == 0)
         return launch_step_fused_f64(precession, anis, variant, bz, reps, tiles, ntiles, in, out,

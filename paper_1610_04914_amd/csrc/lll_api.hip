@@ -71,6 +71,9 @@ struct Engine {
     double* d_result = nullptr;   // [nrep][8]
     double* d_accum = nullptr;    // [nrep][8]
     unsigned long long* d_kickdev = nullptr;  // [nrep]
+    double* d_kickpart = nullptr;  // per-block / per-tile maxima of the kick deviation
+    int kickpart_cap = 0;
+    bool kick_epilogue = true;     // kick as the fused step's epilogue (else its own launch)
     double* d_trace = nullptr;
     size_t trace_cap = 0;         // doubles
     int variant = 0, bz = 0;      // step configuration (0 = unfused)
@@ -90,10 +93,10 @@ struct Engine {
         fr(yB.x); fr(yB.y); fr(yB.z);
         fr(acc.x); fr(acc.y); fr(acc.z);
         fr(dreps); fr(d_blk_rep); fr(d_oblk_rep); fr(d_tiles); fr(d_partials); fr(d_result);
-        fr(d_accum); fr(d_kickdev); fr(d_trace);
+        fr(d_accum); fr(d_kickdev); fr(d_trace); fr(d_kickpart);
         s = alt = yA = yB = acc = State{};
         dreps = nullptr; d_blk_rep = d_oblk_rep = nullptr; d_tiles = nullptr;
-        d_partials = d_result = d_accum = d_trace = nullptr; d_kickdev = nullptr;
+        d_partials = d_result = d_accum = d_trace = d_kickpart = nullptr; d_kickdev = nullptr;
     }
 };
 
@@ -141,6 +144,8 @@ lll_status build_tables(Engine& E) {
     HIP_TRY(hipMalloc(&E.d_kickdev, sizeof(unsigned long long) * E.nrep));
     HIP_TRY(hipMemset(E.d_kickdev, 0, sizeof(unsigned long long) * E.nrep));
     HIP_TRY(hipMalloc(&E.dreps, sizeof(RepDev) * E.nrep));
+    HIP_TRY(hipMalloc(&E.d_kickpart, sizeof(double) * E.nblk));
+    E.kickpart_cap = E.nblk;
     return LLL_OK;
 }
 
@@ -294,6 +299,13 @@ lll_status ensure_tiles(Engine& E) {
     }
     HIP_TRY(hipStreamSynchronize(E.st));
     HIP_TRY(hipMemcpy(E.d_tiles, ord.data(), sizeof(int4) * n, hipMemcpyHostToDevice));
+    if (n > E.kickpart_cap) {
+        if (E.d_kickpart) (void)hipFree(E.d_kickpart);
+        E.d_kickpart = nullptr;
+        E.kickpart_cap = 0;
+        HIP_TRY(hipMalloc(&E.d_kickpart, sizeof(double) * n));
+        E.kickpart_cap = n;
+    }
     E.ntiles = n;
     E.tiles_variant = E.variant;
     E.tiles_bz = E.bz;
@@ -314,28 +326,32 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
             HIP_TRY(launch_step_unfused(E.prec, E.precession, E.anis, E.dreps, E.d_blk_rep, E.nblk,
                                         cur_state(E), E.yA, E.yB, E.acc, E.st));
         if (kick_last)
-            HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k,
-                                sigma_override, E.d_kickdev, E.st));
+            HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, E.nrep, cur_state(E), k,
+                                sigma_override, E.d_kickpart, E.d_kickdev, E.st));
         return LLL_OK;
     }
     lll_status s = alloc_state(E, E.alt);
     if (s != LLL_OK) return s;
     if ((s = ensure_tiles(E)) != LLL_OK) return s;
     for (int64_t q = 0; q < n; ++q) {
-        const bool kk = kick_last && q == n - 1;
+        const bool kk = kick_last && q == n - 1 && E.kick_epilogue;
         State in = cur_state(E);
         State out = E.cur ? E.s : E.alt;
         HIP_TRY(launch_step_fused(E.prec, E.precession, E.anis, E.variant, eff_bz(E), E.dreps, E.d_tiles,
-                                  E.ntiles, in, out, kk ? 1 : 0, k, sigma_override, E.d_kickdev,
+                                  E.ntiles, in, out, kk ? 1 : 0, k, sigma_override, E.d_kickpart,
                                   E.st));
+        if (kk) HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, 1, E.d_kickdev, E.st));
         E.cur ^= 1;
     }
+    if (kick_last && !E.kick_epilogue)
+        HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, E.nrep, cur_state(E), k,
+                            sigma_override, E.d_kickpart, E.d_kickdev, E.st));
     return LLL_OK;
 }
 
 lll_status do_kick(Engine& E, uint64_t k, double sigma_override) {
-    HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k, sigma_override,
-                        E.d_kickdev, E.st));
+    HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, E.nrep, cur_state(E), k,
+                        sigma_override, E.d_kickpart, E.d_kickdev, E.st));
     return LLL_OK;
 }
 
@@ -663,6 +679,14 @@ extern "C" lll_status lll_set_step_config(lll_lattice* L, int32_t variant, int32
     return LLL_OK;
 }
 
+extern "C" lll_status lll_set_kick_fusion(lll_lattice* L, int32_t fused) {
+    if (!L) return set_err(LLL_EINVAL, "lattice is NULL");
+    lll_status s = settle(L->E);
+    if (s != LLL_OK) return s;
+    L->E.kick_epilogue = fused != 0;
+    return LLL_OK;
+}
+
 extern "C" lll_status lll_get_step_config(lll_lattice* L, int32_t* variant, int32_t* bz) {
     if (!L) return set_err(LLL_EINVAL, "lattice is NULL");
     if (variant) *variant = L->E.variant;
@@ -681,23 +705,27 @@ extern "C" lll_status lll_philox4x32_10(uint64_t seed, uint32_t i0, int64_t n, u
 
 // ------------------------------------------------------------- autotune ---
 // Times every step configuration (unfused, and each fused tile shape with
-// z-chunks of 4..64 planes) on the engine's own state and keeps the fastest;
-// the state is restored afterwards.  The optional cache file holds
-// "key variant bz" lines; a cached key is used without timing.
+// z-chunks of 4..64 planes) on the engine's own state and keeps the fastest,
+// then times whole noise intervals with the kick as the fused step's epilogue
+// and as a launch of its own (both give identical results).  The state and the
+// kick-deviation maxima are restored afterwards.  The optional cache file holds
+// "key variant bz kick_fused" lines; a cached key is used without timing.
 namespace {
-lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, const char* cache_path,
-                           int32_t* chosen_variant, int32_t* chosen_bz) {
+lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t n_interval,
+                           const char* cache_path, int32_t* chosen_variant, int32_t* chosen_bz) {
     lll_status s;
     if (cache_path) {
         FILE* f = fopen(cache_path, "r");
         if (f) {
-            char k[200];
-            int v, b;
+            char line[320], k[200];
+            int v, b, kf;
             bool found = false;
-            while (fscanf(f, "%199s %d %d", k, &v, &b) == 3) {
-                if (key == k && v >= 0 && v <= fused_variant_count(E.prec) && b >= 0) {
+            while (fgets(line, sizeof line, f)) {
+                const int got = sscanf(line, "%199s %d %d %d", k, &v, &b, &kf);
+                if (got >= 3 && key == k && v >= 0 && v <= fused_variant_count(E.prec) && b >= 0) {
                     E.variant = v;
                     E.bz = b;
+                    E.kick_epilogue = got < 4 || kf != 0;
                     found = true;
                 }
             }
@@ -713,6 +741,10 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, const c
     State save{};
     if ((s = alloc_state(E, save)) != LLL_OK) return s;
     HIP_TRY(launch_copy(E.prec, save, E.s, E.nsites, E.st));
+    std::vector<unsigned long long> kd_save(E.nrep);
+    HIP_TRY(hipMemcpyAsync(kd_save.data(), E.d_kickdev, sizeof(unsigned long long) * E.nrep,
+                           hipMemcpyDeviceToHost, E.st));
+    HIP_TRY(hipStreamSynchronize(E.st));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -750,11 +782,34 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, const c
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     E.variant = bv;
     E.bz = bb;
+    // kick placement: epilogue of the fused step, or its own launch (whole intervals timed)
+    bool bk = true;
+    if (s == LLL_OK && bv != 0 && E.anis != ANIS_SITE && n_interval >= 2) {
+        double tk[2] = {1e30, 1e30};
+        for (int trial = 0; trial < 2 && s == LLL_OK; ++trial)
+            for (int mode = 0; mode < 2 && s == LLL_OK; ++mode) {
+                E.kick_epilogue = mode == 1;
+                if ((s = do_interval(E, n_interval, 0, -1.0)) != LLL_OK) break;
+                HIP_TRY(hipEventRecord(e0, E.st));
+                for (int q = 0; q < 3 && s == LLL_OK; ++q) s = do_interval(E, n_interval, 1 + q, -1.0);
+                HIP_TRY(hipEventRecord(e1, E.st));
+                if (s == LLL_OK) s = settle(E);
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                tk[mode] = std::min(tk[mode], (double)ms);
+            }
+        bk = tk[1] <= tk[0];
+    }
+    E.kick_epilogue = bk;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     hipError_t ce = launch_copy(E.prec, E.s, save, E.nsites, E.st);
+    if (ce == hipSuccess)
+        ce = hipMemcpyAsync(E.d_kickdev, kd_save.data(), sizeof(unsigned long long) * E.nrep,
+                            hipMemcpyHostToDevice, E.st);
     (void)hipStreamSynchronize(E.st);
     (void)hipFree(save.x);
     (void)hipFree(save.y);
@@ -764,7 +819,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, const c
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s %d %d\n", key.c_str(), bv, bb);
+            fprintf(f, "%s %d %d %d\n", key.c_str(), bv, bb, bk ? 1 : 0);
             fclose(f);
         }
     }
@@ -782,7 +837,9 @@ extern "C" lll_status lll_autotune(lll_lattice* L, const lll_params* p, const ch
     char buf[200];
     snprintf(buf, sizeof buf, "L%dx%dx%d_bc%d_%s_prec%d_anis%d", L->Lx, L->Ly, L->Lz, L->bc,
              L->E.prec == 0 ? "fp64" : "fp32", L->E.precession, L->E.anis);
-    return engine_autotune(L->E, buf, L->Lz, cache_path, chosen_variant, chosen_bz);
+    int64_t n = 0;
+    if (steps_per_interval(L->dt, L->Dt, &n) != LLL_OK) n = 0;
+    return engine_autotune(L->E, buf, L->Lz, n, cache_path, chosen_variant, chosen_bz);
 }
 
 // ------------------------------------------------------------- adjoint ----
@@ -862,7 +919,8 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
                                       slot(0, 2), slot(0, 3), accb, nxt, E.st));
             std::swap(cur, nxt);
         } else {
-            HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, cur, opk[j], -1.0, E.d_kickdev, E.st));
+            HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, E.nrep, cur, opk[j], -1.0,
+                                E.d_kickpart, E.d_kickdev, E.st));
         }
     }
     // loss and its cotangent
@@ -883,8 +941,8 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
                                           slot(sl, 1), slot(sl, 2), slot(sl, 3), accb, nx, E.st));
             } else {
                 HIP_TRY(launch_copy(pr, nx, slot(sl, 0), E.nsites, E.st));
-                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, opk[j], -1.0,
-                                    E.d_kickdev, E.st));
+                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, E.nrep, nx, opk[j], -1.0,
+                                    E.d_kickpart, E.d_kickdev, E.st));
             }
         }
         for (int64_t j = j1 - 1; j >= j0; --j) {
@@ -1124,7 +1182,7 @@ extern "C" lll_status lll_batch_autotune(lll_batch* B, const char* cache_path,
     char buf[200];
     snprintf(buf, sizeof buf, "B%d_%lld_%016llx_%s_prec%d_anis%d", E.nrep, (long long)E.nsites,
              (unsigned long long)h, E.prec == 0 ? "fp64" : "fp32", E.precession, E.anis);
-    lll_status s = engine_autotune(E, buf, maxLz, cache_path, chosen_variant, chosen_bz);
+    lll_status s = engine_autotune(E, buf, maxLz, B->n, cache_path, chosen_variant, chosen_bz);
     if (B->gexec) {
         (void)hipGraphExecDestroy(B->gexec);
         B->gexec = nullptr;

@@ -39,63 +39,74 @@ __device__ __forceinline__ uint4 philox_site(uint64_t seed, uint32_t i, uint32_t
     return philox4x32_10(i, k, r, tag, (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32));
 }
 
-// Three unit normals by Box-Muller from one Philox block, u = (w + 1/2) 2^-32.
+// Three unit normals by Box-Muller from one Philox block, u = (w + 1/2) 2^-32:
+// G = (r0 cos 2pi u1, r0 sin 2pi u1, r1 cos 2pi u3), r = sqrt(-2 ln u).
 template <typename T>
 __device__ __forceinline__ void gauss3(uint4 w, T G[3]);
 
 template <>
 __device__ __forceinline__ void gauss3<double>(uint4 w, double G[3]) {
     const double s = 2.3283064365386963e-10;  // 2^-32
-    const double two_pi = 6.283185307179586;
     const double u0 = ((double)w.x + 0.5) * s;
-    const double u1 = ((double)w.y + 0.5) * s;
     const double u2 = ((double)w.z + 0.5) * s;
-    const double u3 = ((double)w.w + 0.5) * s;
     const double r0 = sqrt(-2.0 * log(u0));
     const double r1 = sqrt(-2.0 * log(u2));
+    // sin/cos(2 pi u) = sinpi/cospi(2u); 2u = (w + 1/2) 2^-31 exactly
+    const double a1 = ((double)w.y + 0.5) * 4.656612873077393e-10;
+    const double a3 = ((double)w.w + 0.5) * 4.656612873077393e-10;
     double sn, cs;
-    sincos(two_pi * u1, &sn, &cs);
+    sincospi(a1, &sn, &cs);
     G[0] = r0 * cs;
     G[1] = r0 * sn;
-    G[2] = r1 * cos(two_pi * u3);
+    G[2] = r1 * cospi(a3);
 }
 
-// -ln(u) in fp32 with full relative accuracy at both ends of (0,1): for
-// u >= 1/2 it is -log1p(-(1-u)) with 1-u = (~w + 1/2) 2^-32 formed exactly
-// from the complemented word.
+// -ln u in fp32 with full relative accuracy over all of (0,1) from one
+// hardware log2 (about 1 ulp on gfx950).  u < 1/2: -ln u = -log2(u) ln 2.
+// u >= 1/2: -ln u = -log1p(-v) with v = 1 - u formed exactly from the
+// complemented word, evaluated by Kahan's identity
+// log1p(x) = ln(1 + x) x / ((1 + x) - 1) (D. Goldberg, "What every computer
+// scientist should know about floating-point arithmetic", 1991), y = 1 - v.
 __device__ __forceinline__ float neglog_u01(uint32_t w) {
-    if (w < 0x80000000u) return -logf(((float)w + 0.5f) * 2.3283064365386963e-10f);
-    const uint32_t c = ~w;
-    return -log1pf(-(((float)c + 0.5f) * 2.3283064365386963e-10f));
+    const bool lo = w < 0x80000000u;
+    const float v = ((float)(lo ? w : ~w) + 0.5f) * 2.3283064365386963e-10f;  // u, or 1 - u
+    const float y = lo ? v : 1.0f - v;
+    const float L = __builtin_amdgcn_logf(y) * 0.6931471805599453f;            // ln y
+    const float hi = (y == 1.0f) ? v : L * v * __builtin_amdgcn_rcpf(y - 1.0f);
+    return lo ? -L : hi;
 }
 
 template <>
 __device__ __forceinline__ void gauss3<float>(uint4 w, float G[3]) {
-    const float r0 = sqrtf(2.0f * neglog_u01(w.x));
-    const float r1 = sqrtf(2.0f * neglog_u01(w.z));
-    // 2 u = (w + 1/2) 2^-31; sin/cos(pi * 2u) = sin/cos(2 pi u)
-    const float a1 = ((float)w.y + 0.5f) * 4.656612873077393e-10f;
-    const float a3 = ((float)w.w + 0.5f) * 4.656612873077393e-10f;
-    float sn, cs;
-    sincospif(a1, &sn, &cs);
-    G[0] = r0 * cs;
-    G[1] = r0 * sn;
-    G[2] = r1 * cospif(a3);
+    const float r0 = __builtin_amdgcn_sqrtf(2.0f * neglog_u01(w.x));
+    const float r1 = __builtin_amdgcn_sqrtf(2.0f * neglog_u01(w.z));
+    // hardware sin/cos take the angle in revolutions: sin(2 pi u)
+    const float u1 = ((float)w.y + 0.5f) * 2.3283064365386963e-10f;
+    const float u3 = ((float)w.w + 0.5f) * 2.3283064365386963e-10f;
+    G[0] = r0 * __builtin_amdgcn_cosf(u1);
+    G[1] = r0 * __builtin_amdgcn_sinf(u1);
+    G[2] = r1 * __builtin_amdgcn_cosf(u3);
 }
 
+// |phi|, 1/|phi| and sin/cos |phi| of the rotation angle.
 template <typename T>
-__device__ __forceinline__ T dsqrt(T v);
-template <>
-__device__ __forceinline__ double dsqrt<double>(double v) { return sqrt(v); }
-template <>
-__device__ __forceinline__ float dsqrt<float>(float v) { return sqrtf(v); }
+__device__ __forceinline__ void angle_of(T ph2, T& inv, T& sn, T& cs);
 
-template <typename T>
-__device__ __forceinline__ void dsincos(T a, T* s, T* c);
 template <>
-__device__ __forceinline__ void dsincos<double>(double a, double* s, double* c) { sincos(a, s, c); }
+__device__ __forceinline__ void angle_of<double>(double ph2, double& inv, double& sn, double& cs) {
+    const double ph = sqrt(ph2);
+    inv = 1.0 / ph;
+    sincospi(ph * 0.3183098861837907, &sn, &cs);  // sin/cos(pi * ph/pi)
+}
+
 template <>
-__device__ __forceinline__ void dsincos<float>(float a, float* s, float* c) { sincosf(a, s, c); }
+__device__ __forceinline__ void angle_of<float>(float ph2, float& inv, float& sn, float& cs) {
+    const float ph = __builtin_amdgcn_sqrtf(ph2);
+    inv = __builtin_amdgcn_rcpf(ph);
+    const float rev = __builtin_amdgcn_fractf(ph * 0.15915494309189535f);  // ph / 2pi, in [0,1)
+    sn = __builtin_amdgcn_sinf(rev);
+    cs = __builtin_amdgcn_cosf(rev);
+}
 
 // Kick of one spin: rotation by phi = sigma G about n = phi/|phi| (Eq. (6)),
 // identity when phi = 0, then renormalisation with the norm taken in fp64.
@@ -110,10 +121,9 @@ __device__ __forceinline__ double kick_spin(T& sx, T& sy, T& sz, uint4 w, T sigm
     const T ph2 = px * px + py * py + pz * pz;
     T ox = sx, oy = sy, oz = sz;
     if (ph2 > T(0)) {
-        const T ph = dsqrt<T>(ph2);
-        const T nx = px / ph, ny = py / ph, nz = pz / ph;
-        T sn, cs;
-        dsincos<T>(ph, &sn, &cs);
+        T inv, sn, cs;
+        angle_of<T>(ph2, inv, sn, cs);
+        const T nx = px * inv, ny = py * inv, nz = pz * inv;
         const T cx = ny * sz - nz * sy;  // n x s
         const T cy = nz * sx - nx * sz;
         const T cz = nx * sy - ny * sx;
@@ -125,9 +135,10 @@ __device__ __forceinline__ double kick_spin(T& sx, T& sy, T& sz, uint4 w, T sigm
     }
     const double dx = (double)ox, dy = (double)oy, dz = (double)oz;
     const double nrm = sqrt(dx * dx + dy * dy + dz * dz);
-    sx = (T)(dx / nrm);
-    sy = (T)(dy / nrm);
-    sz = (T)(dz / nrm);
+    const double inv = 1.0 / nrm;
+    sx = (T)(dx * inv);
+    sy = (T)(dy * inv);
+    sz = (T)(dz * inv);
     return fabs(nrm - 1.0);
 }
 

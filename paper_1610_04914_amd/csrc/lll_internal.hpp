@@ -44,9 +44,15 @@ hipError_t launch_philox_words(uint64_t seed, uint32_t i0, int64_t n, uint32_t c
 hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
                        int mode, double dx, double dy, double dz, hipStream_t st);
 // sigma_override >= 0 replaces every replica's kick scale (per-pulse temperature).
-hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
-                       uint64_t k, double sigma_override, unsigned long long* kickdev,
-                       hipStream_t st);
+// kickpart: scratch [nblk] of per-block maxima of | |s'| - 1 |, folded into
+// kickdev[replica] (fp64 bit patterns of running maxima).
+hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, int nrep,
+                       State s, uint64_t k, double sigma_override, double* kickpart,
+                       unsigned long long* kickdev, hipStream_t st);
+// Folds per-block maxima into kickdev: parts of replica r are its per-site
+// blocks (by_tiles = 0) or its fused-step tiles in tile order (by_tiles = 1).
+hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part, int by_tiles,
+                                 unsigned long long* kickdev, hipStream_t st);
 hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
                       int nobblk, int nrep, State s, double* partials, double* result,
                       double* accum, int accumulate, hipStream_t st);
@@ -62,12 +68,13 @@ struct FusedInfo {
 };
 int fused_variant_count(int prec);
 bool fused_variant_info(int prec, int variant, FusedInfo* out);
-// kick != 0: apply kick number k to the step's output (epilogue);
-// sigma_override >= 0 replaces every replica's kick scale.
+// kick != 0: apply kick number k to the step's output (epilogue), writing each
+// tile's maximum of | |s'| - 1 | to kickpart[tile0 + tile]; sigma_override >= 0
+// replaces every replica's kick scale.
 hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz,
                              const RepDev* reps, const int4* tiles, int ntiles, State in,
                              State out, int kick, uint64_t k, double sigma_override,
-                             unsigned long long* kickdev, hipStream_t st);
+                             double* kickpart, hipStream_t st);
 
 // RK4 step keeping the stage inputs y2, y3, y4 (per-stage launches).
 hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* reps,

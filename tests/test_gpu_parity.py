@@ -241,6 +241,17 @@ def test_schedule_identity_bitexact(P, prec):
         d.run(gp, first_pulse=20, n_pulses=3)
         torch.cuda.synchronize()
         assert torch.equal(a.state, d.state)
+        # kick as its own launch instead of the fused step's epilogue
+        e = P.Lattice(shape, precision=prec, seed=3)
+        e.set_step_config(v, 0)
+        e.set_kick_fusion(False)
+        e.run(gp, first_pulse=20, n_pulses=3)
+        a2 = P.Lattice(shape, precision=prec, seed=3)
+        a2.set_step_config(v, 0)
+        a2.run(gp, first_pulse=20, n_pulses=3)
+        torch.cuda.synchronize()
+        assert torch.equal(a.state, e.state), v
+        assert e.kick_norm_dev() == a2.kick_norm_dev(), v
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

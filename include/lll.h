@@ -159,6 +159,14 @@ lll_status lll_get_step_config(lll_lattice* lat, int32_t* variant, int32_t* bz);
  * own.  Results are identical; only the timing differs.  No effect on the
  * unfused step. */
 lll_status lll_set_kick_fusion(lll_lattice* lat, int32_t fused);
+/* Kernel timing of the fused RK4 step (launches without kick epilogue).
+ * enable != 0 starts a measurement: later launches record events taken from
+ * their own dispatch into a ring of 64 pairs (a pair still in flight is
+ * skipped, so the timed launches are a sample spread over the run).
+ * enable == 0 synchronises the lattice's stream, ends the measurement and
+ * returns the mean kernel duration *avg_ms over *n_timed launches (either
+ * pointer may be NULL; 0 launches gives 0.0). */
+lll_status lll_kernel_timing(lll_lattice* lat, int32_t enable, double* avg_ms, int64_t* n_timed);
 /* Tile shape of a variant for a precision: out[0..3] = {bx, by, threads, lds_bytes};
  * LLL_EINVAL past the last variant. */
 lll_status lll_step_variant_info(lll_precision prec, int32_t variant, int32_t* out4);

@@ -91,6 +91,7 @@ def lib():
     L.lll_set_step_config.argtypes = [_P, C.c_int32, C.c_int32]
     L.lll_get_step_config.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.lll_set_kick_fusion.argtypes = [_P, C.c_int32]
+    L.lll_kernel_timing.argtypes = [_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.lll_step_variant_info.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     L.lll_autotune.argtypes = [_P, pp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.lll_adjoint.argtypes = [_P, pp, C.c_uint64, C.c_int64, C.c_int32, C.c_double,
@@ -284,6 +285,16 @@ class Lattice:
 
     def set_step_config(self, variant: int, bz: int = 0):
         _check(lib().lll_set_step_config(self.h, variant, bz))
+
+    def kernel_timing_start(self):
+        """Start timing fused-step launches (events recorded by the dispatches)."""
+        _check(lib().lll_kernel_timing(self.h, 1, None, None))
+
+    def kernel_timing_stop(self):
+        """Synchronise and return (mean kernel ms, launches timed)."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().lll_kernel_timing(self.h, 0, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def set_kick_fusion(self, fused: bool):
         """Kick as the fused step's epilogue (True) or as its own launch."""

@@ -187,120 +187,157 @@ hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int
 }
 
 // ----------------------------------------------------------- observables ---
-// Pass 1: per-block fp64 partial sums {sum_bonds s_i.s_j, sum H.s, sum D (s.e)^2,
-// sum s (3), max | |s| - 1 |} in a fixed order; pass 2 sums the partials of
-// every replica in a fixed order.  No floating-point atomics: results are
-// bit-identical from run to run.
-template <typename T>
-__device__ __forceinline__ void load3(const State& s, int64_t g, double& x, double& y, double& z) {
-    x = (double)static_cast<const T*>(s.x)[g];
-    y = (double)static_cast<const T*>(s.y)[g];
-    z = (double)static_cast<const T*>(s.z)[g];
+// Pass 1: per-block fp64 partial sums {sum_bonds s_i.s_j, sum H.s,
+// sum D (s.e)^2, sum s (3), max | |s| - 1 |} in a fixed order; pass 2 sums
+// the partials of every replica in block order.  No floating-point atomics:
+// results are bit-identical from run to run.  (A single pass that lets the
+// last block finish would need a device-scope release per block, which
+// writes back the L2 of its XCD each time and costs far more than a launch.)  Each site owns its bonds to its +x, +y and
+// +z neighbours (Eq. (2) counts every bond once).
+__device__ __forceinline__ double nan_max(double a, double c) { return (c > a || c != c) ? c : a; }
+
+// Butterfly over the 64 lanes of a wavefront (fixed pairing, so the result
+// does not depend on timing); every lane ends with the wave's total.
+__device__ __forceinline__ void wave_reduce7(double q[7]) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) q[j] += __shfl_xor(q[j], o, 64);
+        q[6] = nan_max(q[6], __shfl_xor(q[6], o, 64));
+    }
+}
+
+// Sum of the 7 quantities over a block of NT threads into out[0..6] (thread 0).
+template <int NT>
+__device__ __forceinline__ void block_reduce7(double q[7], double* out) {
+    constexpr int NW = NT / 64;
+    __shared__ double red[NW][7];
+    wave_reduce7(q);
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+        for (int j = 0; j < 7; ++j) red[w][j] = q[j];
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        const int j = threadIdx.x;
+        double a = red[0][j];
+        for (int v = 1; v < NW; ++v) a = (j < 6) ? a + red[v][j] : nan_max(a, red[v][j]);
+        out[j] = a;
+    }
 }
 
 template <typename T, int ANIS>
 __global__ void __launch_bounds__(kObsBlock)
     obs_partial_kernel(const RepDev* reps, const int32_t* oblk_rep, State s, double* partials) {
+    // sites per thread and pass; their loads are issued together
+    constexpr int U = sizeof(T) == 4 ? 4 : 2;
     const int b = blockIdx.x;
     const int r = oblk_rep[b];
     const RepDev& R = reps[r];
     const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
-    const int64_t N = (int64_t)Lx * Ly * Lz;
-    const int lb = b - R.ob0, nb = R.nob;
+    const int64_t Lxy = (int64_t)Lx * Ly;
+    const int64_t N = Lxy * Lz;
     const bool pbc = R.bc == 0;
-    double q[6] = {0, 0, 0, 0, 0, 0};
-    double dev = 0.0;
-    for (int64_t i = (int64_t)lb * kObsBlock + threadIdx.x; i < N; i += (int64_t)nb * kObsBlock) {
-        const int x = (int)(i % Lx);
-        const int y = (int)((i / Lx) % Ly);
-        const int z = (int)(i / ((int64_t)Lx * Ly));
-        const int64_t g = R.off + i;
-        double sx, sy, sz;
-        load3<T>(s, g, sx, sy, sz);
-        double bx = 0, by = 0, bz = 0;
-        if (pbc || x + 1 < Lx) {
-            const int xn = (x + 1 == Lx) ? 0 : x + 1;
-            double tx, ty, tz;
-            load3<T>(s, R.off + xn + (int64_t)Lx * (y + (int64_t)Ly * z), tx, ty, tz);
-            bx += tx; by += ty; bz += tz;
+    const T* __restrict__ px = static_cast<const T*>(s.x) + R.off;
+    const T* __restrict__ py = static_cast<const T*>(s.y) + R.off;
+    const T* __restrict__ pz = static_cast<const T*>(s.z) + R.off;
+    const int64_t stride = (int64_t)R.nob * kObsBlock;
+    int64_t i = (int64_t)(b - R.ob0) * kObsBlock + threadIdx.x;
+    // coordinates of i; they advance by those of the stride with carries, so
+    // no division runs per site
+    int x = (int)(i % Lx), y = (int)((i / Lx) % Ly), z = (int)(i / Lxy);
+    const int dx = (int)(stride % Lx), dy = (int)((stride / Lx) % Ly), dz = (int)(stride / Lxy);
+    double q[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (; i < N; i += U * stride) {
+        // site and +x, +y, +z neighbour indices; every index is a valid site
+        // (lanes past the end read site 0, missing free-boundary bonds read a
+        // wrapped site), the flags drop what does not count
+        int64_t g[U];
+        int dn[U][3];
+        bool ok[U], hx[U], hy[U], hz[U];
+        int64_t ci = i;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            ok[k] = ci < N;
+            const int xx = ok[k] ? x : 0, yy = ok[k] ? y : 0, zz = ok[k] ? z : 0;
+            g[k] = ok[k] ? ci : 0;
+            dn[k][0] = xx + 1 < Lx ? 1 : 1 - Lx;
+            dn[k][1] = yy + 1 < Ly ? Lx : (int)(Lx - Lxy);
+            dn[k][2] = zz + 1 < Lz ? (int)Lxy : (int)(Lxy - N);
+            hx[k] = pbc || xx + 1 < Lx;
+            hy[k] = pbc || yy + 1 < Ly;
+            hz[k] = pbc || zz + 1 < Lz;
+            ci += stride;
+            x += dx;
+            if (x >= Lx) { x -= Lx; ++y; }
+            y += dy;
+            if (y >= Ly) { y -= Ly; ++z; }
+            z += dz;
         }
-        if (pbc || y + 1 < Ly) {
-            const int yn = (y + 1 == Ly) ? 0 : y + 1;
-            double tx, ty, tz;
-            load3<T>(s, R.off + x + (int64_t)Lx * (yn + (int64_t)Ly * z), tx, ty, tz);
-            bx += tx; by += ty; bz += tz;
+        T v[U][4][3];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int64_t c = g[k] + (m == 0 ? 0 : dn[k][m - 1]);
+                v[k][m][0] = px[c];
+                v[k][m][1] = py[c];
+                v[k][m][2] = pz[c];
+            }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (!ok[k]) continue;
+            const double sx = (double)v[k][0][0], sy = (double)v[k][0][1], sz = (double)v[k][0][2];
+            double bx = 0, by = 0, bz = 0;
+            if (hx[k]) { bx += (double)v[k][1][0]; by += (double)v[k][1][1]; bz += (double)v[k][1][2]; }
+            if (hy[k]) { bx += (double)v[k][2][0]; by += (double)v[k][2][1]; bz += (double)v[k][2][2]; }
+            if (hz[k]) { bx += (double)v[k][3][0]; by += (double)v[k][3][1]; bz += (double)v[k][3][2]; }
+            q[0] += sx * bx + sy * by + sz * bz;
+            q[1] += R.H[0] * sx + R.H[1] * sy + R.H[2] * sz;
+            if constexpr (ANIS == ANIS_Z) {
+                q[2] += R.D * sz * sz;
+            } else if constexpr (ANIS == ANIS_AXIS) {
+                const double se = sx * R.e[0] + sy * R.e[1] + sz * R.e[2];
+                q[2] += R.D * se * se;
+            } else if constexpr (ANIS == ANIS_SITE) {
+                const T* Ds = static_cast<const T*>(R.D_site);
+                const T* es = static_cast<const T*>(R.e_site);
+                const int64_t c = g[k];
+                const double se = sx * (double)es[c] + sy * (double)es[N + c] + sz * (double)es[2 * N + c];
+                q[2] += (double)Ds[c] * se * se;
+            }
+            q[3] += sx;
+            q[4] += sy;
+            q[5] += sz;
+            q[6] = nan_max(q[6], fabs(sqrt(sx * sx + sy * sy + sz * sz) - 1.0));
         }
-        if (pbc || z + 1 < Lz) {
-            const int zn = (z + 1 == Lz) ? 0 : z + 1;
-            double tx, ty, tz;
-            load3<T>(s, R.off + x + (int64_t)Lx * (y + (int64_t)Ly * zn), tx, ty, tz);
-            bx += tx; by += ty; bz += tz;
-        }
-        q[0] += sx * bx + sy * by + sz * bz;
-        q[1] += R.H[0] * sx + R.H[1] * sy + R.H[2] * sz;
-        if constexpr (ANIS == ANIS_Z) {
-            q[2] += R.D * sz * sz;
-        } else if constexpr (ANIS == ANIS_AXIS) {
-            const double se = sx * R.e[0] + sy * R.e[1] + sz * R.e[2];
-            q[2] += R.D * se * se;
-        } else if constexpr (ANIS == ANIS_SITE) {
-            const T* Ds = static_cast<const T*>(R.D_site);
-            const T* es = static_cast<const T*>(R.e_site);
-            const double se = sx * (double)es[i] + sy * (double)es[N + i] + sz * (double)es[2 * N + i];
-            q[2] += (double)Ds[i] * se * se;
-        }
-        q[3] += sx;
-        q[4] += sy;
-        q[5] += sz;
-        const double d = fabs(sqrt(sx * sx + sy * sy + sz * sz) - 1.0);
-        dev = (d > dev || d != d) ? d : dev;
     }
-    __shared__ double red[7][kObsBlock];
-    for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = q[j];
-    red[6][threadIdx.x] = dev;
-    __syncthreads();
-    for (int o = kObsBlock / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
-            const double a = red[6][threadIdx.x], c = red[6][threadIdx.x + o];
-            red[6][threadIdx.x] = (c > a || c != c) ? c : a;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < 7) partials[(int64_t)b * 8 + threadIdx.x] = red[threadIdx.x][0];
+    block_reduce7<kObsBlock>(q, partials + (int64_t)b * 8);
 }
 
-__global__ void __launch_bounds__(256)
+constexpr int kObsFinal = 256;
+
+// Sums the partials of replica blockIdx.x in block order.
+__global__ void __launch_bounds__(kObsFinal)
     obs_final_kernel(const RepDev* reps, const double* partials, double* result, double* accum,
                      int accumulate) {
     const int r = blockIdx.x;
     const RepDev& R = reps[r];
-    double q[6] = {0, 0, 0, 0, 0, 0};
-    double dev = 0.0;
-    for (int b = R.ob0 + threadIdx.x; b < R.ob0 + R.nob; b += 256) {
-        for (int j = 0; j < 6; ++j) q[j] += partials[(int64_t)b * 8 + j];
-        const double d = partials[(int64_t)b * 8 + 6];
-        dev = (d > dev || d != d) ? d : dev;
+    double q[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = R.ob0 + threadIdx.x; b < R.ob0 + R.nob; b += kObsFinal) {
+        const double* p = partials + (int64_t)b * 8;
+        for (int j = 0; j < 6; ++j) q[j] += p[j];
+        q[6] = nan_max(q[6], p[6]);
     }
-    __shared__ double red[7][256];
-    for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = q[j];
-    red[6][threadIdx.x] = dev;
+    __shared__ double tot[7];
+    block_reduce7<kObsFinal>(q, tot);
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
-            const double a = red[6][threadIdx.x], c = red[6][threadIdx.x + o];
-            red[6][threadIdx.x] = (c > a || c != c) ? c : a;
-        }
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
         const double N = (double)R.Lx * R.Ly * R.Lz;
-        const double Eex = -R.J * red[0][0];
-        const double Ez = -red[1][0];
-        const double Ea = -red[2][0];
+        const double Eex = -R.J * tot[0];
+        const double Ez = -tot[1];
+        const double Ea = -tot[2];
         const double Et = Eex + Ez + Ea;
-        const double mx = red[3][0] / N, my = red[4][0] / N, mz = red[5][0] / N;
+        const double mx = tot[3] / N, my = tot[4] / N, mz = tot[5] / N;
         double* o = result + (int64_t)r * 8;
         o[0] = Et;
         o[1] = Eex;
@@ -309,7 +346,7 @@ __global__ void __launch_bounds__(256)
         o[4] = mx;
         o[5] = my;
         o[6] = mz;
-        o[7] = red[6][0];
+        o[7] = tot[6];
         if (accumulate) {
             double* a = accum + (int64_t)r * 8;
             const double m2 = mx * mx + my * my + mz * mz;
@@ -358,8 +395,8 @@ hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* obl
         launch_obs_t<float>(anis, reps, oblk_rep, nobblk, s, partials, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(obs_final_kernel, dim3(nrep), dim3(256), 0, st, reps, partials, result,
-                       accum, accumulate);
+    hipLaunchKernelGGL(obs_final_kernel, dim3(nrep), dim3(kObsFinal), 0, st, reps, partials,
+                       result, accum, accumulate);
     return hipGetLastError();
 }
 

@@ -14,6 +14,10 @@
 // one partial wave per stage.  With the kick flag, the pulse-noise kick of
 // Eqs. (5)-(6) is applied to the output before it is stored.
 #pragma once
+#include <hip/hip_ext.h>
+
+#include <type_traits>
+
 #include "lll_device.hpp"
 
 namespace lll {
@@ -182,7 +186,13 @@ __global__ void __launch_bounds__(NT)
     if constexpr (Plan::ON) {
         const int wave = wbase >> 6;
         if (wave >= Plan::NC) {
-            pfirst[0] = R4 + 64 * plan.chunk[wave - Plan::NC];
+            // select by compile-time index: a run-time index into the plan
+            // would place the whole table in per-lane private memory
+            int ch = 0;
+#pragma unroll
+            for (int q = 0; q < Plan::NW - Plan::NC; ++q)
+                if (wave - Plan::NC == q) ch = plan.chunk[q];
+            pfirst[0] = R4 + 64 * ch;
             pidx[0] = pfirst[0] + (tid & 63);
         }
     }
@@ -278,9 +288,12 @@ __global__ void __launch_bounds__(NT)
 #define LLL_ITEM_WAVE_IN(j, Rs) (((j) + 1) * NT <= (Rs) || pfirst[j] < (Rs))
 #define LLL_ITEM_LANE_IN(j, Rs) (((j) + 1) * NT <= (Rs) || pidx[j] < (Rs))
 
-    load_plane(z0 - 4);
-
-    for (int t0 = 0; t0 < niter4; t0 += 4) {
+    // Four planes per block (FIFO slots are then compile-time).  F = 0, 1:
+    // iterations 0-3 and 4-7, where stage s runs only from iteration 2s on (its
+    // input planes exist from then; earlier results would never be used);
+    // F = 2: the steady state, all four stages every iteration.
+    auto plane_block = [&](const int t0, auto Fc) {
+        constexpr int F = decltype(Fc)::value;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int t = t0 + u;
@@ -308,7 +321,7 @@ __global__ void __launch_bounds__(NT)
             __builtin_amdgcn_sched_barrier(0);
             load_plane(P + 1);
             // ---- stage 1 on plane P-1 (region R1); k1, y2 = x + k1/2, acc = x + k1/6
-            {
+            if (F == 2 || 4 * F + u >= 2 * 1) {
                 const int sl = (t - 1) & 1;
 #pragma unroll
                 for (int j = 0; j < NI; ++j) {
@@ -335,7 +348,7 @@ __global__ void __launch_bounds__(NT)
                 }
             }
             // ---- stage 2 on plane P-2 (region R2); y3 = x + k2/2, acc += k2/3
-            {
+            if (F == 2 || 4 * F + u >= 2 * 2) {
                 const int sl = (t - 2) & 1;
 #pragma unroll
                 for (int j = 0; j < NI; ++j) {
@@ -362,7 +375,7 @@ __global__ void __launch_bounds__(NT)
                 }
             }
             // ---- stage 3 on plane P-3 (region R3); y4 = x + k3, acc += k3/3
-            {
+            if (F == 2 || 4 * F + u >= 2 * 3) {
                 const int sl = (t - 3) & 1;
 #pragma unroll
                 for (int j = 0; j < NI; ++j) {
@@ -389,7 +402,7 @@ __global__ void __launch_bounds__(NT)
                 }
             }
             // ---- stage 4 on plane P-4 (core): x' = acc + k4/6, optional kick, store
-            {
+            if (F == 2 || 4 * F + u >= 2 * 4) {
                 const int sl = (t - 4) & 1;
                 const int gz = P - 4;
                 const bool zst = gz >= z0 && gz < zend;
@@ -421,7 +434,12 @@ __global__ void __launch_bounds__(NT)
             }
             __syncthreads();
         }
-    }
+    };
+
+    load_plane(z0 - 4);
+    plane_block(0, std::integral_constant<int, 0>{});
+    plane_block(4, std::integral_constant<int, 1>{});
+    for (int t0 = 8; t0 < niter4; t0 += 4) plane_block(t0, std::integral_constant<int, 2>{});
 #undef LLL_ITEM_WAVE_IN
 #undef LLL_ITEM_LANE_IN
     if constexpr (KICK) {
@@ -451,10 +469,14 @@ __global__ void __launch_bounds__(NT)
 template <typename T, int BX, int BY, int NT, bool PREC, int ANIS>
 inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, State in, State out,
                            int bz, int kick, uint64_t k, double so, double* kd,
-                           hipStream_t st) {
+                           const LaunchEvents* ev, hipStream_t st) {
     if (kick)
         hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, true>), dim3(ntiles), dim3(NT),
                            0, st, reps, tiles, in, out, bz, k, so, kd);
+    else if (ev)  // start/stop events taken from the dispatch itself
+        hipExtLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false>), dim3(ntiles),
+                              dim3(NT), 0, st, ev->start, ev->stop, 0, reps, tiles, in, out, bz, k,
+                              so, kd);
     else
         hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false>), dim3(ntiles),
                            dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd);
@@ -464,11 +486,11 @@ inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, St
 template <typename T, int BX, int BY, int NT, bool PREC>
 inline hipError_t launch_a(int anis, const RepDev* reps, const int4* tiles, int ntiles, State in,
                            State out, int bz, int kick, uint64_t k, double so,
-                           double* kd, hipStream_t st) {
+                           double* kd, const LaunchEvents* ev, hipStream_t st) {
     switch (anis) {
-        case ANIS_NONE: return launch_v<T, BX, BY, NT, PREC, ANIS_NONE>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
-        case ANIS_Z: return launch_v<T, BX, BY, NT, PREC, ANIS_Z>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
-        case ANIS_AXIS: return launch_v<T, BX, BY, NT, PREC, ANIS_AXIS>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+        case ANIS_NONE: return launch_v<T, BX, BY, NT, PREC, ANIS_NONE>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+        case ANIS_Z: return launch_v<T, BX, BY, NT, PREC, ANIS_Z>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+        case ANIS_AXIS: return launch_v<T, BX, BY, NT, PREC, ANIS_AXIS>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
         default: return hipErrorInvalidValue;  // per-site anisotropy runs on the unfused step
     }
 }
@@ -476,10 +498,10 @@ inline hipError_t launch_a(int anis, const RepDev* reps, const int4* tiles, int 
 template <typename T, int BX, int BY, int NT>
 inline hipError_t launch_p(int precession, int anis, const RepDev* reps, const int4* tiles,
                            int ntiles, State in, State out, int bz, int kick, uint64_t k,
-                           double so, double* kd, hipStream_t st) {
+                           double so, double* kd, const LaunchEvents* ev, hipStream_t st) {
     if (precession)
-        return launch_a<T, BX, BY, NT, true>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
-    return launch_a<T, BX, BY, NT, false>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, st);
+        return launch_a<T, BX, BY, NT, true>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+    return launch_a<T, BX, BY, NT, false>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
 }
 
 }  // namespace lll

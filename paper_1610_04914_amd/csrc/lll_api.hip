@@ -78,8 +78,23 @@ struct Engine {
     size_t trace_cap = 0;         // doubles
     int variant = 0, bz = 0;      // step configuration (0 = unfused)
     int cur = 0;                  // 0: state in s, 1: state in alt
+    // kernel timing of fused steps without kick: a ring of event pairs that the
+    // launches record themselves; a pair still in flight is skipped, so the
+    // timed launches are a sample spread over the run
+    bool kt_on = false;
+    std::vector<LaunchEvents> kt_ev;
+    std::vector<char> kt_busy;
+    size_t kt_next = 0;
+    double kt_ms = 0;
+    int64_t kt_n = 0;
 
-    ~Engine() { release(); }
+    ~Engine() {
+        release();
+        for (auto& e : kt_ev) {
+            (void)hipEventDestroy(e.start);
+            (void)hipEventDestroy(e.stop);
+        }
+    }
 
     void release() {
         auto fr = [](void* p) {
@@ -317,6 +332,26 @@ State cur_state(Engine& E) { return E.cur ? E.alt : E.s; }
 
 // n RK4 steps; when kick_last, kick k is applied right after the last step
 // (as the fused kernel's epilogue, or as a separate launch).
+void kt_harvest(Engine& E, size_t j) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, E.kt_ev[j].start, E.kt_ev[j].stop) == hipSuccess) {
+        E.kt_ms += ms;
+        E.kt_n += 1;
+    }
+    E.kt_busy[j] = 0;
+}
+
+const LaunchEvents* kt_take(Engine& E) {
+    if (!E.kt_on || E.kt_ev.empty()) return nullptr;
+    const size_t j = E.kt_next++ % E.kt_ev.size();
+    if (E.kt_busy[j]) {
+        if (hipEventQuery(E.kt_ev[j].stop) != hipSuccess) return nullptr;
+        kt_harvest(E, j);
+    }
+    E.kt_busy[j] = 1;
+    return &E.kt_ev[j];
+}
+
 lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sigma_override) {
     if (n <= 0) return LLL_OK;
     if (E.variant == 0 || E.anis == ANIS_SITE) {
@@ -339,7 +374,7 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
         State out = E.cur ? E.s : E.alt;
         HIP_TRY(launch_step_fused(E.prec, E.precession, E.anis, E.variant, eff_bz(E), E.dreps, E.d_tiles,
                                   E.ntiles, in, out, kk ? 1 : 0, k, sigma_override, E.d_kickpart,
-                                  E.st));
+                                  kk ? nullptr : kt_take(E), E.st));
         if (kk) HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, 1, E.d_kickdev, E.st));
         E.cur ^= 1;
     }
@@ -684,6 +719,36 @@ extern "C" lll_status lll_set_kick_fusion(lll_lattice* L, int32_t fused) {
     lll_status s = settle(L->E);
     if (s != LLL_OK) return s;
     L->E.kick_epilogue = fused != 0;
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_kernel_timing(lll_lattice* L, int32_t enable, double* avg_ms,
+                                        int64_t* n_timed) {
+    if (!L) return set_err(LLL_EINVAL, "lattice is NULL");
+    Engine& E = L->E;
+    if (enable) {
+        if (E.kt_ev.empty()) {
+            E.kt_ev.resize(64);
+            E.kt_busy.assign(64, 0);
+            for (auto& e : E.kt_ev) {
+                e.start = e.stop = nullptr;
+                HIP_TRY(hipEventCreate(&e.start));
+                HIP_TRY(hipEventCreate(&e.stop));
+            }
+        }
+        for (size_t j = 0; j < E.kt_ev.size(); ++j) E.kt_busy[j] = 0;
+        E.kt_ms = 0;
+        E.kt_n = 0;
+        E.kt_next = 0;
+        E.kt_on = true;
+        return LLL_OK;
+    }
+    HIP_TRY(hipStreamSynchronize(E.st));
+    for (size_t j = 0; j < E.kt_ev.size(); ++j)
+        if (E.kt_busy[j]) kt_harvest(E, j);
+    E.kt_on = false;
+    if (avg_ms) *avg_ms = E.kt_n > 0 ? E.kt_ms / (double)E.kt_n : 0.0;
+    if (n_timed) *n_timed = E.kt_n;
     return LLL_OK;
 }
 

@@ -53,6 +53,8 @@ hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int
 // blocks (by_tiles = 0) or its fused-step tiles in tile order (by_tiles = 1).
 hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part, int by_tiles,
                                  unsigned long long* kickdev, hipStream_t st);
+// Observables of every replica into result[r][8] (and accum when accumulate);
+// partials: [nobblk][8] scratch.
 hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
                       int nobblk, int nrep, State s, double* partials, double* result,
                       double* accum, int accumulate, hipStream_t st);
@@ -68,13 +70,18 @@ struct FusedInfo {
 };
 int fused_variant_count(int prec);
 bool fused_variant_info(int prec, int variant, FusedInfo* out);
+// Event pair that a launch records at its own start and end (kernel timing).
+struct LaunchEvents {
+    hipEvent_t start, stop;
+};
 // kick != 0: apply kick number k to the step's output (epilogue), writing each
 // tile's maximum of | |s'| - 1 | to kickpart[tile0 + tile]; sigma_override >= 0
-// replaces every replica's kick scale.
+// replaces every replica's kick scale.  ev (optional, steps without kick only)
+// times the launch.
 hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz,
                              const RepDev* reps, const int4* tiles, int ntiles, State in,
                              State out, int kick, uint64_t k, double sigma_override,
-                             double* kickpart, hipStream_t st);
+                             double* kickpart, const LaunchEvents* ev, hipStream_t st);
 
 // RK4 step keeping the stage inputs y2, y3, y4 (per-stage launches).
 hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* reps,

@@ -94,60 +94,103 @@ def _timed(fn):
     return time.perf_counter() - t0, r
 
 
-def extra_batched(n_pulses: int = 500):
+def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn: int = 1000):
     """Uneven-replica workload: 32 each of 24^3, 48^3, 64^3, T uniform in
     [0.3, 2], lambda log-uniform in [0.005, 0.05], J = 1, H = 0, dt = 0.1,
-    Dt = 1.0, random-sphere starts.  fp32 batch (one graph per run) vs the
-    plain fp64 single-lattice path on the same replicas one after another;
-    accuracy compared through each replica's time average of E/N."""
+    Dt = 1.0, random-sphere starts, per-replica noise keys.
+
+    Throughput (random starts): the fp32 batch (one graph per run) over n_pulses, and the plain
+    fp64 single-lattice path on the same replicas one after another over n_seq
+    pulses (each lattice keyed with its replica's seed and index, so it draws
+    the same noise as the batch).  Accuracy: fp32 and fp64 batches from the
+    same start and noise over n_acc pulses; per replica, the time averages of
+    E/N and |m| after `burn` pulses are compared against their combined
+    standard errors (from each series' integrated autocorrelation time); the
+    signed mean of the differences over replicas shows any fp32 bias.  The fp64 batch follows the fp64 single-lattice
+    path's trajectory (same keys, same arithmetic).  The accuracy runs start
+    ordered along +z so that the series are stationary after the burn-in."""
     import numpy as np
     import paper_1610_04914_amd as P
     from tests import inputs
     reps = inputs.batch_replicas(seed=0)
-    B = P.Batch([dict(r, J=1.0) for r in reps], precision="fp32", dt=0.1, Dt=1.0)
+    descs = [dict(r, J=1.0) for r in reps]
+    sites = sum(int(np.prod(r["L"])) for r in reps)
+    B = P.Batch(descs, precision="fp32", dt=0.1, Dt=1.0)
     B.autotune(cache_path=TUNE_CACHE)
     B.run(first_pulse=0, n_pulses=10)  # capture + warm-up
     B.run(first_pulse=0, n_pulses=10)
-    el_b, tr_b = _timed(lambda: B.run(first_pulse=10, n_pulses=n_pulses, obs_every=1))
-    sites = sum(int(np.prod(r["L"])) for r in reps)
-    spin_steps = sites * 10 * n_pulses
-    Eb = np.array([[tr_b[m][r]["E_total"] for m in range(n_pulses)] for r in range(len(reps))])
+    el_b, _ = _timed(lambda: B.run(first_pulse=10, n_pulses=n_pulses, obs_every=1))
     B.close()
 
-    # fp64 single lattices started from the same replica states (the batch keys
-    # each random sphere by (seed, replica); a lone lattice uses replica 0)
-    B0 = P.Batch([dict(r, J=1.0) for r in reps], precision="fp64", dt=0.1, Dt=1.0)
+    B0 = P.Batch(descs, precision="fp64", dt=0.1, Dt=1.0)
     lats = []
     for i, r in enumerate(reps):
         lat = P.Lattice(r["L"], precision="fp64", state=B0.state(i))
-        lats.append((lat, P.Params(J=1.0, lam=r["lam"], T=r["T"], dt=0.1, Dt=1.0, seed=r["seed"])))
+        lats.append((lat, P.Params(J=1.0, lam=r["lam"], T=r["T"], dt=0.1, Dt=1.0, seed=r["seed"],
+                                   replica=r["replica"])))
     B0.close()
     for lat, p in lats:
-        lat.run(p, first_pulse=0, n_pulses=10)
+        lat.run(p, first_pulse=0, n_pulses=2)
 
     def run_seq():
-        return [lat.run(p, first_pulse=10, n_pulses=n_pulses, obs_every=1) for lat, p in lats]
-    el_s, tr_s = _timed(run_seq)
-    Es = np.array([[t["E_total"] for t in tr] for tr in tr_s])
-    N = np.array([float(np.prod(r["L"])) for r in reps])
-    burn = n_pulses // 5
-    mb, ms = Eb[:, burn:].mean(1) / N, Es[:, burn:].mean(1) / N
-
-    def sem(x):
-        nb = 10
-        x = x[: len(x) // nb * nb].reshape(nb, -1).mean(1)
-        return x.std(ddof=1) / np.sqrt(nb)
-    sb = np.array([sem(Eb[r, burn:] / N[r]) for r in range(len(reps))])
-    ss = np.array([sem(Es[r, burn:] / N[r]) for r in range(len(reps))])
-    z = np.abs(mb - ms) / np.sqrt(sb**2 + ss**2)
+        return [lat.run(p, first_pulse=2, n_pulses=n_seq, obs_every=1) for lat, p in lats]
+    el_s, _ = _timed(run_seq)
     for lat, _ in lats:
         lat.close()
+
+    def series(prec):
+        # ordered starts (+z): below T_c a random start keeps coarsening far
+        # beyond the run, so time averages would not be stationary
+        A = P.Batch([dict(d, init="direction") for d in descs], precision=prec, dt=0.1, Dt=1.0)
+        tr = A.run(first_pulse=0, n_pulses=n_acc, obs_every=1)
+        A.close()
+        e = np.array([[tr[m][r]["E_total"] for m in range(n_acc)] for r in range(len(reps))])
+        mag = np.array([[np.linalg.norm(tr[m][r]["m"]) for m in range(n_acc)]
+                        for r in range(len(reps))])
+        N = np.array([float(np.prod(r["L"])) for r in reps])
+        return e / N[:, None], mag
+
+    def mean_sem(x):
+        """Mean after burn-in and its standard error from the integrated
+        autocorrelation time (automatic window: the first M >= 5 tau(M))."""
+        x = x[:, burn:]
+        n = x.shape[1]
+        means, sems = x.mean(1), np.zeros(x.shape[0])
+        for r in range(x.shape[0]):
+            d = x[r] - means[r]
+            f = np.fft.rfft(d, 2 * n)
+            acf = np.fft.irfft(f * np.conj(f))[:n]
+            if acf[0] <= 0:
+                continue
+            rho = acf / acf[0]
+            tau = 0.5
+            for M in range(1, n):
+                tau += rho[M]
+                if M >= 5 * tau:
+                    break
+            sems[r] = np.sqrt(acf[0] / n * 2 * max(tau, 0.5) / n)
+        return means, sems
+
+    e32, m32 = series("fp32")
+    e64, m64 = series("fp64")
+    zs = {}
+    for name, a, b in (("E_per_site", e32, e64), ("abs_m", m32, m64)):
+        ma, sa = mean_sem(a)
+        mb, sb = mean_sem(b)
+        zs[name] = (ma - mb) / np.sqrt(sa**2 + sb**2 + 1e-300)
+    rate_b = sites * 10 * n_pulses / el_b
+    rate_s = sites * 10 * n_seq / el_s
     return {"workload": "96 replicas (32 x 24^3, 48^3, 64^3), fp32 batch vs fp64 single-lattice path",
-            "batched_fp32_spin_steps_per_s": spin_steps / el_b,
-            "sequential_fp64_spin_steps_per_s": spin_steps / el_s,
-            "speedup": el_s / el_b,
-            "replicas_within_2sigma": int(np.sum(z < 2.0)), "replicas": len(reps),
-            "max_z": float(z.max()), "pulses": n_pulses}
+            "batched_fp32_spin_steps_per_s": rate_b,
+            "sequential_fp64_spin_steps_per_s": rate_s,
+            "speedup": rate_b / rate_s,
+            "pulses_timed": {"batch": n_pulses, "sequential": n_seq},
+            "accuracy": {"pulses": n_acc, "burn_in": burn, "replicas": len(reps),
+                         **{k: {"within_2sigma": int(np.sum(np.abs(z) < 2.0)),
+                                "within_3sigma": int(np.sum(np.abs(z) < 3.0)),
+                                "mean_signed_z": float(z.mean()),
+                                "max_abs_z": float(np.abs(z).max())}
+                            for k, z in zs.items()}}}
 
 
 def extra_adjoint():

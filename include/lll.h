@@ -88,6 +88,9 @@ typedef struct {
     int32_t precession;   /* 1: full Eq. (1); 0: slow equation (precession dropped) */
     int32_t integrator;   /* LLL_RK4 */
     uint64_t seed;        /* Philox key of the kicks */
+    uint32_t replica;     /* Philox counter word 2 of the kicks: 0 for a lone lattice; set it to
+                             a batch replica's index to draw that replica's noise */
+    int32_t reserved;     /* set to 0 */
 } lll_params;
 
 /* Observables of one state, fp64. */

@@ -43,6 +43,7 @@ class lll_params(C.Structure):
         ("D_site", C.c_void_p), ("e_site", C.c_void_p),
         ("lambda_", C.c_double), ("T", C.c_double), ("dt", C.c_double), ("Dt", C.c_double),
         ("precession", C.c_int32), ("integrator", C.c_int32), ("seed", C.c_uint64),
+        ("replica", C.c_uint32), ("reserved", C.c_int32),
     ]
 
 
@@ -199,6 +200,7 @@ class Params:
     Dt: float = 1.0
     precession: bool = True
     seed: int = 0
+    replica: int = 0                  # Philox counter word 2 of the kicks (batch replica index)
     D_site: Optional[object] = None   # device tensor [N] of the lattice dtype
     e_site: Optional[object] = None   # device tensor [3, N] of the lattice dtype
 
@@ -217,6 +219,8 @@ class Params:
         p.precession = 1 if self.precession else 0
         p.integrator = 0
         p.seed = int(self.seed)
+        p.replica = int(self.replica)
+        p.reserved = 0
         return p
 
 

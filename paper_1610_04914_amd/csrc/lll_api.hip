@@ -454,6 +454,7 @@ struct lll_lattice {
     double dt = 0, Dt = 0;
     int precession = 1;
     uint64_t seed = 0;
+    uint32_t replica = 0;
 };
 
 static lll_status lattice_params(lll_lattice* L, const lll_params* p, bool need_schedule) {
@@ -483,11 +484,12 @@ static lll_status lattice_params(lll_lattice* L, const lll_params* p, bool need_
     if (p->D_site && !p->e_site) return set_err(LLL_EINVAL, "D_site needs e_site");
     const int prec = p->precession ? 1 : 0;
     const bool same = L->have_params && memcmp(&ph, &L->phys, sizeof ph) == 0 && L->dt == p->dt &&
-                      L->Dt == Dt && L->precession == prec && L->seed == p->seed;
+                      L->Dt == Dt && L->precession == prec && L->seed == p->seed &&
+                      L->replica == p->replica;
     if (same) return LLL_OK;
     Engine& E = L->E;
     RepDev& R = E.hreps[0];
-    fill_physics(R, ph, p->dt, Dt, prec, p->seed, 0u);
+    fill_physics(R, ph, p->dt, Dt, prec, p->seed, p->replica);
     E.precession = prec;
     E.anis = anis_mode_of(ph);
     if ((s = upload_reps(E)) != LLL_OK) return s;
@@ -496,6 +498,7 @@ static lll_status lattice_params(lll_lattice* L, const lll_params* p, bool need_
     L->Dt = Dt;
     L->precession = prec;
     L->seed = p->seed;
+    L->replica = p->replica;
     L->have_params = true;
     return LLL_OK;
 }

@@ -59,6 +59,7 @@ int main(void) {
   printf("lll_params %zu\nlll_obs %zu\nlll_replica_desc %zu\n", sizeof(lll_params), sizeof(lll_obs),
          sizeof(lll_replica_desc));
   F(lll_params, D_site) F(lll_params, lambda) F(lll_params, precession) F(lll_params, seed)
+  F(lll_params, replica)
   F(lll_obs, m) F(lll_obs, max_norm_dev)
   F(lll_replica_desc, lambda) F(lll_replica_desc, seed) F(lll_replica_desc, replica)
   F(lll_replica_desc, init)
@@ -77,6 +78,7 @@ int main(void) {
     assert lay["lll_replica_desc"] == C.sizeof(P.lll_replica_desc)
     assert lay["lll_params.D_site"] == P.lll_params.D_site.offset
     assert lay["lll_params.lambda"] == P.lll_params.lambda_.offset
+    assert lay["lll_params.replica"] == P.lll_params.replica.offset
     assert lay["lll_params.precession"] == P.lll_params.precession.offset
     assert lay["lll_params.seed"] == P.lll_params.seed.offset
     assert lay["lll_obs.m"] == P.lll_obs.m.offset

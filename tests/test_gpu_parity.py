@@ -353,3 +353,39 @@ def test_batch_matches_oracle(P, prec):
     acc = B.accumulators()
     assert all(a[0] == 2 for a in acc)
     B.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lattice_with_replica_key_follows_batch(P, prec):
+    """A lone lattice whose kicks use a batch replica's key (seed, replica)
+    and that starts from that replica's state follows the replica's
+    trajectory (the noise is a function of site, pulse, replica and seed
+    only); with replica key 0 it draws different noise."""
+    reps = [dict(L=(24, 24, 24), T=1.4, lam=0.01, seed=1000, replica=0),
+            dict(L=(48, 48, 48), T=0.8, lam=0.02, seed=1040, replica=40),
+            dict(L=(20, 12, 9), T=1.0, lam=0.03, seed=7, replica=5, bc="free")]
+    dt, Dt = 0.1, 1.0
+    B = P.Batch([dict(r, J=1.0) for r in reps], precision=prec, dt=dt, Dt=Dt)
+    lats = []
+    for i, r in enumerate(reps):
+        lat = P.Lattice(r["L"], precision=prec, bc=r.get("bc", "periodic"), state=B.state(i))
+        p = P.Params(J=1.0, lam=r["lam"], T=r["T"], dt=dt, Dt=Dt, seed=r["seed"], replica=r["replica"])
+        lats.append((lat, p))
+    other = P.Lattice(reps[1]["L"], precision=prec, state=B.state(1))
+    p_other = P.Params(J=1.0, lam=reps[1]["lam"], T=reps[1]["T"], dt=dt, Dt=Dt, seed=reps[1]["seed"])
+    B.run(first_pulse=3, n_pulses=3)
+    for lat, p in lats:
+        lat.run(p, first_pulse=3, n_pulses=3)
+    other.run(p_other, first_pulse=3, n_pulses=3)
+    torch.cuda.synchronize()
+    # fp32: batch and lone lattice may run different step kernels (fused tiles
+    # vs per-stage launches), whose rounding orders differ over 30 steps
+    tol = 1e-12 if prec == "fp64" else 5e-5
+    for i, (lat, _) in enumerate(lats):
+        d = (lat.state.double() - B.state(i).double()).abs().max().item()
+        assert d < tol, (i, d)
+    assert (other.state.double() - B.state(1).double()).abs().max().item() > 0.1
+    for lat, _ in lats:
+        lat.close()
+    other.close()
+    B.close()

@@ -9,7 +9,11 @@ after every interval.  One benchmark "step" is one interval of the schedule
 timed region is the workload's full 2000 pulses (20000 RK4 steps).
 
 Metric: spin-steps/s = sites x RK4 steps / s (kicks and reductions are inside
-the timed region but are not counted as steps).
+the timed region but are not counted as steps).  The JSON line also carries the
+roofline of the dominant kernel (the fused RK4 step: VALU-bound, with its HBM
+fraction alongside), the batched and adjoint ratios and the 256^3 overdamped
+run ("extras", skipped with --no-extras), and the FP64 oracle timed on a
+bounded sample on the host ("cpu_baseline").
 
 Prints ONE JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
 """
@@ -31,6 +35,15 @@ PHYS = dict(J=1.0, H=(0.0, 0.0, 0.1), D=0.05, e=(0.0, 0.0, 1.0), lam=0.01, T=1.0
             precession=True, seed=0)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SPIN_STEP = {"fp32": 24, "fp64": 48}
+# Arithmetic per spin and RK4 step (precessional equation, uniaxial z
+# anisotropy), counted per stage: neighbour sum 15, h = cJ n + cH 6, anisotropy
+# 2, s x h 9, h - lam (s x h) 6, s x (...) 9, next stage input 6, accumulator 6.
+FLOPS_PER_SPIN_STEP = 4 * 59
+# Vector ALU peak for the instruction forms this library issues: 256 CUs x 4 SIMDs
+# x 16 lanes x 2 flop (FMA) x 2.4 GHz.  The same for fp32 and fp64, because packed
+# fp32 (which doubles the fp32 rate to 157.3 TFLOP/s) is disabled in the build.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+METRIC = "spin-steps/s (RK4, 128^3 sc, fp32) + % HBM roofline; batched & adjoint ratios"
 TUNE_CACHE = os.path.join(ROOT, "paper_1610_04914_amd", "tune_cache.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rk4_fused_128c_fp32_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1610_04914_amd", "csrc", f)
@@ -99,16 +112,19 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
     [0.3, 2], lambda log-uniform in [0.005, 0.05], J = 1, H = 0, dt = 0.1,
     Dt = 1.0, random-sphere starts, per-replica noise keys.
 
-    Throughput (random starts): the fp32 batch (one graph per run) over n_pulses, and the plain
-    fp64 single-lattice path on the same replicas one after another over n_seq
-    pulses (each lattice keyed with its replica's seed and index, so it draws
-    the same noise as the batch).  Accuracy: fp32 and fp64 batches from the
-    same start and noise over n_acc pulses; per replica, the time averages of
-    E/N and |m| after `burn` pulses are compared against their combined
-    standard errors (from each series' integrated autocorrelation time); the
-    signed mean of the differences over replicas shows any fp32 bias.  The fp64 batch follows the fp64 single-lattice
-    path's trajectory (same keys, same arithmetic).  The accuracy runs start
-    ordered along +z so that the series are stationary after the burn-in."""
+    Throughput (random starts): the fp32 batch (one graph per run) over
+    n_pulses, and the plain fp64 single-lattice path on the same replicas one
+    after another over n_seq pulses (each lattice keyed with its replica's seed
+    and index, so it draws the same noise as the batch).
+
+    Accuracy: fp32 and fp64 batches from the same start and noise over n_acc
+    pulses; per replica, the time averages of E/N and |m| after `burn` pulses
+    are compared against their combined standard errors (from each series'
+    integrated autocorrelation time); the signed mean of the differences over
+    replicas shows any fp32 bias.  The fp64 batch follows the fp64
+    single-lattice path's trajectory (same keys, same arithmetic).  The
+    accuracy runs start ordered along +z so that the series are stationary
+    after the burn-in."""
     import numpy as np
     import paper_1610_04914_amd as P
     from tests import inputs
@@ -250,8 +266,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10)
-    ap.add_argument("--extras", action="store_true",
-                    help="also time the batched, adjoint and 256^3 overdamped workloads")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="skip the batched, adjoint and 256^3 overdamped workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -303,11 +319,13 @@ def main():
     spin_steps = N * n * args.steps
     value = spin_steps / elapsed
     alg_bytes = BYTES_PER_SPIN_STEP[prec] * N
-    achieved = alg_bytes / (step_ms * 1e-3) / 1e9 if step_ms > 0 else 0.0
+    alg_flops = FLOPS_PER_SPIN_STEP * N
+    achieved_gbs = alg_bytes / (step_ms * 1e-3) / 1e9 if step_ms > 0 else 0.0
+    achieved_tf = alg_flops / (step_ms * 1e-3) / 1e12 if step_ms > 0 else 0.0
     traffic = measured_traffic() if prec == "fp32" else None
 
     out = {
-        "metric": "spin-steps/s (RK4, 128^3 sc, fp32)" if prec == "fp32" else "spin-steps/s (RK4, 128^3 sc, fp64)",
+        "metric": METRIC if prec == "fp32" else "spin-steps/s (RK4, 128^3 sc, fp64)",
         "value": value,
         "unit": "spin-steps/s",
         "n_gpus": 1,
@@ -323,12 +341,15 @@ def main():
                                "RK4 dt=0.2, Dt=2.0 (n=10), obs every interval",
                    "sites": N, "rk4_steps_per_interval": n, "intervals": args.steps,
                    "step_variant": variant, "bz": bz, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": ALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tf / ALU_PEAK_TFLOPS,
                      "traffic": traffic,
                      "kernel": "rk4_fused_kernel",
+                     "alg_flops_per_launch": alg_flops,
                      "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": step_ms, "launches_timed": n_timed},
+                     "avg_launch_ms": step_ms, "launches_timed": n_timed,
+                     "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved_gbs / HBM_PEAK_GBS}},
         "final_obs": trace[-1] if trace else None,
     }
     if args.extras:

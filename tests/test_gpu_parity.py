@@ -389,3 +389,88 @@ def test_lattice_with_replica_key_follows_batch(P, prec):
         lat.close()
     other.close()
     B.close()
+
+
+# ------------------------------------------- the other workload configs -----
+def test_small_fp64_workload_per_segment(P):
+    """16^3 periodic fp64 ferromagnet (J = 1, H = 0, D = 0, lambda = 0.01, T = 1,
+    dt = 0.1, Dt = 1): three intervals in the tuned launch configuration, each
+    against the oracle started from the GPU's state before it."""
+    import bench
+    shape = (16, 16, 16)
+    op = orc.Params(J=1.0, lam=0.01, T=1.0, dt=0.1, Dt=1.0)
+    gp = P.Params(J=1.0, H=(0, 0, 0), D=0.0, lam=0.01, T=1.0, dt=0.1, Dt=1.0, seed=0)
+    lat = P.Lattice(shape, precision="fp64", init="random", seed=0)
+    lat.autotune(gp, cache_path=bench.TUNE_CACHE)
+    g = orc.geom(shape)
+    prev = np_state(lat)
+    np.testing.assert_allclose(prev, orc.init_random_sphere(g, 0), atol=4e-16)
+    for q in range(3):
+        tr = lat.run(gp, first_pulse=q, n_pulses=1, obs_every=1)
+        cur = np_state(lat)
+        want, otr, _ = orc.run(g, op, prev, seed=0, first_pulse=q, n_pulses=1, obs_every=1)
+        assert np.max(np.abs(cur - want)) < TOL["fp64"], q
+        assert tr[0]["E_total"] == pytest.approx(otr[0]["E_total"], rel=1e-11)
+        prev = cur
+    lat.close()
+
+
+def test_full_batch_sampled(P):
+    """The 96-replica uneven batch (32 each of 24^3, 48^3, 64^3) in fp32 in the
+    tuned launch configuration: one interval; one replica of each size is
+    recomputed whole by the oracle from the batch's own start state and keys."""
+    import bench
+    reps = inputs.batch_replicas(seed=0)
+    B = P.Batch([dict(r, J=1.0) for r in reps], precision="fp32", dt=0.1, Dt=1.0)
+    B.autotune(cache_path=bench.TUNE_CACHE)
+    picks = [5, 40, 77]
+    s0 = {i: B.state(i).double().cpu().numpy() for i in picks}
+    tr = B.run(first_pulse=0, n_pulses=1, obs_every=1)
+    for i in picks:
+        r = reps[i]
+        g = orc.geom(r["L"])
+        op = orc.Params(J=1.0, lam=r["lam"], T=r["T"], dt=0.1, Dt=1.0)
+        want, _, _ = orc.run(g, op, s0[i], seed=r["seed"], r=r["replica"], first_pulse=0,
+                             n_pulses=1)
+        cur = B.state(i).double().cpu().numpy()
+        assert np.max(np.abs(cur - want)) < TOL["fp32"], i
+        o = orc.observables(g, op, cur)
+        assert tr[0][i]["E_total"] == pytest.approx(o["E_total"], rel=1e-12, abs=1e-12)
+        np.testing.assert_allclose(tr[0][i]["m"], o["m"], rtol=1e-11, atol=1e-14)
+    B.close()
+
+
+def test_full_size_overdamped_sampled(P):
+    """256^3 fp32 slow equation (J = 1, D = 0.02 z, lambda = 0.1, dt = Dt = 0.4,
+    a pulse every step, first two temperatures of the 2.0 -> 0.5 ramp) in the
+    tuned launch configuration; sampled sites against the oracle on free-boundary
+    cut-outs of radius 8 with the sites' global noise counters."""
+    import bench
+    shape = (256, 256, 256)
+    Ts = [2.0, 2.0 - 1.5 / 4999]
+    op = orc.Params(J=1.0, D=0.02, e=(0, 0, 1), lam=0.1, T=Ts[0], dt=0.4, Dt=0.4,
+                    precession=False)
+    gp = P.Params(J=1.0, D=0.02, e=(0, 0, 1), lam=0.1, T=Ts[0], dt=0.4, Dt=0.4,
+                  precession=False, seed=0)
+    lat = P.Lattice(shape, precision="fp32", init="random", seed=0)
+    lat.autotune(gp, cache_path=bench.TUNE_CACHE)
+    s0 = np_state(lat)
+    lat.run(gp, first_pulse=0, n_pulses=2, T_per_pulse=Ts)
+    s1 = np_state(lat)
+    rng = np.random.default_rng(5)
+    cen = [tuple(c) for c in rng.integers(0, 256, size=(16, 3))] + [(0, 0, 0), (255, 255, 255),
+                                                                      (64, 0, 63), (1, 128, 64)]
+    rad = 8
+    n = 2 * rad + 1
+    gc = orc.geom((n, n, n), "free")
+    mid = (n**3) // 2
+    for c in cen:
+        cut, ids = _cutout(s0, shape, c, rad)
+        st = cut
+        for k, T in enumerate(Ts):  # n = 1: kick, then the step
+            st, _ = orc.kick_indexed(gc, op, st, T, seed=0, r=0, k=k, site_id=ids)
+            st = orc.step(gc, op, st, 1)
+        i = c[0] + 256 * (c[1] + 256 * c[2])
+        err = np.max(np.abs(st[:, mid] - s1[:, i]))
+        assert err < TOL["fp32"], (c, err)
+    lat.close()

@@ -111,12 +111,11 @@ __device__ __forceinline__ void block_max_part(double v, double* part) {
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// Block r: maximum over the parts of replica r (its per-site blocks, or its
-// fused-step tiles in tile order) folded into kickdev[r].
-__global__ void __launch_bounds__(256)
-    kickmax_reduce(const RepDev* reps, const double* part, int by_tiles,
-                   unsigned long long* kickdev) {
-    const RepDev& R = reps[blockIdx.x];
+// Maximum over the parts of replica R (its per-site blocks, or its fused-step
+// tiles in tile order) folded into *kickdev by thread 0; the whole block of
+// 256 threads takes part.
+__device__ __forceinline__ void kickmax_fold(const RepDev& R, const double* part, int by_tiles,
+                                             unsigned long long* kickdev) {
     const int p0 = by_tiles ? R.tile0 : R.sb0;
     const int np = by_tiles ? R.tx * R.ty * R.tz : R.nsb;
     double m = 0.0;
@@ -135,10 +134,17 @@ __global__ void __launch_bounds__(256)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double old = __longlong_as_double((long long)kickdev[blockIdx.x]);
+        const double old = __longlong_as_double((long long)*kickdev);
         const double nw = red[0];
-        if (nw > old || nw != nw) kickdev[blockIdx.x] = (unsigned long long)__double_as_longlong(nw);
+        if (nw > old || nw != nw) *kickdev = (unsigned long long)__double_as_longlong(nw);
     }
+}
+
+// Block r: kick maximum of replica r folded into kickdev[r].
+__global__ void __launch_bounds__(256)
+    kickmax_reduce(const RepDev* reps, const double* part, int by_tiles,
+                   unsigned long long* kickdev) {
+    kickmax_fold(reps[blockIdx.x], part, by_tiles, kickdev + blockIdx.x);
 }
 
 hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part, int by_tiles,
@@ -171,9 +177,8 @@ __global__ void __launch_bounds__(kSiteBlock)
     block_max_part(dev, kickpart);
 }
 
-hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, int nrep,
-                       State s, uint64_t k, double sigma_override, double* kickpart,
-                       unsigned long long* kickdev, hipStream_t st) {
+hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
+                       uint64_t k, double sigma_override, double* kickpart, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
     if (prec == 0)
         hipLaunchKernelGGL(kick_kernel<double>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
@@ -181,9 +186,7 @@ hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int
     else
         hipLaunchKernelGGL(kick_kernel<float>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
                            s, k, sigma_override, kickpart);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_kickmax_reduce(reps, nrep, kickpart, 0, kickdev, st);
+    return hipGetLastError();
 }
 
 // ----------------------------------------------------------- observables ---
@@ -195,32 +198,40 @@ hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int
 // writes back the L2 of its XCD each time and costs far more than a launch.)  Each site owns its bonds to its +x, +y and
 // +z neighbours (Eq. (2) counts every bond once).
 __device__ __forceinline__ double nan_max(double a, double c) { return (c > a || c != c) ? c : a; }
+__device__ __forceinline__ double nan_min(double a, double c) { return (c < a || c != c) ? c : a; }
+
+// The 8 reduced quantities: sums 0..5, max (6) and min (7) of |s|^2.  The
+// norm deviation max_i | |s_i| - 1 | follows from the extremes alone (sqrt and
+// the subtraction are monotone on each side of 1), so no per-site square root.
+__device__ __forceinline__ double red8(int j, double a, double c) {
+    return j < 6 ? a + c : (j == 6 ? nan_max(a, c) : nan_min(a, c));
+}
 
 // Butterfly over the 64 lanes of a wavefront (fixed pairing, so the result
-// does not depend on timing); every lane ends with the wave's total.
-__device__ __forceinline__ void wave_reduce7(double q[7]) {
+// does not depend on timing); every lane ends with the wave's result.
+__device__ __forceinline__ void wave_reduce8(double q[8]) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) q[j] += __shfl_xor(q[j], o, 64);
-        q[6] = nan_max(q[6], __shfl_xor(q[6], o, 64));
+        for (int j = 0; j < 8; ++j) q[j] = red8(j, q[j], __shfl_xor(q[j], o, 64));
     }
 }
 
-// Sum of the 7 quantities over a block of NT threads into out[0..6] (thread 0).
+// Reduction of the 8 quantities over a block of NT threads into out[0..7]
+// (written by threads 0..7).
 template <int NT>
-__device__ __forceinline__ void block_reduce7(double q[7], double* out) {
+__device__ __forceinline__ void block_reduce8(double q[8], double* out) {
     constexpr int NW = NT / 64;
-    __shared__ double red[NW][7];
-    wave_reduce7(q);
+    __shared__ double red[NW][8];
+    wave_reduce8(q);
     const int w = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0)
-        for (int j = 0; j < 7; ++j) red[w][j] = q[j];
+        for (int j = 0; j < 8; ++j) red[w][j] = q[j];
     __syncthreads();
-    if (threadIdx.x < 7) {
+    if (threadIdx.x < 8) {
         const int j = threadIdx.x;
         double a = red[0][j];
-        for (int v = 1; v < NW; ++v) a = (j < 6) ? a + red[v][j] : nan_max(a, red[v][j]);
+        for (int v = 1; v < NW; ++v) a = red8(j, a, red[v][j]);
         out[j] = a;
     }
 }
@@ -246,7 +257,7 @@ __global__ void __launch_bounds__(kObsBlock)
     // no division runs per site
     int x = (int)(i % Lx), y = (int)((i / Lx) % Ly), z = (int)(i / Lxy);
     const int dx = (int)(stride % Lx), dy = (int)((stride / Lx) % Ly), dz = (int)(stride / Lxy);
-    double q[7] = {0, 0, 0, 0, 0, 0, 0};
+    double q[8] = {0, 0, 0, 0, 0, 0, 0, __builtin_huge_val()};
     for (; i < N; i += U * stride) {
         // site and +x, +y, +z neighbour indices; every index is a valid site
         // (lanes past the end read site 0, missing free-boundary bonds read a
@@ -308,28 +319,36 @@ __global__ void __launch_bounds__(kObsBlock)
             q[3] += sx;
             q[4] += sy;
             q[5] += sz;
-            q[6] = nan_max(q[6], fabs(sqrt(sx * sx + sy * sy + sz * sz) - 1.0));
+            const double n2 = sx * sx + sy * sy + sz * sz;
+            q[6] = nan_max(q[6], n2);
+            q[7] = nan_min(q[7], n2);
         }
     }
-    block_reduce7<kObsBlock>(q, partials + (int64_t)b * 8);
+    block_reduce8<kObsBlock>(q, partials + (int64_t)b * 8);
 }
 
 constexpr int kObsFinal = 256;
 
-// Sums the partials of replica blockIdx.x in block order.
+// Sums the partials of replica blockIdx.x in block order.  kick_mode >= 0:
+// also folds the pending kick maxima (per-site blocks 0, fused tiles 1) of the
+// replica into kickdev, saving a launch after a kick.
 __global__ void __launch_bounds__(kObsFinal)
     obs_final_kernel(const RepDev* reps, const double* partials, double* result, double* accum,
-                     int accumulate) {
+                     int accumulate, const double* kickpart, int kick_mode,
+                     unsigned long long* kickdev) {
     const int r = blockIdx.x;
     const RepDev& R = reps[r];
-    double q[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (kick_mode >= 0) {
+        kickmax_fold(R, kickpart, kick_mode, kickdev + r);
+        __syncthreads();
+    }
+    double q[8] = {0, 0, 0, 0, 0, 0, 0, __builtin_huge_val()};
     for (int b = R.ob0 + threadIdx.x; b < R.ob0 + R.nob; b += kObsFinal) {
         const double* p = partials + (int64_t)b * 8;
-        for (int j = 0; j < 6; ++j) q[j] += p[j];
-        q[6] = nan_max(q[6], p[6]);
+        for (int j = 0; j < 8; ++j) q[j] = red8(j, q[j], p[j]);
     }
-    __shared__ double tot[7];
-    block_reduce7<kObsFinal>(q, tot);
+    __shared__ double tot[8];
+    block_reduce8<kObsFinal>(q, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
         const double N = (double)R.Lx * R.Ly * R.Lz;
@@ -346,7 +365,7 @@ __global__ void __launch_bounds__(kObsFinal)
         o[4] = mx;
         o[5] = my;
         o[6] = mz;
-        o[7] = tot[6];
+        o[7] = nan_max(sqrt(tot[6]) - 1.0, 1.0 - sqrt(tot[7]));
         if (accumulate) {
             double* a = accum + (int64_t)r * 8;
             const double m2 = mx * mx + my * my + mz * mz;
@@ -387,7 +406,8 @@ static void launch_obs_t(int anis, const RepDev* reps, const int32_t* oblk_rep, 
 
 hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
                       int nobblk, int nrep, State s, double* partials, double* result,
-                      double* accum, int accumulate, hipStream_t st) {
+                      double* accum, int accumulate, const double* kickpart, int kick_mode,
+                      unsigned long long* kickdev, hipStream_t st) {
     if (nobblk <= 0 || nrep <= 0) return hipSuccess;
     if (prec == 0)
         launch_obs_t<double>(anis, reps, oblk_rep, nobblk, s, partials, st);
@@ -396,7 +416,7 @@ hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* obl
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(obs_final_kernel, dim3(nrep), dim3(kObsFinal), 0, st, reps, partials,
-                       result, accum, accumulate);
+                       result, accum, accumulate, kickpart, kick_mode, kickdev);
     return hipGetLastError();
 }
 

@@ -74,6 +74,10 @@ struct Engine {
     double* d_kickpart = nullptr;  // per-block / per-tile maxima of the kick deviation
     int kickpart_cap = 0;
     bool kick_epilogue = true;     // kick as the fused step's epilogue (else its own launch)
+    // kick maxima written to d_kickpart but not yet folded into d_kickdev:
+    // -1 none, 0 per-site blocks, 1 fused-step tiles (folded by the next
+    // measurement, or by a reduction launch before the next kick / run end)
+    int kick_pending = -1;
     double* d_trace = nullptr;
     size_t trace_cap = 0;         // doubles
     int variant = 0, bz = 0;      // step configuration (0 = unfused)
@@ -352,6 +356,15 @@ const LaunchEvents* kt_take(Engine& E) {
     return &E.kt_ev[j];
 }
 
+lll_status kick_flush(Engine& E) {
+    if (E.kick_pending >= 0) {
+        HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, E.kick_pending, E.d_kickdev,
+                                      E.st));
+        E.kick_pending = -1;
+    }
+    return LLL_OK;
+}
+
 lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sigma_override) {
     if (n <= 0) return LLL_OK;
     if (E.variant == 0 || E.anis == ANIS_SITE) {
@@ -360,9 +373,12 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
         for (int64_t q = 0; q < n; ++q)
             HIP_TRY(launch_step_unfused(E.prec, E.precession, E.anis, E.dreps, E.d_blk_rep, E.nblk,
                                         cur_state(E), E.yA, E.yB, E.acc, E.st));
-        if (kick_last)
-            HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, E.nrep, cur_state(E), k,
-                                sigma_override, E.d_kickpart, E.d_kickdev, E.st));
+        if (kick_last) {
+            if ((s = kick_flush(E)) != LLL_OK) return s;
+            HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k,
+                                sigma_override, E.d_kickpart, E.st));
+            E.kick_pending = 0;
+        }
         return LLL_OK;
     }
     lll_status s = alloc_state(E, E.alt);
@@ -370,23 +386,30 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
     if ((s = ensure_tiles(E)) != LLL_OK) return s;
     for (int64_t q = 0; q < n; ++q) {
         const bool kk = kick_last && q == n - 1 && E.kick_epilogue;
+        if (kk && (s = kick_flush(E)) != LLL_OK) return s;
         State in = cur_state(E);
         State out = E.cur ? E.s : E.alt;
         HIP_TRY(launch_step_fused(E.prec, E.precession, E.anis, E.variant, eff_bz(E), E.dreps, E.d_tiles,
                                   E.ntiles, in, out, kk ? 1 : 0, k, sigma_override, E.d_kickpart,
                                   kk ? nullptr : kt_take(E), E.st));
-        if (kk) HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, 1, E.d_kickdev, E.st));
+        if (kk) E.kick_pending = 1;
         E.cur ^= 1;
     }
-    if (kick_last && !E.kick_epilogue)
-        HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, E.nrep, cur_state(E), k,
-                            sigma_override, E.d_kickpart, E.d_kickdev, E.st));
+    if (kick_last && !E.kick_epilogue) {
+        if ((s = kick_flush(E)) != LLL_OK) return s;
+        HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k, sigma_override,
+                            E.d_kickpart, E.st));
+        E.kick_pending = 0;
+    }
     return LLL_OK;
 }
 
 lll_status do_kick(Engine& E, uint64_t k, double sigma_override) {
-    HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, E.nrep, cur_state(E), k,
-                        sigma_override, E.d_kickpart, E.d_kickdev, E.st));
+    lll_status s = kick_flush(E);
+    if (s != LLL_OK) return s;
+    HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k, sigma_override,
+                        E.d_kickpart, E.st));
+    E.kick_pending = 0;
     return LLL_OK;
 }
 
@@ -410,9 +433,12 @@ lll_status do_interval(Engine& E, int64_t n, uint64_t k, double sigma_override) 
     return do_steps(E, n2, false, 0, -1.0);
 }
 
+// Observables into result; folds a pending kick maximum in the same launches.
 lll_status do_obs(Engine& E, double* result, int accumulate) {
     HIP_TRY(launch_obs(E.prec, E.anis, E.dreps, E.d_oblk_rep, E.nobblk, E.nrep, cur_state(E),
-                       E.d_partials, result, E.d_accum, accumulate, E.st));
+                       E.d_partials, result, E.d_accum, accumulate, E.d_kickpart, E.kick_pending,
+                       E.d_kickdev, E.st));
+    E.kick_pending = -1;
     return LLL_OK;
 }
 
@@ -588,7 +614,8 @@ extern "C" lll_status lll_noise_pulse(lll_lattice* L, const lll_params* p, uint6
     lll_status s = lattice_params(L, p, true);
     if (s != LLL_OK) return s;
     if ((s = settle(L->E)) != LLL_OK) return s;
-    return do_kick(L->E, pulse_index, -1.0);
+    if ((s = do_kick(L->E, pulse_index, -1.0)) != LLL_OK) return s;
+    return kick_flush(L->E);
 }
 
 extern "C" lll_status lll_observables(lll_lattice* L, const lll_params* p, lll_obs* out) {
@@ -641,6 +668,7 @@ extern "C" lll_status lll_run(lll_lattice* L, const lll_params* p, uint64_t firs
             ++m;
         }
     }
+    if ((s = kick_flush(E)) != LLL_OK) return s;
     if ((s = settle(E)) != LLL_OK) return s;
     if (want_trace) {
         std::vector<double> h((size_t)nmeas * 8);
@@ -670,6 +698,8 @@ extern "C" lll_status lll_get_state(lll_lattice* L, void** sx, void** sy, void**
 
 extern "C" lll_status lll_kick_norm_dev(lll_lattice* L, double* out, int32_t reset) {
     if (!L || !out) return set_err(LLL_EINVAL, "NULL argument");
+    lll_status s = kick_flush(L->E);
+    if (s != LLL_OK) return s;
     unsigned long long v = 0;
     HIP_TRY(hipMemcpyAsync(&v, L->E.d_kickdev, sizeof v, hipMemcpyDeviceToHost, L->E.st));
     HIP_TRY(hipStreamSynchronize(L->E.st));
@@ -809,6 +839,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     State save{};
     if ((s = alloc_state(E, save)) != LLL_OK) return s;
     HIP_TRY(launch_copy(E.prec, save, E.s, E.nsites, E.st));
+    if ((s = kick_flush(E)) != LLL_OK) return s;
     std::vector<unsigned long long> kd_save(E.nrep);
     HIP_TRY(hipMemcpyAsync(kd_save.data(), E.d_kickdev, sizeof(unsigned long long) * E.nrep,
                            hipMemcpyDeviceToHost, E.st));
@@ -872,6 +903,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
         bk = tk[1] <= tk[0];
     }
     E.kick_epilogue = bk;
+    E.kick_pending = -1;  // maxima of the timing runs are dropped (kickdev is restored below)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     hipError_t ce = launch_copy(E.prec, E.s, save, E.nsites, E.st);
@@ -987,13 +1019,14 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
                                       slot(0, 2), slot(0, 3), accb, nxt, E.st));
             std::swap(cur, nxt);
         } else {
-            HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, E.nrep, cur, opk[j], -1.0,
-                                E.d_kickpart, E.d_kickdev, E.st));
+            HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, cur, opk[j], -1.0, E.d_kickpart,
+                                E.st));
+            HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, 0, E.d_kickdev, E.st));
         }
     }
     // loss and its cotangent
     HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, cur, E.d_partials, E.d_result,
-                       E.d_accum, 0, E.st));
+                       E.d_accum, 0, nullptr, -1, nullptr, E.st));
     HIP_TRY(launch_adj_loss(pr, an, E.dreps, E.d_blk_rep, E.nblk, cur, sbar, wE, wm, gD, part, acc5,
                             E.st));
     // backward
@@ -1009,8 +1042,9 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
                                           slot(sl, 1), slot(sl, 2), slot(sl, 3), accb, nx, E.st));
             } else {
                 HIP_TRY(launch_copy(pr, nx, slot(sl, 0), E.nsites, E.st));
-                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, E.nrep, nx, opk[j], -1.0,
-                                    E.d_kickpart, E.d_kickdev, E.st));
+                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, opk[j], -1.0, E.d_kickpart,
+                                    E.st));
+                HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, 0, E.d_kickdev, E.st));
             }
         }
         for (int64_t j = j1 - 1; j >= j0; --j) {
@@ -1156,6 +1190,7 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
                 ++m;
             }
         }
+        if (cap == LLL_OK) cap = kick_flush(E);  // every replay starts and ends with nothing pending
         if (cap == LLL_OK) cap = settle(E);
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(cs, &g);

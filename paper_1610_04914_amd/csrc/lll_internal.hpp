@@ -44,20 +44,21 @@ hipError_t launch_philox_words(uint64_t seed, uint32_t i0, int64_t n, uint32_t c
 hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
                        int mode, double dx, double dy, double dz, hipStream_t st);
 // sigma_override >= 0 replaces every replica's kick scale (per-pulse temperature).
-// kickpart: scratch [nblk] of per-block maxima of | |s'| - 1 |, folded into
-// kickdev[replica] (fp64 bit patterns of running maxima).
-hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, int nrep,
-                       State s, uint64_t k, double sigma_override, double* kickpart,
-                       unsigned long long* kickdev, hipStream_t st);
+// kickpart: scratch [nblk] of per-block maxima of | |s'| - 1 |, to be folded
+// into the running maxima by launch_kickmax_reduce (or by launch_obs).
+hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
+                       uint64_t k, double sigma_override, double* kickpart, hipStream_t st);
 // Folds per-block maxima into kickdev: parts of replica r are its per-site
 // blocks (by_tiles = 0) or its fused-step tiles in tile order (by_tiles = 1).
 hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part, int by_tiles,
                                  unsigned long long* kickdev, hipStream_t st);
 // Observables of every replica into result[r][8] (and accum when accumulate);
-// partials: [nobblk][8] scratch.
+// partials: [nobblk][8] scratch.  kick_mode >= 0 also folds pending kick maxima
+// (as launch_kickmax_reduce with by_tiles = kick_mode) into kickdev.
 hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
                       int nobblk, int nrep, State s, double* partials, double* result,
-                      double* accum, int accumulate, hipStream_t st);
+                      double* accum, int accumulate, const double* kickpart, int kick_mode,
+                      unsigned long long* kickdev, hipStream_t st);
 // Unfused RK4 step: four stage launches; scratch yA, yB, acc of the same shape.
 hipError_t launch_step_unfused(int prec, int precession, int anis, const RepDev* reps,
                                const int32_t* blk_rep, int nblk, State s, State yA, State yB,

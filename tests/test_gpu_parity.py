@@ -474,3 +474,37 @@ def test_full_size_overdamped_sampled(P):
         err = np.max(np.abs(st[:, mid] - s1[:, i]))
         assert err < TOL["fp32"], (c, err)
     lat.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_kick_maximum_same_on_every_fold_path(P, prec):
+    """The running maximum of | |s'| - 1 | over the kicks of a run is the same,
+    bit for bit, whether each kick's maximum is folded by the next measurement,
+    by a reduction before the next kick, or at the end of the run, for both
+    kick placements; and it matches the oracle's over the same interval."""
+    shape = (40, 24, 20)
+    op, gp = both_params("zaxis", dt=0.1, Dt=0.4, seed=21)
+    got = {}
+    for v in (0, 1):
+        for fused in (True, False):
+            for every in (0, 1, 2):
+                lat = P.Lattice(shape, precision=prec, init="random", seed=4)
+                lat.set_step_config(v, 0)
+                lat.set_kick_fusion(fused)
+                lat.kick_norm_dev(reset=True)
+                lat.run(gp, first_pulse=0, n_pulses=4, obs_every=every)
+                got[(v, fused, every)] = lat.kick_norm_dev()
+                lat.close()
+    for v in (0, 1):  # bit-identical within one step kernel
+        assert len({x for key, x in got.items() if key[0] == v}) == 1, got
+    # the unfused and fused steps round differently; d = | |s'| - 1 | ~ 1e-3 is
+    # a difference of O(1) numbers, so its fp32 error is absolute (state ulps)
+    tol = dict(rel=1e-12) if prec == "fp64" else dict(abs=2e-6)
+    assert got[(0, True, 0)] == pytest.approx(got[(1, True, 0)], **tol)
+    lat = P.Lattice(shape, precision=prec, init="random", seed=4)
+    s0 = np_state(lat)
+    want_state, _, dev = orc.run(orc.geom(shape), op, s0, seed=21, first_pulse=0, n_pulses=1)
+    lat.kick_norm_dev(reset=True)
+    lat.run(gp, first_pulse=0, n_pulses=1)
+    assert lat.kick_norm_dev() == pytest.approx(dev, **tol)
+    lat.close()

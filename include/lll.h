@@ -66,7 +66,12 @@ typedef enum {
     LLL_INIT_DIRECTION = 1,     /* every spin along dir (normalised) */
     LLL_INIT_KEEP = 2           /* the caller has filled the buffers it passes */
 } lll_init;
-typedef enum { LLL_RK4 = 0 } lll_integrator;
+/* Step integrators (Appendix).  LLL_RK4: classical fourth order, one fused
+ * launch per step.  LLL_RK2MID: midpoint, K1 = dt f(x), K2 = dt f(x + K1/2),
+ * x' = x + K2.  LLL_RK5B: Butcher's six-stage fifth-order method (the
+ * paper's main solver).  RK2MID and RK5B run one launch per stage and are
+ * not available to the adjoint or the batch. */
+typedef enum { LLL_RK4 = 0, LLL_RK2MID = 1, LLL_RK5B = 2 } lll_integrator;
 
 /* Physical and numerical parameters, copied on every call.  Thresholds of the
  * applicability warning: 2 lambda T Dt > 0.2 (Eq. (8)); lambda h_max Dt > 0.2
@@ -86,7 +91,7 @@ typedef struct {
     double dt;            /* RK4 step, > 0 */
     double Dt;            /* pulse spacing; Dt/dt must be an integer n >= 1 (|Dt/dt - n| <= 1e-9 n) */
     int32_t precession;   /* 1: full Eq. (1); 0: slow equation (precession dropped) */
-    int32_t integrator;   /* LLL_RK4 */
+    int32_t integrator;   /* lll_integrator */
     uint64_t seed;        /* Philox key of the kicks */
     uint32_t replica;     /* Philox counter word 2 of the kicks: 0 for a lone lattice; set it to
                              a batch replica's index to draw that replica's noise */

@@ -199,6 +199,7 @@ class Params:
     dt: float = 0.1
     Dt: float = 1.0
     precession: bool = True
+    integrator: str = "rk4"           # "rk4", "rk2mid" (midpoint) or "rk5b" (Butcher's RK5)
     seed: int = 0
     replica: int = 0                  # Philox counter word 2 of the kicks (batch replica index)
     D_site: Optional[object] = None   # device tensor [N] of the lattice dtype
@@ -217,7 +218,7 @@ class Params:
         p.dt = float(self.dt)
         p.Dt = float(self.Dt)
         p.precession = 1 if self.precession else 0
-        p.integrator = 0
+        p.integrator = _INTEGRATOR[self.integrator]
         p.seed = int(self.seed)
         p.replica = int(self.replica)
         p.reserved = 0
@@ -225,6 +226,7 @@ class Params:
 
 
 _PREC = {"fp64": LLL_FP64, "fp32": LLL_FP32}
+_INTEGRATOR = {"rk4": 0, "rk2mid": 1, "rk5b": 2}
 _BC = {"periodic": LLL_BC_PERIODIC, "free": LLL_BC_FREE}
 
 

@@ -425,13 +425,11 @@ hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* obl
 // the accumulator; stage 1: acc = x + k/6, y2 = x + k/2; stage 2: acc += k/3,
 // y3 = x + k/2; stage 3: acc += k/3, y4 = x + k; stage 4: x' = acc + k/6
 // (written over x, which stage 4 does not read).
+// k = dt f(y) at the site of c: the six-neighbour sum of y (missing neighbours
+// of free boundaries contribute nothing), then Eq. (1).
 template <typename T, bool PREC, int ANIS>
-__global__ void __launch_bounds__(kSiteBlock)
-    stage_kernel(const RepDev* reps, const int32_t* blk_rep, State yin, State xs, State acc,
-                 State out, int stage) {
-    SiteCtx c;
-    if (!site_of_thread(reps, blk_rep, c)) return;
-    const RepDev& R = reps[c.r];
+__device__ __forceinline__ void site_k(const RepDev& R, const SiteCtx& c, const State& yin, T& kx,
+                                       T& ky, T& kz) {
     const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
     const int64_t N = (int64_t)Lx * Ly * Lz;
     const int x = (int)(c.i % Lx);
@@ -464,8 +462,17 @@ __global__ void __launch_bounds__(kSiteBlock)
         ey = es[N + c.i];
         ez = es[2 * N + c.i];
     }
-    T kx, ky, kz;
     stage_k<T, PREC, ANIS>(sx, sy, sz, nx, ny, nz, C, Di, ex, ey, ez, kx, ky, kz);
+}
+
+template <typename T, bool PREC, int ANIS>
+__global__ void __launch_bounds__(kSiteBlock)
+    stage_kernel(const RepDev* reps, const int32_t* blk_rep, State yin, State xs, State acc,
+                 State out, int stage) {
+    SiteCtx c;
+    if (!site_of_thread(reps, blk_rep, c)) return;
+    T kx, ky, kz;
+    site_k<T, PREC, ANIS>(reps[c.r], c, yin, kx, ky, kz);
     T* ax = static_cast<T*>(acc.x);
     T* ay = static_cast<T*>(acc.y);
     T* az = static_cast<T*>(acc.z);
@@ -572,6 +579,91 @@ hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* r
                           : stages_p<double, false>(anis, reps, blk_rep, nblk, x, y2, y3, y4, acc, xnext, st);
     return precession ? stages_p<float, true>(anis, reps, blk_rep, nblk, x, y2, y3, y4, acc, xnext, st)
                       : stages_p<float, false>(anis, reps, blk_rep, nblk, x, y2, y3, y4, acc, xnext, st);
+}
+
+// ---------------------------------------------------- explicit RK tableau --
+// One stage j of an explicit Runge-Kutta step given by its tableau: k_j =
+// dt f(y_j) from the neighbourhood of yin = y_j; then either the next stage's
+// input y_{j+1} = x + sum_{l<=j} a[j+1][l] k_l (k_j kept in K[j]) or, for the
+// last stage, x' = x + sum_l b[l] k_l written over x (which no thread reads
+// as a neighbour in that stage).
+template <typename T, bool PREC, int ANIS>
+__global__ void __launch_bounds__(kSiteBlock)
+    tableau_stage_kernel(const RepDev* reps, const int32_t* blk_rep, State yin, State xs, KSet ks,
+                         Tableau tb, int j, State out) {
+    SiteCtx c;
+    if (!site_of_thread(reps, blk_rep, c)) return;
+    T kx, ky, kz;
+    site_k<T, PREC, ANIS>(reps[c.r], c, yin, kx, ky, kz);
+    const int64_t g = c.gi;
+    const bool last = j == tb.stages - 1;
+    const double* w = last ? tb.b : tb.a[j + 1];
+    T* px = static_cast<T*>(xs.x);
+    T* py = static_cast<T*>(xs.y);
+    T* pz = static_cast<T*>(xs.z);
+    T ox = px[g], oy = py[g], oz = pz[g];
+    for (int l = 0; l < j; ++l) {
+        if (w[l] == 0.0) continue;
+        const T wl = (T)w[l];
+        ox += wl * static_cast<const T*>(ks.K[l].x)[g];
+        oy += wl * static_cast<const T*>(ks.K[l].y)[g];
+        oz += wl * static_cast<const T*>(ks.K[l].z)[g];
+    }
+    const T wj = (T)w[j];
+    ox += wj * kx;
+    oy += wj * ky;
+    oz += wj * kz;
+    if (last) {
+        px[g] = ox;
+        py[g] = oy;
+        pz[g] = oz;
+        return;
+    }
+    static_cast<T*>(ks.K[j].x)[g] = kx;
+    static_cast<T*>(ks.K[j].y)[g] = ky;
+    static_cast<T*>(ks.K[j].z)[g] = kz;
+    static_cast<T*>(out.x)[g] = ox;
+    static_cast<T*>(out.y)[g] = oy;
+    static_cast<T*>(out.z)[g] = oz;
+}
+
+template <typename T, bool PREC, int ANIS>
+static hipError_t tableau_t(const RepDev* reps, const int32_t* blk_rep, int nblk, const Tableau& tb,
+                            State s, State yA, State yB, const KSet& ks, hipStream_t st) {
+    State yin = s;
+    for (int j = 0; j < tb.stages; ++j) {
+        const State out = (j % 2 == 0) ? yA : yB;
+        hipLaunchKernelGGL((tableau_stage_kernel<T, PREC, ANIS>), dim3(nblk), dim3(kSiteBlock), 0, st,
+                           reps, blk_rep, yin, s, ks, tb, j, out);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        yin = out;
+    }
+    return hipSuccess;
+}
+
+template <typename T, bool PREC>
+static hipError_t tableau_p(int anis, const RepDev* reps, const int32_t* blk_rep, int nblk,
+                            const Tableau& tb, State s, State yA, State yB, const KSet& ks,
+                            hipStream_t st) {
+    switch (anis) {
+        case ANIS_NONE: return tableau_t<T, PREC, ANIS_NONE>(reps, blk_rep, nblk, tb, s, yA, yB, ks, st);
+        case ANIS_Z: return tableau_t<T, PREC, ANIS_Z>(reps, blk_rep, nblk, tb, s, yA, yB, ks, st);
+        case ANIS_AXIS: return tableau_t<T, PREC, ANIS_AXIS>(reps, blk_rep, nblk, tb, s, yA, yB, ks, st);
+        default: return tableau_t<T, PREC, ANIS_SITE>(reps, blk_rep, nblk, tb, s, yA, yB, ks, st);
+    }
+}
+
+hipError_t launch_step_tableau(int prec, int precession, int anis, const RepDev* reps,
+                               const int32_t* blk_rep, int nblk, const Tableau& tb, State s,
+                               State yA, State yB, const KSet& ks, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    if (tb.stages < 1 || tb.stages > 6) return hipErrorInvalidValue;
+    if (prec == 0)
+        return precession ? tableau_p<double, true>(anis, reps, blk_rep, nblk, tb, s, yA, yB, ks, st)
+                          : tableau_p<double, false>(anis, reps, blk_rep, nblk, tb, s, yA, yB, ks, st);
+    return precession ? tableau_p<float, true>(anis, reps, blk_rep, nblk, tb, s, yA, yB, ks, st)
+                      : tableau_p<float, false>(anis, reps, blk_rep, nblk, tb, s, yA, yB, ks, st);
 }
 
 // ------------------------------------------------------------------ copy ---

@@ -81,6 +81,8 @@ struct Engine {
     double* d_trace = nullptr;
     size_t trace_cap = 0;         // doubles
     int variant = 0, bz = 0;      // step configuration (0 = unfused)
+    int integrator = 0;           // lll_integrator; other than RK4 runs the per-stage tableau path
+    State Kt[6]{};                // stage increments of the tableau path
     int cur = 0;                  // 0: state in s, 1: state in alt
     // kernel timing of fused steps without kick: a ring of event pairs that the
     // launches record themselves; a pair still in flight is skipped, so the
@@ -111,6 +113,10 @@ struct Engine {
         fr(yA.x); fr(yA.y); fr(yA.z);
         fr(yB.x); fr(yB.y); fr(yB.z);
         fr(acc.x); fr(acc.y); fr(acc.z);
+        for (State& k : Kt) {
+            fr(k.x); fr(k.y); fr(k.z);
+            k = State{};
+        }
         fr(dreps); fr(d_blk_rep); fr(d_oblk_rep); fr(d_tiles); fr(d_partials); fr(d_result);
         fr(d_accum); fr(d_kickdev); fr(d_trace); fr(d_kickpart);
         s = alt = yA = yB = acc = State{};
@@ -261,6 +267,49 @@ lll_status ensure_unfused_scratch(Engine& E) {
     return LLL_OK;
 }
 
+// Tableaus of the integrators of the Appendix besides RK4 (which has its own
+// fused kernel): RK2 midpoint and Butcher's six-stage fifth-order method.
+Tableau tableau_of(int integrator) {
+    Tableau tb{};
+    if (integrator == LLL_RK2MID) {
+        tb.stages = 2;
+        tb.a[1][0] = 0.5;
+        tb.b[1] = 1.0;
+    } else if (integrator == LLL_RK5B) {
+        tb.stages = 6;
+        tb.a[1][0] = 0.25;
+        tb.a[2][0] = 0.125;
+        tb.a[2][1] = 0.125;
+        tb.a[3][1] = -0.5;
+        tb.a[3][2] = 1.0;
+        tb.a[4][0] = 3.0 / 16.0;
+        tb.a[4][3] = 9.0 / 16.0;
+        tb.a[5][0] = -3.0 / 7.0;
+        tb.a[5][1] = 2.0 / 7.0;
+        tb.a[5][2] = 12.0 / 7.0;
+        tb.a[5][3] = -12.0 / 7.0;
+        tb.a[5][4] = 8.0 / 7.0;
+        tb.b[0] = 7.0 / 90.0;
+        tb.b[2] = 32.0 / 90.0;
+        tb.b[3] = 12.0 / 90.0;
+        tb.b[4] = 32.0 / 90.0;
+        tb.b[5] = 7.0 / 90.0;
+    }  // anything else: no stages (rejected by the launcher)
+    return tb;
+}
+
+lll_status ensure_tableau_scratch(Engine& E, int stages, KSet& ks) {
+    lll_status s;
+    if ((s = alloc_state(E, E.yA)) != LLL_OK) return s;
+    if ((s = alloc_state(E, E.yB)) != LLL_OK) return s;
+    ks = KSet{};
+    for (int j = 0; j + 1 < stages; ++j) {
+        if ((s = alloc_state(E, E.Kt[j])) != LLL_OK) return s;
+        ks.K[j] = E.Kt[j];
+    }
+    return LLL_OK;
+}
+
 // z-chunk of the fused kernel: the configured one, else 16 planes (fp32) or
 // 32 planes (fp64, whose tiles are smaller in x and y).
 int eff_bz(const Engine& E) { return E.bz > 0 ? E.bz : (E.prec == 0 ? 32 : 16); }
@@ -367,6 +416,22 @@ lll_status kick_flush(Engine& E) {
 
 lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sigma_override) {
     if (n <= 0) return LLL_OK;
+    if (E.integrator != LLL_RK4) {
+        const Tableau tb = tableau_of(E.integrator);
+        KSet ks;
+        lll_status s = ensure_tableau_scratch(E, tb.stages, ks);
+        if (s != LLL_OK) return s;
+        for (int64_t q = 0; q < n; ++q)
+            HIP_TRY(launch_step_tableau(E.prec, E.precession, E.anis, E.dreps, E.d_blk_rep, E.nblk,
+                                        tb, cur_state(E), E.yA, E.yB, ks, E.st));
+        if (kick_last) {
+            if ((s = kick_flush(E)) != LLL_OK) return s;
+            HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k,
+                                sigma_override, E.d_kickpart, E.st));
+            E.kick_pending = 0;
+        }
+        return LLL_OK;
+    }
     if (E.variant == 0 || E.anis == ANIS_SITE) {
         lll_status s = ensure_unfused_scratch(E);
         if (s != LLL_OK) return s;
@@ -498,7 +563,8 @@ static lll_status lattice_params(lll_lattice* L, const lll_params* p, bool need_
     ph.e_site = p->e_site;
     lll_status s = check_phys(ph);
     if (s != LLL_OK) return s;
-    if (p->integrator != LLL_RK4) return set_err(LLL_EUNSUPPORTED, "only LLL_RK4 is implemented");
+    if (p->integrator != LLL_RK4 && p->integrator != LLL_RK2MID && p->integrator != LLL_RK5B)
+        return set_err(LLL_EINVAL, "unknown integrator %d", (int)p->integrator);
     if (!(p->dt > 0) || !is_fin(p->dt)) return set_err(LLL_EINVAL, "dt must be positive");
     double Dt = p->Dt;
     if (need_schedule) {
@@ -511,13 +577,14 @@ static lll_status lattice_params(lll_lattice* L, const lll_params* p, bool need_
     const int prec = p->precession ? 1 : 0;
     const bool same = L->have_params && memcmp(&ph, &L->phys, sizeof ph) == 0 && L->dt == p->dt &&
                       L->Dt == Dt && L->precession == prec && L->seed == p->seed &&
-                      L->replica == p->replica;
+                      L->replica == p->replica && L->E.integrator == p->integrator;
     if (same) return LLL_OK;
     Engine& E = L->E;
     RepDev& R = E.hreps[0];
     fill_physics(R, ph, p->dt, Dt, prec, p->seed, p->replica);
     E.precession = prec;
     E.anis = anis_mode_of(ph);
+    E.integrator = p->integrator;
     if ((s = upload_reps(E)) != LLL_OK) return s;
     L->phys = ph;
     L->dt = p->dt;
@@ -974,6 +1041,8 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
                                   void* g_D, void* g_s0) {
     if (!L || !loss || !g_H || !g_J || !g_D || !wm) return set_err(LLL_EINVAL, "NULL argument");
     if (n_pulses < 0 || ckpt_every < 1) return set_err(LLL_EINVAL, "bad n_pulses or ckpt_every");
+    if (p && p->integrator != LLL_RK4)
+        return set_err(LLL_EUNSUPPORTED, "the adjoint is implemented for LLL_RK4 only");
     lll_status s = lattice_params(L, p, true);
     if (s != LLL_OK) return s;
     Engine& E = L->E;

@@ -65,6 +65,22 @@ hipError_t launch_step_unfused(int prec, int precession, int anis, const RepDev*
                                State acc, hipStream_t st);
 hipError_t launch_copy(int prec, State dst, State src, int64_t n, hipStream_t st);
 
+// Explicit Runge-Kutta tableau of up to six stages: stage j's input is
+// x + sum_{l<j} a[j][l] k_l, the step is x + sum_l b[l] k_l (k_l = dt f).
+struct Tableau {
+    int stages;
+    double a[6][6];
+    double b[6];
+};
+// Scratch arrays of the stage increments k_0 .. k_{stages-2}.
+struct KSet {
+    State K[6];
+};
+// One step of the tableau with one launch per stage (yA, yB: stage-input scratch).
+hipError_t launch_step_tableau(int prec, int precession, int anis, const RepDev* reps,
+                               const int32_t* blk_rep, int nblk, const Tableau& tb, State s,
+                               State yA, State yB, const KSet& ks, hipStream_t st);
+
 // Fused RK4 step (one launch per step, z-marching LDS tiles).
 struct FusedInfo {
     int bx, by, threads, lds_bytes;

@@ -508,3 +508,44 @@ def test_kick_maximum_same_on_every_fold_path(P, prec):
     lat.run(gp, first_pulse=0, n_pulses=1)
     assert lat.kick_norm_dev() == pytest.approx(dev, **tol)
     lat.close()
+
+
+# ------------------------------------------------- other integrators (RK2, RK5) ---
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", ["rk2mid", "rk5b"])
+@pytest.mark.parametrize("kind,precession", [("zaxis", True), ("axis", True), ("none", False)])
+@pytest.mark.parametrize("shape,bc", [((40, 24, 20), "periodic"), ((17, 5, 3), "free")])
+def test_integrator_per_segment(P, prec, method, kind, precession, shape, bc):
+    """RK2 midpoint and Butcher's RK5 (Appendix) inside the pulse schedule:
+    each interval (2 steps, kick, 3 steps) against the oracle's steppers and
+    kick started from the GPU's state before it."""
+    op, _ = both_params(kind, dt=0.1, Dt=0.5, precession=precession)
+    kw = dict(PHYS[kind])
+    gp = P.Params(seed=13, dt=0.1, Dt=0.5, precession=precession, integrator=method, **kw)
+    lat = P.Lattice(shape, bc=bc, precision=prec, init="random", seed=2)
+    g = orc.geom(shape, bc)
+    prev = np_state(lat)
+    for q in range(2):
+        lat.run(gp, first_pulse=q, n_pulses=1)
+        cur = np_state(lat)
+        want = orc.step(g, op, prev, 2, method=method)
+        want, _ = orc.kick(g, op, want, op.T, seed=13, r=0, k=q)
+        want = orc.step(g, op, want, 3, method=method)
+        err = np.max(np.abs(cur - want))
+        assert err < TOL[prec], (q, err)
+        prev = cur
+    # the step alone
+    lat.step(gp, 3)
+    want = orc.step(g, op, prev, 3, method=method)
+    assert np.max(np.abs(np_state(lat) - want)) < TOL[prec]
+    lat.close()
+
+
+def test_integrator_rejections(P):
+    shape = (8, 8, 8)
+    lat = P.Lattice(shape, precision="fp64", init="random", seed=2)
+    gp = P.Params(J=1.0, lam=0.01, T=0.5, dt=0.1, Dt=0.5, seed=1, integrator="rk5b")
+    with pytest.raises(P.LLLError) as ei:
+        lat.adjoint(gp, 0, 1, ckpt_every=5, wE=1.0, wm=(0, 0, 0))
+    assert ei.value.status == P.LLL_EUNSUPPORTED
+    lat.close()

@@ -185,7 +185,7 @@ lll_status lll_step_variant_info(lll_precision prec, int32_t variant, int32_t* o
  * and the kick-deviation maximum are restored.  cache_path (optional) is a
  * text file of "key variant bz kick_fused" lines (a missing fourth field means
  * fused) that is read first and updated; the key is the shape, precision,
- * boundary, precession and anisotropy mode.  *chosen_variant and *chosen_bz
+ * boundary, precession, anisotropy mode and integrator.  *chosen_variant and *chosen_bz
  * may be NULL. */
 lll_status lll_autotune(lll_lattice* lat, const lll_params* params, const char* cache_path,
                         int32_t* chosen_variant, int32_t* chosen_bz);

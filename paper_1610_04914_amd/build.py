@@ -13,7 +13,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblll.so")
-SOURCES = ["kern_fused_f32.hip", "kern_fused_f64.hip", "lll_api.hip", "kern_basic.hip", "kern_adjoint.hip"]
+SOURCES = ["kern_fused_f32.hip", "kern_fused_f64.hip", "kern_fused_rk2_f32.hip",
+           "kern_fused_rk2_f64.hip", "lll_api.hip", "kern_basic.hip", "kern_adjoint.hip"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
@@ -30,7 +31,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 7) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     cc = hipcc()

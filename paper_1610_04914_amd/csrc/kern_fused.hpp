@@ -121,7 +121,11 @@ __device__ __forceinline__ void stage_at(const T* L0, const T* L1, const T* L2, 
     stage_k<T, PREC, ANIS>(c[0], c[1], c[2], nx, ny, nz, C, Di, ex, ey, ez, kx, ky, kz);
 }
 
-template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, bool KICK>
+// SCHEME 0: one classical RK4 step.  SCHEME 1: two RK2-midpoint steps, whose
+// four stage evaluations have the same dependency depth (y2 = x + k1/2,
+// x1 = x + k2, y4 = x1 + k3/2, x2 = x1 + k4).  SCHEME 2: one RK2-midpoint step
+// (stages 1 and 2 only; x1 is the output).
+template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, bool KICK, int SCHEME>
 __global__ void __launch_bounds__(NT)
     rk4_fused_kernel(const RepDev* __restrict__ reps, const int4* __restrict__ tiles, State in,
                      State out, int bz_arg, uint64_t kpulse, double sigma_override,
@@ -334,7 +338,7 @@ __global__ void __launch_bounds__(NT)
                         Y2[j][u1][0] = kx * c2 + X[j][u1][0];
                         Y2[j][u1][1] = ky * c2 + X[j][u1][1];
                         Y2[j][u1][2] = kz * c2 + X[j][u1][2];
-                        if (j * NT < R4) {
+                        if (SCHEME == 0 && j * NT < R4) {
                             A[j][u1][0] = kx * c6 + X[j][u1][0];
                             A[j][u1][1] = ky * c6 + X[j][u1][1];
                             A[j][u1][2] = kz * c6 + X[j][u1][2];
@@ -358,15 +362,21 @@ __global__ void __launch_bounds__(NT)
                         site_aniso(j, P - 2, Di, ex, ey, ez);
                         stage_at<T, PREC, ANIS, W1>(sA2[sl][0], sA2[sl][1], sA2[sl][2], r2[j], Y2[j][u2],
                                                     Y2[j][u3], Y2[j][u1], C, Di, ex, ey, ez, kx, ky, kz);
-                        Y3[j][u2][0] = kx * c2 + X[j][u2][0];
-                        Y3[j][u2][1] = ky * c2 + X[j][u2][1];
-                        Y3[j][u2][2] = kz * c2 + X[j][u2][2];
-                        if (j * NT < R4) {
-                            A[j][u2][0] = kx * c3 + A[j][u2][0];
-                            A[j][u2][1] = ky * c3 + A[j][u2][1];
-                            A[j][u2][2] = kz * c3 + A[j][u2][2];
+                        if constexpr (SCHEME == 0) {
+                            Y3[j][u2][0] = kx * c2 + X[j][u2][0];
+                            Y3[j][u2][1] = ky * c2 + X[j][u2][1];
+                            Y3[j][u2][2] = kz * c2 + X[j][u2][2];
+                            if (j * NT < R4) {
+                                A[j][u2][0] = kx * c3 + A[j][u2][0];
+                                A[j][u2][1] = ky * c3 + A[j][u2][1];
+                                A[j][u2][2] = kz * c3 + A[j][u2][2];
+                            }
+                        } else {  // x1 = x + k2
+                            Y3[j][u2][0] = kx + X[j][u2][0];
+                            Y3[j][u2][1] = ky + X[j][u2][1];
+                            Y3[j][u2][2] = kz + X[j][u2][2];
                         }
-                        if (LLL_ITEM_LANE_IN(j, R2)) {
+                        if (SCHEME != 2 && LLL_ITEM_LANE_IN(j, R2)) {
                             sA3[sl][0][o3[j]] = Y3[j][u2][0];
                             sA3[sl][1][o3[j]] = Y3[j][u2][1];
                             sA3[sl][2][o3[j]] = Y3[j][u2][2];
@@ -375,7 +385,7 @@ __global__ void __launch_bounds__(NT)
                 }
             }
             // ---- stage 3 on plane P-3 (region R3); y4 = x + k3, acc += k3/3
-            if (F == 2 || 4 * F + u >= 2 * 3) {
+            if (SCHEME != 2 && (F == 2 || 4 * F + u >= 2 * 3)) {
                 const int sl = (t - 3) & 1;
 #pragma unroll
                 for (int j = 0; j < NI; ++j) {
@@ -385,13 +395,19 @@ __global__ void __launch_bounds__(NT)
                         site_aniso(j, P - 3, Di, ex, ey, ez);
                         stage_at<T, PREC, ANIS, W2>(sA3[sl][0], sA3[sl][1], sA3[sl][2], r3[j], Y3[j][u3],
                                                     Y3[j][u], Y3[j][u2], C, Di, ex, ey, ez, kx, ky, kz);
-                        Y4[j][u3][0] = kx + X[j][u3][0];
-                        Y4[j][u3][1] = ky + X[j][u3][1];
-                        Y4[j][u3][2] = kz + X[j][u3][2];
-                        if (j * NT < R4) {
-                            A[j][u3][0] = kx * c3 + A[j][u3][0];
-                            A[j][u3][1] = ky * c3 + A[j][u3][1];
-                            A[j][u3][2] = kz * c3 + A[j][u3][2];
+                        if constexpr (SCHEME == 0) {
+                            Y4[j][u3][0] = kx + X[j][u3][0];
+                            Y4[j][u3][1] = ky + X[j][u3][1];
+                            Y4[j][u3][2] = kz + X[j][u3][2];
+                            if (j * NT < R4) {
+                                A[j][u3][0] = kx * c3 + A[j][u3][0];
+                                A[j][u3][1] = ky * c3 + A[j][u3][1];
+                                A[j][u3][2] = kz * c3 + A[j][u3][2];
+                            }
+                        } else {  // y4 = x1 + k3/2
+                            Y4[j][u3][0] = kx * c2 + Y3[j][u3][0];
+                            Y4[j][u3][1] = ky * c2 + Y3[j][u3][1];
+                            Y4[j][u3][2] = kz * c2 + Y3[j][u3][2];
                         }
                         if (LLL_ITEM_LANE_IN(j, R3)) {
                             sA4[sl][0][o4[j]] = Y4[j][u3][0];
@@ -410,13 +426,27 @@ __global__ void __launch_bounds__(NT)
                 for (int j = 0; j < NI; ++j) {
                     if (j * NT >= R4) continue;
                     if (LLL_ITEM_WAVE_IN(j, R4)) {
-                        T Di, ex, ey, ez, kx, ky, kz;
-                        site_aniso(j, gz, Di, ex, ey, ez);
-                        stage_at<T, PREC, ANIS, W3>(sA4[sl][0], sA4[sl][1], sA4[sl][2], r4[j], Y4[j][u],
-                                                    Y4[j][u1], Y4[j][u3], C, Di, ex, ey, ez, kx, ky, kz);
-                        T rx = kx * c6 + A[j][u][0];
-                        T ry = ky * c6 + A[j][u][1];
-                        T rz = kz * c6 + A[j][u][2];
+                        T rx, ry, rz;
+                        if constexpr (SCHEME == 2) {  // output x1
+                            rx = Y3[j][u][0];
+                            ry = Y3[j][u][1];
+                            rz = Y3[j][u][2];
+                        } else {
+                            T Di, ex, ey, ez, kx, ky, kz;
+                            site_aniso(j, gz, Di, ex, ey, ez);
+                            stage_at<T, PREC, ANIS, W3>(sA4[sl][0], sA4[sl][1], sA4[sl][2], r4[j],
+                                                        Y4[j][u], Y4[j][u1], Y4[j][u3], C, Di, ex,
+                                                        ey, ez, kx, ky, kz);
+                            if constexpr (SCHEME == 0) {
+                                rx = kx * c6 + A[j][u][0];
+                                ry = ky * c6 + A[j][u][1];
+                                rz = kz * c6 + A[j][u][2];
+                            } else {  // x2 = x1 + k4
+                                rx = kx + Y3[j][u][0];
+                                ry = ky + Y3[j][u][1];
+                                rz = kz + Y3[j][u][2];
+                            }
+                        }
                         if (zst && outok[j]) {
                             const int64_t g = (int64_t)col[j] + plane * gz;
                             if constexpr (KICK) {
@@ -466,42 +496,81 @@ __global__ void __launch_bounds__(NT)
     }
 }
 
-template <typename T, int BX, int BY, int NT, bool PREC, int ANIS>
+template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, int SCHEME>
 inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, State in, State out,
                            int bz, int kick, uint64_t k, double so, double* kd,
                            const LaunchEvents* ev, hipStream_t st) {
     if (kick)
-        hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, true>), dim3(ntiles), dim3(NT),
-                           0, st, reps, tiles, in, out, bz, k, so, kd);
+        hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, true, SCHEME>), dim3(ntiles),
+                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd);
     else if (ev)  // start/stop events taken from the dispatch itself
-        hipExtLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false>), dim3(ntiles),
-                              dim3(NT), 0, st, ev->start, ev->stop, 0, reps, tiles, in, out, bz, k,
-                              so, kd);
+        hipExtLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false, SCHEME>),
+                              dim3(ntiles), dim3(NT), 0, st, ev->start, ev->stop, 0, reps, tiles, in,
+                              out, bz, k, so, kd);
     else
-        hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false>), dim3(ntiles),
+        hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false, SCHEME>), dim3(ntiles),
                            dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd);
     return hipGetLastError();
 }
 
-template <typename T, int BX, int BY, int NT, bool PREC>
+template <typename T, int BX, int BY, int NT, bool PREC, int SCHEME>
 inline hipError_t launch_a(int anis, const RepDev* reps, const int4* tiles, int ntiles, State in,
                            State out, int bz, int kick, uint64_t k, double so,
                            double* kd, const LaunchEvents* ev, hipStream_t st) {
     switch (anis) {
-        case ANIS_NONE: return launch_v<T, BX, BY, NT, PREC, ANIS_NONE>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case ANIS_Z: return launch_v<T, BX, BY, NT, PREC, ANIS_Z>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case ANIS_AXIS: return launch_v<T, BX, BY, NT, PREC, ANIS_AXIS>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+        case ANIS_NONE: return launch_v<T, BX, BY, NT, PREC, ANIS_NONE, SCHEME>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+        case ANIS_Z: return launch_v<T, BX, BY, NT, PREC, ANIS_Z, SCHEME>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+        case ANIS_AXIS: return launch_v<T, BX, BY, NT, PREC, ANIS_AXIS, SCHEME>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
         default: return hipErrorInvalidValue;  // per-site anisotropy runs on the unfused step
     }
 }
 
-template <typename T, int BX, int BY, int NT>
+template <typename T, int BX, int BY, int NT, int SCHEME>
 inline hipError_t launch_p(int precession, int anis, const RepDev* reps, const int4* tiles,
                            int ntiles, State in, State out, int bz, int kick, uint64_t k,
                            double so, double* kd, const LaunchEvents* ev, hipStream_t st) {
     if (precession)
-        return launch_a<T, BX, BY, NT, true>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-    return launch_a<T, BX, BY, NT, false>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+        return launch_a<T, BX, BY, NT, true, SCHEME>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+    return launch_a<T, BX, BY, NT, false, SCHEME>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
 }
+
+// Tile variants (bx, by, threads) by precision, for one scheme.  The same
+// lists give the variant table (kern_fused_f32.hip).
+#define LLL_FUSED_ARGS                                                                    \
+    int precession, int anis, int variant, int bz, const RepDev *reps, const int4 *tiles, \
+        int ntiles, State in, State out, int kick, uint64_t k, double so, double *kd,     \
+        const LaunchEvents *ev, hipStream_t st
+#define LLL_FUSED_PASS precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st
+
+template <int SCHEME>
+inline hipError_t fused_f32(LLL_FUSED_ARGS) {
+    switch (variant) {
+        case 1: return launch_p<float, 32, 16, 960, SCHEME>(LLL_FUSED_PASS);
+        case 2: return launch_p<float, 32, 16, 512, SCHEME>(LLL_FUSED_PASS);
+        case 3: return launch_p<float, 16, 16, 576, SCHEME>(LLL_FUSED_PASS);
+        case 4: return launch_p<float, 32, 8, 640, SCHEME>(LLL_FUSED_PASS);
+        case 5: return launch_p<float, 64, 8, 512, SCHEME>(LLL_FUSED_PASS);
+        case 6: return launch_p<float, 32, 16, 1024, SCHEME>(LLL_FUSED_PASS);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int SCHEME>
+inline hipError_t fused_f64(LLL_FUSED_ARGS) {
+    switch (variant) {
+        case 1: return launch_p<double, 32, 8, 640, SCHEME>(LLL_FUSED_PASS);
+        case 2: return launch_p<double, 16, 16, 576, SCHEME>(LLL_FUSED_PASS);
+        case 3: return launch_p<double, 16, 16, 256, SCHEME>(LLL_FUSED_PASS);
+        case 4: return launch_p<double, 32, 8, 256, SCHEME>(LLL_FUSED_PASS);
+        case 5: return launch_p<double, 16, 8, 384, SCHEME>(LLL_FUSED_PASS);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// One function per translation unit (schemes are split across them).
+hipError_t fused_f32_rk4(LLL_FUSED_ARGS);
+hipError_t fused_f64_rk4(LLL_FUSED_ARGS);
+hipError_t fused_f32_rk2(int scheme, LLL_FUSED_ARGS);
+hipError_t fused_f64_rk2(int scheme, LLL_FUSED_ARGS);
 
 }  // namespace lll

@@ -35,28 +35,18 @@ bool fused_variant_info(int prec, int variant, FusedInfo* out) {
     return true;
 }
 
-hipError_t launch_step_fused_f64(int precession, int anis, int variant, int bz, const RepDev* reps,
-                                 const int4* tiles, int ntiles, State in, State out, int kick,
-                                 uint64_t k, double so, double* kd, const LaunchEvents* ev,
-                                 hipStream_t st);
+hipError_t fused_f32_rk4(LLL_FUSED_ARGS) { return fused_f32<0>(precession, anis, variant, bz, reps, tiles, ntiles, in, out, kick, k, so, kd, ev, st); }
 
-hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz,
+hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz, int scheme,
                              const RepDev* reps, const int4* tiles, int ntiles, State in,
                              State out, int kick, uint64_t k, double so,
                              double* kd, const LaunchEvents* ev, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    if (prec == 0)
-        return launch_step_fused_f64(precession, anis, variant, bz, reps, tiles, ntiles, in, out,
-                                     kick, k, so, kd, ev, st);
-    switch (variant) {
-        case 1: return launch_p<float, 32, 16, 960>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case 2: return launch_p<float, 32, 16, 512>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case 3: return launch_p<float, 16, 16, 576>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case 4: return launch_p<float, 32, 8, 640>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case 5: return launch_p<float, 64, 8, 512>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case 6: return launch_p<float, 32, 16, 1024>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        default: return hipErrorInvalidValue;
-    }
+    if (scheme == 0)
+        return prec == 0 ? fused_f64_rk4(precession, anis, variant, bz, reps, tiles, ntiles, in, out, kick, k, so, kd, ev, st)
+                         : fused_f32_rk4(precession, anis, variant, bz, reps, tiles, ntiles, in, out, kick, k, so, kd, ev, st);
+    return prec == 0 ? fused_f64_rk2(scheme, precession, anis, variant, bz, reps, tiles, ntiles, in, out, kick, k, so, kd, ev, st)
+                     : fused_f32_rk2(scheme, precession, anis, variant, bz, reps, tiles, ntiles, in, out, kick, k, so, kd, ev, st);
 }
 
 }  // namespace lll

@@ -3,18 +3,6 @@
 
 namespace lll {
 
-hipError_t launch_step_fused_f64(int precession, int anis, int variant, int bz, const RepDev* reps,
-                                 const int4* tiles, int ntiles, State in, State out, int kick,
-                                 uint64_t k, double so, double* kd, const LaunchEvents* ev,
-                                 hipStream_t st) {
-    switch (variant) {
-        case 1: return launch_p<double, 32, 8, 640>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case 2: return launch_p<double, 16, 16, 576>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case 3: return launch_p<double, 16, 16, 256>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case 4: return launch_p<double, 32, 8, 256>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        case 5: return launch_p<double, 16, 8, 384>(precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        default: return hipErrorInvalidValue;
-    }
-}
+hipError_t fused_f64_rk4(LLL_FUSED_ARGS) { return fused_f64<0>(precession, anis, variant, bz, reps, tiles, ntiles, in, out, kick, k, so, kd, ev, st); }
 
 }  // namespace lll

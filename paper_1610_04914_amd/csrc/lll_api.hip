@@ -416,7 +416,8 @@ lll_status kick_flush(Engine& E) {
 
 lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sigma_override) {
     if (n <= 0) return LLL_OK;
-    if (E.integrator != LLL_RK4) {
+    const bool fused_ok = E.variant != 0 && E.anis != ANIS_SITE;
+    if (E.integrator == LLL_RK5B || (E.integrator == LLL_RK2MID && !fused_ok)) {
         const Tableau tb = tableau_of(E.integrator);
         KSet ks;
         lll_status s = ensure_tableau_scratch(E, tb.stages, ks);
@@ -432,7 +433,7 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
         }
         return LLL_OK;
     }
-    if (E.variant == 0 || E.anis == ANIS_SITE) {
+    if (!fused_ok) {
         lll_status s = ensure_unfused_scratch(E);
         if (s != LLL_OK) return s;
         for (int64_t q = 0; q < n; ++q)
@@ -449,16 +450,24 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
     lll_status s = alloc_state(E, E.alt);
     if (s != LLL_OK) return s;
     if ((s = ensure_tiles(E)) != LLL_OK) return s;
-    for (int64_t q = 0; q < n; ++q) {
-        const bool kk = kick_last && q == n - 1 && E.kick_epilogue;
+    // RK4: one step per launch.  RK2 midpoint: two steps per launch, and one
+    // single-step launch when the count is odd.
+    for (int64_t q = 0; q < n;) {
+        int scheme = 0, adv = 1;
+        if (E.integrator == LLL_RK2MID) {
+            scheme = n - q >= 2 ? 1 : 2;
+            adv = n - q >= 2 ? 2 : 1;
+        }
+        const bool kk = kick_last && q + adv == n && E.kick_epilogue;
         if (kk && (s = kick_flush(E)) != LLL_OK) return s;
         State in = cur_state(E);
         State out = E.cur ? E.s : E.alt;
-        HIP_TRY(launch_step_fused(E.prec, E.precession, E.anis, E.variant, eff_bz(E), E.dreps, E.d_tiles,
-                                  E.ntiles, in, out, kk ? 1 : 0, k, sigma_override, E.d_kickpart,
-                                  kk ? nullptr : kt_take(E), E.st));
+        HIP_TRY(launch_step_fused(E.prec, E.precession, E.anis, E.variant, eff_bz(E), scheme,
+                                  E.dreps, E.d_tiles, E.ntiles, in, out, kk ? 1 : 0, k,
+                                  sigma_override, E.d_kickpart, kk ? nullptr : kt_take(E), E.st));
         if (kk) E.kick_pending = 1;
         E.cur ^= 1;
+        q += adv;
     }
     if (kick_last && !E.kick_epilogue) {
         if ((s = kick_flush(E)) != LLL_OK) return s;
@@ -1002,8 +1011,9 @@ extern "C" lll_status lll_autotune(lll_lattice* L, const lll_params* p, const ch
     lll_status s = lattice_params(L, p, false);
     if (s != LLL_OK) return s;
     char buf[200];
-    snprintf(buf, sizeof buf, "L%dx%dx%d_bc%d_%s_prec%d_anis%d", L->Lx, L->Ly, L->Lz, L->bc,
-             L->E.prec == 0 ? "fp64" : "fp32", L->E.precession, L->E.anis);
+    snprintf(buf, sizeof buf, "L%dx%dx%d_bc%d_%s_prec%d_anis%d%s", L->Lx, L->Ly, L->Lz, L->bc,
+             L->E.prec == 0 ? "fp64" : "fp32", L->E.precession, L->E.anis,
+             L->E.integrator == LLL_RK2MID ? "_rk2" : L->E.integrator == LLL_RK5B ? "_rk5" : "");
     int64_t n = 0;
     if (steps_per_interval(L->dt, L->Dt, &n) != LLL_OK) n = 0;
     return engine_autotune(L->E, buf, L->Lz, n, cache_path, chosen_variant, chosen_bz);

@@ -95,7 +95,8 @@ struct LaunchEvents {
 // tile's maximum of | |s'| - 1 | to kickpart[tile0 + tile]; sigma_override >= 0
 // replaces every replica's kick scale.  ev (optional, steps without kick only)
 // times the launch.
-hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz,
+// scheme: 0 one RK4 step, 1 two RK2-midpoint steps, 2 one RK2-midpoint step.
+hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz, int scheme,
                              const RepDev* reps, const int4* tiles, int ntiles, State in,
                              State out, int kick, uint64_t k, double sigma_override,
                              double* kickpart, const LaunchEvents* ev, hipStream_t st);

@@ -549,3 +549,38 @@ def test_integrator_rejections(P):
         lat.adjoint(gp, 0, 1, ckpt_every=5, wE=1.0, wm=(0, 0, 0))
     assert ei.value.status == P.LLL_EUNSUPPORTED
     lat.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind,precession", [("zaxis", True), ("axis", False)])
+def test_rk2_fused_all_variants(P, prec, kind, precession):
+    """Fused RK2 midpoint (two steps per launch, plus a one-step launch for an
+    odd count) in every tile shape and z-chunk, against the oracle's stepper;
+    and one interval (2 steps with the kick epilogue, then 3 steps)."""
+    op, _ = both_params(kind, dt=0.1, Dt=0.5, precession=precession)
+    gp = P.Params(seed=31, dt=0.1, Dt=0.5, precession=precession, integrator="rk2mid", **PHYS[kind])
+    for shape, bc, bz in STEP_SHAPES:
+        N = int(np.prod(shape))
+        s0 = rounded(inputs.unit_spins(N, 200 + N), prec)
+        g = orc.geom(shape, bc)
+        for nst in (3, 4):
+            want = orc.step(g, op, s0, nst, method="rk2mid")
+            for v in variants(P, prec):
+                lat = make_lattice(P, shape, bc, prec, s0)
+                lat.set_step_config(v, bz)
+                lat.step(gp, nst)
+                err = np.max(np.abs(np_state(lat) - want))
+                assert err < TOL[prec], (shape, bc, v, bz, nst, err)
+                lat.close()
+        want = orc.step(g, op, s0, 2, method="rk2mid")
+        want, _ = orc.kick(g, op, want, op.T, seed=31, r=0, k=9)
+        want = orc.step(g, op, want, 3, method="rk2mid")
+        for v in variants(P, prec):
+            for fused in (True, False):
+                lat = make_lattice(P, shape, bc, prec, s0)
+                lat.set_step_config(v, bz)
+                lat.set_kick_fusion(fused)
+                lat.run(gp, first_pulse=9, n_pulses=1)
+                err = np.max(np.abs(np_state(lat) - want))
+                assert err < TOL[prec], (shape, bc, v, bz, fused, err)
+                lat.close()

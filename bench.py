@@ -258,6 +258,38 @@ def extra_overdamped(n_pulses: int = 5000):
             "final_abs_m": float(np.linalg.norm(tr[-1]["m"]))}
 
 
+def extra_integrators(n_pulses: int = 50):
+    """The headline lattice and physics (128^3 fp32, precession, dt = 0.2,
+    Dt = 2) stepped with each integrator of the Appendix: classical RK4 (one
+    fused launch per step), RK2 midpoint (two steps per fused launch) and
+    Butcher's RK5 (one launch per stage).  Spin-steps/s over n_pulses
+    intervals with observables, and the mean kernel time of the fused step
+    launches of an even run of steps (RK4: one step, RK2: two steps)."""
+    import torch
+    import paper_1610_04914_amd as P
+    out = {}
+    for method in ("rk4", "rk2mid", "rk5b"):
+        p = P.Params(**dict(PHYS, integrator=method))
+        lat = P.Lattice(SHAPE, precision="fp32", init="random", seed=0)
+        lat.autotune(p, cache_path=TUNE_CACHE)
+        lat.run(p, first_pulse=0, n_pulses=3, obs_every=1)
+        el, _ = _timed(lambda: lat.run(p, first_pulse=3, n_pulses=n_pulses, obs_every=1))
+        n = int(round(PHYS["Dt"] / PHYS["dt"]))
+        rec = {"spin_steps_per_s": lat.N * n * n_pulses / el, "pulses": n_pulses}
+        if method != "rk5b":
+            lat.kernel_timing_start()
+            lat.step(p, 40)
+            ms, nt = lat.kernel_timing_stop()
+            steps_per_launch = 2 if method == "rk2mid" else 1
+            rec["fused_launch_us"] = ms * 1e3
+            rec["steps_per_launch"] = steps_per_launch
+            rec["launches_timed"] = nt
+        out[method] = rec
+        lat.close()
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,7 +386,7 @@ def main():
     }
     if args.extras:
         out["extras"] = {"batched": extra_batched(), "adjoint": extra_adjoint(),
-                         "overdamped_256": extra_overdamped()}
+                         "overdamped_256": extra_overdamped(), "integrators": extra_integrators()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out))

@@ -925,7 +925,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     HIP_TRY(hipEventCreate(&e1));
     std::vector<std::pair<int, int>> cands;
     cands.push_back({0, 0});
-    if (E.anis != ANIS_SITE) {
+    if (E.anis != ANIS_SITE && E.integrator != LLL_RK5B) {  // RK5 has no fused kernel
         for (int v = 1; v <= fused_variant_count(E.prec); ++v) {
             const int bzs[] = {4, 8, 12, 16, 24, 32, 48, 64};
             for (int b : bzs)

@@ -135,6 +135,9 @@ def lib():
         L.orc_adjoint.argtypes = [G, P, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, dp, dp,
                                   C.c_double, dp, dp, dp, dp, dp, dp]
         L.orc_adjoint.restype = C.c_int
+        L.orc_escape_time.argtypes = [C.c_double] * 6 + [C.c_int32, C.c_int32, C.c_uint64,
+                                                          C.c_uint32, C.c_uint32, C.c_int64]
+        L.orc_escape_time.restype = C.c_double
         _lib = L
     return _lib
 
@@ -317,3 +320,88 @@ def adjoint(g: Geom, p: Params, s0, seed: int, r: int = 0, first_pulse: int = 0,
         raise ValueError(f"orc_adjoint failed: {rc}")
     return {"loss": float(loss[0]), "g_s0": gs0, "g_H": gH, "g_J": float(gJ[0]),
             "g_D": gD if p.D_site is not None else float(gD[0])}
+
+
+# --------------------------------------------------------------------------
+# Escape of a uniaxial spin in a transverse field (Sec. III.B)
+# --------------------------------------------------------------------------
+_METHOD = {"rk4": 0, "rk2mid": 1, "rk5b": 2}
+
+
+def escape_time(D: float, H: float, lam: float, T: float, dt: float, Dt: float, run: int,
+                seed: int = 0, r: int = 0, max_pulses: int = 10**6, method: str = "rk4",
+                precession: bool = True) -> float:
+    """First-passage time of one run (see orc_escape_time); -1 if none within
+    max_pulses intervals."""
+    return float(lib().orc_escape_time(D, H, lam, T, dt, Dt, 1 if precession else 0,
+                                       _METHOD[method], C.c_uint64(seed), r, run,
+                                       int(max_pulses)))
+
+
+def escape_F(h: float) -> float:
+    """F(h) of the low-damping escape rate (Sec. III.B), from the paper's
+    one-dimensional form: the integral over u in [0, 1] of
+    x_c/(1 - x_c^2 u^2) [u (2(1 - h) - x_c^2 u^2)^2 / sqrt(1 - u^2) + x_c sqrt(1 - u^2)],
+    x_c = 2 sqrt(h (1 - h)), evaluated with u = sin v (which removes the
+    endpoint singularity) by adaptive quadrature."""
+    from scipy.integrate import quad
+    xc = 2.0 * np.sqrt(h * (1.0 - h))
+
+    def g(v):
+        sv, cv = np.sin(v), np.cos(v)
+        # du/sqrt(1-u^2) = dv, sqrt(1-u^2) du = cos^2 v dv
+        return xc / (1.0 - xc * xc * sv * sv) * (sv * (2.0 * (1.0 - h) - xc * xc * sv * sv) ** 2
+                                                 + xc * cv * cv)
+    if h == 0.5:  # x_c = 1: 1/(1 - sin^2 v) cancels against the bracket
+        def g(v):  # noqa: F811
+            sv, cv = np.sin(v), np.cos(v)
+            return sv * cv * cv + 1.0
+    val, _ = quad(g, 0.0, np.pi / 2, epsabs=1e-13, epsrel=1e-12, limit=200)
+    return float(val)
+
+
+def escape_F_contour(h: float) -> float:
+    """F(h) from its definition as a contour integral over the separatrix
+    f(x, phi) = x^2 + 2h sqrt(1 - x^2) cos(phi) = 2h around one well (Sec.
+    III.B), x = cos(theta): one half of the closed curve, phi(x) =
+    arccos[(2h - x^2) / (2h sqrt(1 - x^2))] for x from 0 to x_c, counted twice
+    (the other half is its mirror phi -> -phi), with the factor 1/2 of the
+    definition; parametrised by the angle phi itself to avoid the endpoint
+    singularities of dphi/dx."""
+    from scipy.integrate import quad
+    from scipy.optimize import brentq
+    xc = 2.0 * np.sqrt(h * (1.0 - h))
+
+    def x_of_phi(ph):
+        # f(x, phi) = 2h on the branch x in [0, x_c]
+        c = np.cos(ph)
+        fun = lambda x: x * x + 2.0 * h * np.sqrt(max(1.0 - x * x, 0.0)) * c - 2.0 * h  # noqa: E731
+        if ph == 0.0:
+            return 0.0
+        return brentq(fun, 1e-15, xc, xtol=1e-15, rtol=1e-15, maxiter=200)
+
+    def integrand(ph):
+        x = x_of_phi(ph)
+        sq = np.sqrt(max(1.0 - x * x, 1e-300))
+        fx = 2.0 * x - 2.0 * h * x * np.cos(ph) / sq
+        fph = -2.0 * h * sq * np.sin(ph)
+        # dx/dphi from f(x(phi), phi) = const: fx dx + fph dphi = 0
+        dxdph = -fph / fx if fx != 0.0 else 0.0
+        return (1.0 - x * x) * fx - fph / (1.0 - x * x) * dxdph
+    val, _ = quad(integrand, 0.0, np.pi, epsabs=1e-11, epsrel=1e-10, limit=400)
+    return float(abs(val))
+
+
+def escape_rate_theory(D: float, H: float, lam: float, T: float, regime: str) -> float:
+    """Escape rate of Sec. III.B: Gamma = omega_0/(2 pi) A exp(-sigma (1 - h)^2),
+    sigma = D/T, omega_0 = 2 D sqrt(1 - h^2) (gamma = 1); A = 1 ("ID"),
+    A = lambda sigma F(h) ("LD") or A_LD / (1 + A_LD) ("ILD")."""
+    h = H / (2.0 * D)
+    sigma = D / T
+    w0 = 2.0 * D * np.sqrt(1.0 - h * h)
+    if regime == "ID":
+        A = 1.0
+    else:
+        ald = lam * sigma * escape_F(h)
+        A = ald if regime == "LD" else ald / (1.0 + ald)
+    return float(w0 / (2.0 * np.pi) * A * np.exp(-sigma * (1.0 - h) ** 2))

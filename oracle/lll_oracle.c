@@ -738,3 +738,54 @@ int orc_adjoint(const orc_geom* g, const orc_params* p, uint64_t seed, uint32_t 
     free(y); free(yb); free(f); free(u);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Thermally activated escape of a uniaxial spin in a transverse field      */
+/* (Sec. III.B): E = -D s_z^2 - H s_x, h = H/(2D) < 1, minima at            */
+/* sin(theta) = h, saddle at s = (1, 0, 0).                                  */
+/* ------------------------------------------------------------------------ */
+/* First-passage time of run `run`.  The spin starts at the bottom of the
+ * well with phi = 0, sin(theta) = h, i.e. s = (h, 0, sqrt(1 - h^2)), and
+ * follows the pulse-noise schedule of orc_run (n1 steps, kick, n2 steps per
+ * interval; pulses 0, 1, ...); the normals of pulse k come from counter
+ * (run, k, r, tag 0).  READING: the run stops at the first step end or kick
+ * after which s_z < 0 (the paper stops after the line s_z = 0 is crossed); the
+ * time is the number of completed steps times dt (a kick takes no time).
+ * method: 0 RK4, 1 RK2 midpoint, 2 Butcher RK5.  Returns -1 when no crossing
+ * happens within max_pulses intervals, -2 on invalid input. */
+double orc_escape_time(double D, double H, double lambda, double T, double dt, double Dt,
+                       int32_t precession, int32_t method, uint64_t seed, uint32_t r,
+                       uint32_t run, int64_t max_pulses)
+{
+    orc_geom g = {1, 1, 1, 1}; /* one site, free boundaries: no exchange */
+    orc_params p;
+    memset(&p, 0, sizeof p);
+    p.J = 0.0;
+    p.H[0] = H;
+    p.D = D;
+    p.e[2] = 1.0;
+    p.lambda = lambda;
+    p.T = T;
+    p.dt = dt;
+    p.Dt = Dt;
+    p.precession = precession;
+    int64_t n = orc_steps_per_interval(&p);
+    if (n < 1 || !(D > 0) || method < 0 || method > 2) return -2.0;
+    double hh = H / (2.0 * D);
+    if (!(hh >= 0.0 && hh < 1.0)) return -2.0;
+    double s[3] = {hh, 0.0, sqrt(1.0 - hh * hh)};
+    int64_t n1 = n / 2;
+    for (int64_t k = 0; k < max_pulses; ++k) {
+        for (int64_t q = 0; q < n; ++q) {
+            if (q == n1) {
+                orc_kick_indexed(&g, &p, T, seed, r, (uint64_t)k, &run, s);
+                if (s[2] < 0.0) return (double)(k * n + q) * dt;
+            }
+            if (method == 0) orc_step_rk4(&g, &p, s, 1);
+            else if (method == 1) orc_step_rk2mid(&g, &p, s, 1);
+            else orc_step_rk5b(&g, &p, s, 1);
+            if (s[2] < 0.0) return (double)(k * n + q + 1) * dt;
+        }
+    }
+    return -1.0;
+}

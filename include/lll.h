@@ -236,6 +236,39 @@ lll_status lll_batch_autotune(lll_batch* b, const char* cache_path, int32_t* cho
                               int32_t* chosen_bz);
 void lll_batch_destroy(lll_batch* b);
 
+/* ------------------------------------------------------------- escape --- */
+/* Thermally activated escape of a uniaxial spin in a transverse field
+ * (Sec. III.B): E = -D s_z^2 - H s_x with h = H/(2D) in [0, 1), minima at
+ * sin(theta) = h, saddle at s = (1, 0, 0), barrier D (1 - h)^2. */
+typedef struct {
+    double D;             /* uniaxial anisotropy along z, > 0 */
+    double H;             /* transverse field along x, 0 <= H < 2D */
+    double lambda;        /* damping, >= 0 */
+    double T;             /* temperature, >= 0 */
+    double dt;            /* integration step, > 0 */
+    double Dt;            /* pulse spacing; Dt/dt an integer n >= 1 */
+    int32_t precession;   /* 1: full Eq. (1); 0: slow equation */
+    int32_t integrator;   /* lll_integrator (the paper used LLL_RK5B) */
+    uint64_t seed;        /* Philox key of the kicks */
+    uint32_t replica;     /* Philox counter word 2 */
+    int32_t reserved;     /* set to 0 */
+} lll_escape_params;
+
+/* First-passage times of n_runs independent spins, each started at the bottom
+ * of the well (phi = 0, sin theta = h: s = (h, 0, sqrt(1 - h^2))) and run
+ * through the pulse-noise schedule (n1 = floor(n/2) steps, kick, n - n1 steps
+ * per interval, pulses 0, 1, ...; run i draws the normals of pulse k from
+ * counter (i, k, replica, 0)) until s_z < 0.  times_dev: caller-owned device
+ * array of n_runs doubles (n_runs < 2^32); entry i receives the number of
+ * completed steps times dt at the first step end or kick after which s_z < 0,
+ * or -1 if that does not happen within max_pulses intervals.  The escape rate
+ * is 1 / mean time (Sec. III.B).  Work is enqueued on hip_stream in bounded
+ * launches of a few hundred pulses; the call synchronises the stream after
+ * each one and returns once every run has escaped or max_pulses is reached.
+ * Errors: LLL_EINVAL for invalid parameters or sizes, LLL_ENOMEM, LLL_EDEVICE. */
+lll_status lll_escape_times(const lll_escape_params* p, int64_t n_runs, int64_t max_pulses,
+                            double* times_dev, void* hip_stream);
+
 /* ---------------------------------------------------------------- misc --- */
 /* Philox4x32-10 words for counters (i0 + j, c1, c2, c3), j < n, key = seed,
  * into the device array out_dev[4*n] (enqueued on hip_stream). */

@@ -56,6 +56,15 @@ class lll_obs(C.Structure):
                 "E_anis": self.E_anis, "m": tuple(self.m), "max_norm_dev": self.max_norm_dev}
 
 
+class lll_escape_params(C.Structure):
+    _fields_ = [
+        ("D", C.c_double), ("H", C.c_double), ("lambda_", C.c_double), ("T", C.c_double),
+        ("dt", C.c_double), ("Dt", C.c_double), ("precession", C.c_int32),
+        ("integrator", C.c_int32), ("seed", C.c_uint64), ("replica", C.c_uint32),
+        ("reserved", C.c_int32),
+    ]
+
+
 class lll_replica_desc(C.Structure):
     _fields_ = [
         ("Lx", C.c_int32), ("Ly", C.c_int32), ("Lz", C.c_int32), ("bc", C.c_int32),
@@ -92,6 +101,7 @@ def lib():
     L.lll_set_step_config.argtypes = [_P, C.c_int32, C.c_int32]
     L.lll_get_step_config.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.lll_set_kick_fusion.argtypes = [_P, C.c_int32]
+    L.lll_escape_times.argtypes = [C.POINTER(lll_escape_params), C.c_int64, C.c_int64, _P, _P]
     L.lll_kernel_timing.argtypes = [_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.lll_step_variant_info.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     L.lll_autotune.argtypes = [_P, pp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
@@ -519,3 +529,24 @@ def _hip_memcpy():
 def _hip_check(rc: int):
     if rc != 0:
         raise LLLError(LLL_EDEVICE, f"hipMemcpy failed with {rc}")
+
+
+def escape_times(D: float, H: float, lam: float, T: float, dt: float, Dt: float, n_runs: int,
+                 seed: int = 0, replica: int = 0, max_pulses: int = 10**6,
+                 integrator: str = "rk4", precession: bool = True):
+    """First-passage times of n_runs spins of the escape problem (Sec. III.B)
+    as a float64 CUDA tensor; -1 marks runs that did not escape within
+    max_pulses intervals (lll_escape_times)."""
+    torch = _torch()
+    p = lll_escape_params()
+    p.D, p.H, p.lambda_, p.T, p.dt, p.Dt = map(float, (D, H, lam, T, dt, Dt))
+    p.precession = 1 if precession else 0
+    p.integrator = _INTEGRATOR[integrator]
+    p.seed = int(seed)
+    p.replica = int(replica)
+    p.reserved = 0
+    out = torch.empty(int(n_runs), dtype=torch.float64, device="cuda")
+    _check(lib().lll_escape_times(C.byref(p), int(n_runs), int(max_pulses),
+                                  C.c_void_p(out.data_ptr()) if n_runs > 0 else None, _stream()),
+           "lll_escape_times")
+    return out

@@ -267,8 +267,8 @@ lll_status ensure_unfused_scratch(Engine& E) {
     return LLL_OK;
 }
 
-// Tableaus of the integrators of the Appendix besides RK4 (which has its own
-// fused kernel): RK2 midpoint and Butcher's six-stage fifth-order method.
+// Tableaus of the integrators of the Appendix: RK2 midpoint, Butcher's
+// six-stage fifth-order method and classical RK4.
 Tableau tableau_of(int integrator) {
     Tableau tb{};
     if (integrator == LLL_RK2MID) {
@@ -294,7 +294,16 @@ Tableau tableau_of(int integrator) {
         tb.b[3] = 12.0 / 90.0;
         tb.b[4] = 32.0 / 90.0;
         tb.b[5] = 7.0 / 90.0;
-    }  // anything else: no stages (rejected by the launcher)
+    } else if (integrator == LLL_RK4) {  // used by the escape runs (lattices have fused RK4)
+        tb.stages = 4;
+        tb.a[1][0] = 0.5;
+        tb.a[2][1] = 0.5;
+        tb.a[3][2] = 1.0;
+        tb.b[0] = 1.0 / 6.0;
+        tb.b[1] = 1.0 / 3.0;
+        tb.b[2] = 1.0 / 3.0;
+        tb.b[3] = 1.0 / 6.0;
+    }
     return tb;
 }
 
@@ -1381,4 +1390,61 @@ extern "C" void lll_batch_destroy(lll_batch* B) {
     if (B->E.st) (void)hipStreamSynchronize(B->E.st);
     else (void)hipDeviceSynchronize();
     delete B;
+}
+
+// ------------------------------------------------------------- escape -----
+extern "C" lll_status lll_escape_times(const lll_escape_params* p, int64_t n_runs,
+                                       int64_t max_pulses, double* times_dev, void* hip_stream) {
+    if (!p) return set_err(LLL_EINVAL, "params is NULL");
+    if (n_runs < 0 || n_runs > 0xFFFFFFFFLL) return set_err(LLL_EINVAL, "n_runs out of range");
+    if (max_pulses < 1) return set_err(LLL_EINVAL, "max_pulses < 1");
+    if (n_runs > 0 && !times_dev) return set_err(LLL_EINVAL, "times_dev is NULL");
+    if (!(p->D > 0) || !is_fin(p->D)) return set_err(LLL_EINVAL, "D must be positive");
+    const double h = p->H / (2.0 * p->D);
+    if (!(h >= 0.0 && h < 1.0)) return set_err(LLL_EINVAL, "need 0 <= H/(2D) < 1");
+    if (!(p->lambda >= 0) || !is_fin(p->lambda) || !(p->T >= 0) || !is_fin(p->T))
+        return set_err(LLL_EINVAL, "lambda and T must be finite and >= 0");
+    if (!(p->dt > 0) || !is_fin(p->dt)) return set_err(LLL_EINVAL, "dt must be positive");
+    if (p->integrator != LLL_RK4 && p->integrator != LLL_RK2MID && p->integrator != LLL_RK5B)
+        return set_err(LLL_EINVAL, "unknown integrator %d", (int)p->integrator);
+    int64_t n;
+    lll_status s = steps_per_interval(p->dt, p->Dt, &n);
+    if (s != LLL_OK) return s;
+    if (n_runs == 0) return LLL_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Phys ph{};
+    ph.J = 0.0;
+    ph.H[0] = p->H;
+    ph.D = p->D;
+    ph.e[2] = 1.0;
+    ph.lambda = p->lambda;
+    ph.T = p->T;
+    RepDev R{};
+    R.Lx = R.Ly = R.Lz = 1;
+    R.bc = 1;
+    fill_physics(R, ph, p->dt, p->Dt, p->precession ? 1 : 0, p->seed, p->replica);
+    const Tableau tb = tableau_of(p->integrator);
+    TmpAlloc tmp;
+    double* st3 = (double*)tmp.get(sizeof(double) * 3 * (size_t)n_runs);
+    unsigned int* act = (unsigned int*)tmp.get(sizeof(unsigned int));
+    if (!st3 || !act) return set_err(LLL_ENOMEM, "escape scratch allocation failed");
+    {
+        std::vector<double> neg((size_t)n_runs, -1.0);
+        HIP_TRY(hipMemcpyAsync(times_dev, neg.data(), sizeof(double) * neg.size(),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    // bounded launches: a chunk of pulses each, until every run has escaped
+    const int64_t chunk = std::max<int64_t>(1, 6000 / (n * tb.stages));
+    for (int64_t k0 = 0; k0 < max_pulses; k0 += chunk) {
+        const int64_t k1 = std::min(max_pulses, k0 + chunk);
+        HIP_TRY(hipMemsetAsync(act, 0, sizeof(unsigned int), st));
+        HIP_TRY(launch_escape(R, tb, p->precession ? 1 : 0, n_runs, n, p->dt, k0, k1, h, st3,
+                              st3 + n_runs, st3 + 2 * n_runs, times_dev, act, st));
+        unsigned int left = 0;
+        HIP_TRY(hipMemcpyAsync(&left, act, sizeof left, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (left == 0) break;
+    }
+    return LLL_OK;
 }

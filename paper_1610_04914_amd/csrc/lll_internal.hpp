@@ -81,6 +81,13 @@ hipError_t launch_step_tableau(int prec, int precession, int anis, const RepDev*
                                const int32_t* blk_rep, int nblk, const Tableau& tb, State s,
                                State yA, State yB, const KSet& ks, hipStream_t st);
 
+// Escape runs of single spins (see kern_escape.hip): pulses k0 .. k1-1 of
+// n_runs runs with state sx/sy/sz and times (negative = still running).
+hipError_t launch_escape(const RepDev& R, const Tableau& tb, int precession, int64_t n_runs,
+                         int64_t n, double dt, int64_t k0, int64_t k1, double h, double* sx,
+                         double* sy, double* sz, double* times, unsigned int* active,
+                         hipStream_t st);
+
 // Fused RK4 step (one launch per step, z-marching LDS tiles).
 struct FusedInfo {
     int bx, by, threads, lds_bytes;

@@ -63,6 +63,8 @@ int main(void) {
   F(lll_obs, m) F(lll_obs, max_norm_dev)
   F(lll_replica_desc, lambda) F(lll_replica_desc, seed) F(lll_replica_desc, replica)
   F(lll_replica_desc, init)
+  printf("lll_escape_params %zu\n", sizeof(lll_escape_params));
+  F(lll_escape_params, precession) F(lll_escape_params, seed) F(lll_escape_params, replica)
   return 0;
 }
 """
@@ -87,6 +89,9 @@ int main(void) {
     assert lay["lll_replica_desc.seed"] == P.lll_replica_desc.seed.offset
     assert lay["lll_replica_desc.replica"] == P.lll_replica_desc.replica.offset
     assert lay["lll_replica_desc.init"] == P.lll_replica_desc.init.offset
+    assert lay["lll_escape_params"] == C.sizeof(P.lll_escape_params)
+    for f in ("precession", "seed", "replica"):
+        assert lay["lll_escape_params." + f] == getattr(P.lll_escape_params, f).offset
 
 
 def test_validation_before_device_use(P):

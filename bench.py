@@ -290,6 +290,51 @@ def extra_integrators(n_pulses: int = 50):
     return out
 
 
+def extra_escape(n_runs: int = 65536):
+    """Thermally activated escape of a uniaxial spin in a transverse field
+    (D = 1, H = 1, h = 1/2; the paper's reference set dt = 1/6, Dt = 1 with
+    Butcher's RK5): per damping lambda and barrier sigma (1 - h)^2 with
+    sigma = D/T, n_runs independent spins on the GPU, capped at three
+    theoretical mean first-passage times; Gamma = escaped runs / total time
+    at risk (censored exponential estimate), compared with the
+    intermediate-damping rate (A = 1) and the interpolated rate with F(1/2)
+    from the paper's one-dimensional formula (1.904) and from its contour
+    definition (4/3)."""
+    import numpy as np
+    import torch
+    import paper_1610_04914_amd as P
+    import oracle as orc
+    D, H, dt, Dt = 1.0, 1.0, 1.0 / 6.0, 1.0
+    n = int(round(Dt / dt))
+    f17, fc = orc.escape_F(0.5), 4.0 / 3.0
+    rows = []
+    tot_steps, tot_s = 0.0, 0.0
+    for sigma in (10.0, 16.0):
+        T = D / sigma
+        g_id = orc.escape_rate_theory(D, H, 0.1, T, "ID")
+        for lam in (0.1, 0.03, 0.01, 0.003, 0.001):
+            g_th = orc.escape_rate_theory(D, H, lam, T, "ILD")
+            maxp = int(3.0 / (g_th * Dt)) + 10
+            el, tt = _timed(lambda: P.escape_times(D, H, lam, T, dt, Dt, n_runs, seed=1,
+                                                   max_pulses=maxp, integrator="rk5b"))
+            t = tt.cpu().numpy()
+            esc = t > 0
+            risk = float(np.where(esc, t, maxp * Dt).sum())
+            g = float(esc.sum()) / risk
+            a17 = lam * sigma * f17
+            ac = lam * sigma * fc
+            tot_steps += risk / dt
+            tot_s += el
+            rows.append({"sigma": sigma, "lambda": lam, "escaped": float(esc.mean()), "gamma": g,
+                         "gamma_over_ID": g / g_id,
+                         "gamma_over_ILD_F1.904": g / (g_id * a17 / (1 + a17)),
+                         "gamma_over_ILD_F4/3": g / (g_id * ac / (1 + ac)),
+                         "seconds": el})
+    torch.cuda.synchronize()
+    return {"workload": f"{n_runs} runs per point, h = 1/2, RK5 dt = 1/6, Dt = 1",
+            "single_spin_steps_per_s": tot_steps / tot_s, "points": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,7 +431,8 @@ def main():
     }
     if args.extras:
         out["extras"] = {"batched": extra_batched(), "adjoint": extra_adjoint(),
-                         "overdamped_256": extra_overdamped(), "integrators": extra_integrators()}
+                         "overdamped_256": extra_overdamped(), "integrators": extra_integrators(),
+                         "escape": extra_escape()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out))

@@ -84,7 +84,9 @@ __device__ __forceinline__ void aniso_of(const RepDev& R, int64_t i, double& D, 
     }
 }
 
-// Block sum of five fp64 partials into part[blockIdx.x][0..4].
+// Block sum of five fp64 partials added to part[blockIdx.x][0..4] (each block
+// owns its row, so the running sums are deterministic; they are reduced once,
+// in block order, at the end of the backward pass).
 __device__ __forceinline__ void block_sum5(double v[5], double* part) {
     __shared__ double red[5][kAdjBlock];
     for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = v[q];
@@ -94,7 +96,7 @@ __device__ __forceinline__ void block_sum5(double v[5], double* part) {
             for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x < 5) part[(int64_t)blockIdx.x * 5 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 5) part[(int64_t)blockIdx.x * 5 + threadIdx.x] += red[threadIdx.x][0];
 }
 
 // Cotangent of the loss L = wE E(s) + wm . m(s) at the final state:
@@ -147,6 +149,61 @@ __global__ void __launch_bounds__(kAdjBlock)
     block_sum5(v, part);
 }
 
+// Reverse of f at one site: u is the cotangent of f(y) there; writes q and
+// loc and adds the site's parameter terms to v (Hbar 0..2, Jbar 3, Dbar 4;
+// per-site Dbar goes to gD).
+template <typename T, bool PREC, int ANIS>
+__device__ __forceinline__ void adj_a_site(const RepDev& R, const SiteA& c, const State& y,
+                                           double u0, double u1, double u2, const State& q,
+                                           const State& loc, double* gD, double v[5]) {
+    const T* yx = static_cast<const T*>(y.x);
+    const T* yy = static_cast<const T*>(y.y);
+    const T* yz = static_cast<const T*>(y.z);
+    const double s0 = yx[c.gi], s1 = yy[c.gi], s2 = yz[c.gi];
+    double n0, n1, n2;
+    nbr_sum<T>(R, c, yx, yy, yz, n0, n1, n2);
+    double D, e0, e1, e2;
+    aniso_of<T, ANIS>(R, c.i, D, e0, e1, e2);
+    const double se = s0 * e0 + s1 * e1 + s2 * e2;
+    const double h0 = R.J * n0 + R.H[0] + 2.0 * D * se * e0;
+    const double h1 = R.J * n1 + R.H[1] + 2.0 * D * se * e1;
+    const double h2 = R.J * n2 + R.H[2] + 2.0 * D * se * e2;
+    const double lam = R.lambda;
+    const double su = s0 * u0 + s1 * u1 + s2 * u2;
+    const double ss = s0 * s0 + s1 * s1 + s2 * s2;
+    const double sh = s0 * h0 + s1 * h1 + s2 * h2;
+    const double hu = h0 * u0 + h1 * u1 + h2 * u2;
+    double q0 = -lam * (s0 * su - u0 * ss);
+    double q1 = -lam * (s1 * su - u1 * ss);
+    double q2 = -lam * (s2 * su - u2 * ss);
+    double l0 = -lam * (u0 * sh + h0 * su - 2.0 * s0 * hu);
+    double l1 = -lam * (u1 * sh + h1 * su - 2.0 * s1 * hu);
+    double l2 = -lam * (u2 * sh + h2 * su - 2.0 * s2 * hu);
+    if constexpr (PREC) {
+        q0 += u1 * s2 - u2 * s1;  // u x s
+        q1 += u2 * s0 - u0 * s2;
+        q2 += u0 * s1 - u1 * s0;
+        l0 += h1 * u2 - h2 * u1;  // h x u
+        l1 += h2 * u0 - h0 * u2;
+        l2 += h0 * u1 - h1 * u0;
+    }
+    static_cast<T*>(q.x)[c.gi] = (T)q0;
+    static_cast<T*>(q.y)[c.gi] = (T)q1;
+    static_cast<T*>(q.z)[c.gi] = (T)q2;
+    static_cast<T*>(loc.x)[c.gi] = (T)l0;
+    static_cast<T*>(loc.y)[c.gi] = (T)l1;
+    static_cast<T*>(loc.z)[c.gi] = (T)l2;
+    v[0] += q0;
+    v[1] += q1;
+    v[2] += q2;
+    v[3] += q0 * n0 + q1 * n1 + q2 * n2;
+    const double dD = 2.0 * se * (q0 * e0 + q1 * e1 + q2 * e2);
+    if constexpr (ANIS == ANIS_SITE)
+        gD[c.i] += dD;
+    else
+        v[4] += dD;
+}
+
 // Pass A: u = scale * kb is the cotangent of f(y); writes q and loc and the
 // parameter partials.
 template <typename T, bool PREC, int ANIS>
@@ -156,71 +213,23 @@ __global__ void __launch_bounds__(kAdjBlock)
     SiteA c;
     double v[5] = {0, 0, 0, 0, 0};
     if (adj_site(reps, blk_rep, c)) {
-        const RepDev& R = reps[c.r];
-        const T* yx = static_cast<const T*>(y.x);
-        const T* yy = static_cast<const T*>(y.y);
-        const T* yz = static_cast<const T*>(y.z);
-        const double s0 = yx[c.gi], s1 = yy[c.gi], s2 = yz[c.gi];
-        double n0, n1, n2;
-        nbr_sum<T>(R, c, yx, yy, yz, n0, n1, n2);
-        double D, e0, e1, e2;
-        aniso_of<T, ANIS>(R, c.i, D, e0, e1, e2);
-        const double se = s0 * e0 + s1 * e1 + s2 * e2;
-        const double h0 = R.J * n0 + R.H[0] + 2.0 * D * se * e0;
-        const double h1 = R.J * n1 + R.H[1] + 2.0 * D * se * e1;
-        const double h2 = R.J * n2 + R.H[2] + 2.0 * D * se * e2;
         const double u0 = scale * (double)static_cast<const T*>(kb.x)[c.gi];
         const double u1 = scale * (double)static_cast<const T*>(kb.y)[c.gi];
         const double u2 = scale * (double)static_cast<const T*>(kb.z)[c.gi];
-        const double lam = R.lambda;
-        const double su = s0 * u0 + s1 * u1 + s2 * u2;
-        const double ss = s0 * s0 + s1 * s1 + s2 * s2;
-        const double sh = s0 * h0 + s1 * h1 + s2 * h2;
-        const double hu = h0 * u0 + h1 * u1 + h2 * u2;
-        double q0 = -lam * (s0 * su - u0 * ss);
-        double q1 = -lam * (s1 * su - u1 * ss);
-        double q2 = -lam * (s2 * su - u2 * ss);
-        double l0 = -lam * (u0 * sh + h0 * su - 2.0 * s0 * hu);
-        double l1 = -lam * (u1 * sh + h1 * su - 2.0 * s1 * hu);
-        double l2 = -lam * (u2 * sh + h2 * su - 2.0 * s2 * hu);
-        if constexpr (PREC) {
-            q0 += u1 * s2 - u2 * s1;  // u x s
-            q1 += u2 * s0 - u0 * s2;
-            q2 += u0 * s1 - u1 * s0;
-            l0 += h1 * u2 - h2 * u1;  // h x u
-            l1 += h2 * u0 - h0 * u2;
-            l2 += h0 * u1 - h1 * u0;
-        }
-        static_cast<T*>(q.x)[c.gi] = (T)q0;
-        static_cast<T*>(q.y)[c.gi] = (T)q1;
-        static_cast<T*>(q.z)[c.gi] = (T)q2;
-        static_cast<T*>(loc.x)[c.gi] = (T)l0;
-        static_cast<T*>(loc.y)[c.gi] = (T)l1;
-        static_cast<T*>(loc.z)[c.gi] = (T)l2;
-        v[0] = q0;
-        v[1] = q1;
-        v[2] = q2;
-        v[3] = q0 * n0 + q1 * n1 + q2 * n2;
-        const double dD = 2.0 * se * (q0 * e0 + q1 * e1 + q2 * e2);
-        if constexpr (ANIS == ANIS_SITE)
-            gD[c.i] += dD;
-        else
-            v[4] = dD;
+        adj_a_site<T, PREC, ANIS>(reps[c.r], c, y, u0, u1, u2, q, loc, gD, v);
     }
     block_sum5(v, part);
 }
 
-// Pass B: ybar = loc + J sum_nn q + 2 D e (e.q), folded into the RK4
-// cotangents (stage 4: xbar = sbar + ybar, kb = sbar/3 + ybar; stage 3:
+// Pass B at one site: ybar = loc + J sum_nn q + 2 D e (e.q), folded into the
+// RK4 cotangents (stage 4: xbar = sbar + ybar, kb = sbar/3 + ybar; stage 3:
 // xbar += ybar, kb = sbar/3 + ybar/2; stage 2: xbar += ybar,
-// kb = sbar/6 + ybar/2; stage 1: xbar += ybar).
+// kb = sbar/6 + ybar/2; stage 1: xbar += ybar).  Returns the new kb at the
+// site as stored (stages 4..2).
 template <typename T, int ANIS>
-__global__ void __launch_bounds__(kAdjBlock)
-    adj_pass_b(const RepDev* reps, const int32_t* blk_rep, State q, State loc, State sbar,
-               State xbar, State kb, int stage) {
-    SiteA c;
-    if (!adj_site(reps, blk_rep, c)) return;
-    const RepDev& R = reps[c.r];
+__device__ __forceinline__ void adj_b_site(const RepDev& R, const SiteA& c, const State& q,
+                                           const State& loc, const State& sbar, const State& xbar,
+                                           const State& kb, int stage, T& kb0, T& kb1, T& kb2) {
     const T* qx = static_cast<const T*>(q.x);
     const T* qy = static_cast<const T*>(q.y);
     const T* qz = static_cast<const T*>(q.z);
@@ -240,9 +249,6 @@ __global__ void __launch_bounds__(kAdjBlock)
     T* xb0 = static_cast<T*>(xbar.x);
     T* xb1 = static_cast<T*>(xbar.y);
     T* xb2 = static_cast<T*>(xbar.z);
-    T* k0 = static_cast<T*>(kb.x);
-    T* k1 = static_cast<T*>(kb.y);
-    T* k2 = static_cast<T*>(kb.z);
     if (stage == 4) {
         xb0[g] = (T)(b0 + y0);
         xb1[g] = (T)(b1 + y1);
@@ -253,18 +259,54 @@ __global__ void __launch_bounds__(kAdjBlock)
         xb2[g] = (T)((double)xb2[g] + y2);
     }
     if (stage == 4) {
-        k0[g] = (T)(b0 / 3.0 + y0);
-        k1[g] = (T)(b1 / 3.0 + y1);
-        k2[g] = (T)(b2 / 3.0 + y2);
+        kb0 = (T)(b0 / 3.0 + y0);
+        kb1 = (T)(b1 / 3.0 + y1);
+        kb2 = (T)(b2 / 3.0 + y2);
     } else if (stage == 3) {
-        k0[g] = (T)(b0 / 3.0 + 0.5 * y0);
-        k1[g] = (T)(b1 / 3.0 + 0.5 * y1);
-        k2[g] = (T)(b2 / 3.0 + 0.5 * y2);
+        kb0 = (T)(b0 / 3.0 + 0.5 * y0);
+        kb1 = (T)(b1 / 3.0 + 0.5 * y1);
+        kb2 = (T)(b2 / 3.0 + 0.5 * y2);
     } else if (stage == 2) {
-        k0[g] = (T)(b0 / 6.0 + 0.5 * y0);
-        k1[g] = (T)(b1 / 6.0 + 0.5 * y1);
-        k2[g] = (T)(b2 / 6.0 + 0.5 * y2);
+        kb0 = (T)(b0 / 6.0 + 0.5 * y0);
+        kb1 = (T)(b1 / 6.0 + 0.5 * y1);
+        kb2 = (T)(b2 / 6.0 + 0.5 * y2);
     }
+    if (stage >= 2) {
+        static_cast<T*>(kb.x)[g] = kb0;
+        static_cast<T*>(kb.y)[g] = kb1;
+        static_cast<T*>(kb.z)[g] = kb2;
+    }
+}
+
+// Pass B of one stage alone (the last stage of a step's reverse).
+template <typename T, int ANIS>
+__global__ void __launch_bounds__(kAdjBlock)
+    adj_pass_b(const RepDev* reps, const int32_t* blk_rep, State q, State loc, State sbar,
+               State xbar, State kb, int stage) {
+    SiteA c;
+    if (!adj_site(reps, blk_rep, c)) return;
+    T k0, k1, k2;
+    adj_b_site<T, ANIS>(reps[c.r], c, q, loc, sbar, xbar, kb, stage, k0, k1, k2);
+}
+
+// Pass B of stage s followed by pass A of stage s - 1 at the same site: the
+// cotangent of k_{s-1} is pointwise in B's result, so one launch does both
+// (q, loc of stage s are read; qn, locn of stage s - 1 are written).
+template <typename T, bool PREC, int ANIS>
+__global__ void __launch_bounds__(kAdjBlock)
+    adj_pass_ba(const RepDev* reps, const int32_t* blk_rep, State q, State loc, State sbar,
+                State xbar, State kb, int stage, State y, double scale, State qn, State locn,
+                double* gD, double* part) {
+    SiteA c;
+    double v[5] = {0, 0, 0, 0, 0};
+    if (adj_site(reps, blk_rep, c)) {
+        const RepDev& R = reps[c.r];
+        T k0, k1, k2;
+        adj_b_site<T, ANIS>(R, c, q, loc, sbar, xbar, kb, stage, k0, k1, k2);
+        adj_a_site<T, PREC, ANIS>(R, c, y, scale * (double)k0, scale * (double)k1,
+                                  scale * (double)k2, qn, locn, gD, v);
+    }
+    block_sum5(v, part);
 }
 
 // acc[0..4] += sum over blocks of part[b][0..4], in block order.
@@ -349,10 +391,12 @@ static hipError_t loss_t(int anis, const RepDev* reps, const int32_t* blk, int n
 
 hipError_t launch_adj_loss(int prec, int anis, const RepDev* reps, const int32_t* blk, int nblk,
                            State s, State sbar, double wE, const double wm[3], double* gD,
-                           double* part, double* acc, hipStream_t st) {
-    hipError_t e = prec == 0 ? loss_t<double>(anis, reps, blk, nblk, s, sbar, wE, wm, gD, part, st)
-                             : loss_t<float>(anis, reps, blk, nblk, s, sbar, wE, wm, gD, part, st);
-    if (e != hipSuccess) return e;
+                           double* part, hipStream_t st) {
+    return prec == 0 ? loss_t<double>(anis, reps, blk, nblk, s, sbar, wE, wm, gD, part, st)
+                     : loss_t<float>(anis, reps, blk, nblk, s, sbar, wE, wm, gD, part, st);
+}
+
+hipError_t launch_adj_finish(const double* part, int nblk, double* acc, hipStream_t st) {
     hipLaunchKernelGGL(adj_reduce5, dim3(1), dim3(256), 0, st, part, nblk, acc);
     return hipGetLastError();
 }
@@ -377,31 +421,55 @@ static void pass_b_t(int anis, const RepDev* reps, const int32_t* blk, int nblk,
     }
 }
 
+template <typename T, bool PREC>
+static void pass_ba_t(int anis, const RepDev* reps, const int32_t* blk, int nblk, State q, State loc,
+                      State sbar, State xbar, State kb, int stage, State y, double scale, State qn,
+                      State locn, double* gD, double* part, hipStream_t st) {
+    switch (anis) {
+        case ANIS_NONE: hipLaunchKernelGGL((adj_pass_ba<T, PREC, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, q, loc, sbar, xbar, kb, stage, y, scale, qn, locn, gD, part); break;
+        case ANIS_SITE: hipLaunchKernelGGL((adj_pass_ba<T, PREC, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, q, loc, sbar, xbar, kb, stage, y, scale, qn, locn, gD, part); break;
+        default: hipLaunchKernelGGL((adj_pass_ba<T, PREC, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, q, loc, sbar, xbar, kb, stage, y, scale, qn, locn, gD, part); break;
+    }
+}
+
 // Reverse of one RK4 step given its stage inputs y[0..3] and the cotangent
 // sbar of its output; on return xbar holds the cotangent of its input.
+// Launches: A of stage 4, then B of stage s fused with A of stage s - 1 for
+// s = 4, 3, 2, then B of stage 1; q/loc alternate between two buffers.
+// Parameter partials accumulate in part (reduced by launch_adj_finish).
 hipError_t launch_adj_step(int prec, int precession, int anis, const RepDev* reps,
                            const int32_t* blk, int nblk, const State y[4], double dt, State sbar,
-                           State xbar, State kb, State q, State loc, double* gD, double* part,
-                           double* acc, hipStream_t st) {
-    for (int s = 4; s >= 1; --s) {
-        const State src = s == 4 ? sbar : kb;
-        const double scale = s == 4 ? dt / 6.0 : dt;
+                           State xbar, State kb, const State q[2], const State loc[2], double* gD,
+                           double* part, hipStream_t st) {
+    if (prec == 0) {
+        if (precession) pass_a_t<double, true>(anis, reps, blk, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
+        else pass_a_t<double, false>(anis, reps, blk, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
+    } else {
+        if (precession) pass_a_t<float, true>(anis, reps, blk, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
+        else pass_a_t<float, false>(anis, reps, blk, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int cur = 0;
+    for (int s = 4; s >= 2; --s) {
+        const State& qi = q[cur];
+        const State& li = loc[cur];
+        const State& qo = q[cur ^ 1];
+        const State& lo = loc[cur ^ 1];
         if (prec == 0) {
-            if (precession) pass_a_t<double, true>(anis, reps, blk, nblk, y[s - 1], src, scale, q, loc, gD, part, st);
-            else pass_a_t<double, false>(anis, reps, blk, nblk, y[s - 1], src, scale, q, loc, gD, part, st);
+            if (precession) pass_ba_t<double, true>(anis, reps, blk, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
+            else pass_ba_t<double, false>(anis, reps, blk, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
         } else {
-            if (precession) pass_a_t<float, true>(anis, reps, blk, nblk, y[s - 1], src, scale, q, loc, gD, part, st);
-            else pass_a_t<float, false>(anis, reps, blk, nblk, y[s - 1], src, scale, q, loc, gD, part, st);
+            if (precession) pass_ba_t<float, true>(anis, reps, blk, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
+            else pass_ba_t<float, false>(anis, reps, blk, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
         }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(adj_reduce5, dim3(1), dim3(256), 0, st, part, nblk, acc);
-        if (prec == 0) pass_b_t<double>(anis, reps, blk, nblk, q, loc, sbar, xbar, kb, s, st);
-        else pass_b_t<float>(anis, reps, blk, nblk, q, loc, sbar, xbar, kb, s, st);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        cur ^= 1;
     }
-    return hipSuccess;
+    if (prec == 0) pass_b_t<double>(anis, reps, blk, nblk, q[cur], loc[cur], sbar, xbar, kb, 1, st);
+    else pass_b_t<float>(anis, reps, blk, nblk, q[cur], loc[cur], sbar, xbar, kb, 1, st);
+    return hipGetLastError();
 }
 
 hipError_t launch_adj_kick(int prec, const RepDev* reps, const int32_t* blk, int nblk, State spre,

@@ -1084,18 +1084,20 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
     TmpAlloc T;
     void* ck = T.get(3 * cb * (size_t)std::max<int64_t>(nblocks, 1));
     void* bb = T.get(3 * cb * (size_t)(4 * K + 1));
-    void* sc = T.get(3 * cb * 8);
+    void* sc = T.get(3 * cb * 10);
     double* part = (double*)T.get(sizeof(double) * 5 * E.nblk);
     double* acc5 = (double*)T.get(sizeof(double) * 5);
     if (!ck || !bb || !sc || !part || !acc5) return set_err(LLL_ENOMEM, "adjoint buffers");
     State cur = state_at(sc, cb, 0), nxt = state_at(sc, cb, 1), accb = state_at(sc, cb, 2);
     State sbar = state_at(sc, cb, 3), xbar = state_at(sc, cb, 4), kb = state_at(sc, cb, 5);
-    State q = state_at(sc, cb, 6), loc = state_at(sc, cb, 7);
+    const State q2[2] = {state_at(sc, cb, 6), state_at(sc, cb, 8)};
+    const State loc2[2] = {state_at(sc, cb, 7), state_at(sc, cb, 9)};
     // block buffer: slot j holds x, y2, y3, y4 of operation j of the block
     auto slot = [&](int64_t j, int c) { return state_at(bb, cb, 4 * j + c); };
     const bool site = p->D_site != nullptr;
     double* gD = site ? (double*)g_D : nullptr;
     HIP_TRY(hipMemsetAsync(acc5, 0, sizeof(double) * 5, E.st));
+    HIP_TRY(hipMemsetAsync(part, 0, sizeof(double) * 5 * E.nblk, E.st));
     if (site) HIP_TRY(hipMemsetAsync(gD, 0, sizeof(double) * E.nsites, E.st));
     const int pr = E.prec, pc = E.precession, an = E.anis;
     // forward with checkpoints
@@ -1115,7 +1117,7 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
     // loss and its cotangent
     HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, cur, E.d_partials, E.d_result,
                        E.d_accum, 0, nullptr, -1, nullptr, E.st));
-    HIP_TRY(launch_adj_loss(pr, an, E.dreps, E.d_blk_rep, E.nblk, cur, sbar, wE, wm, gD, part, acc5,
+    HIP_TRY(launch_adj_loss(pr, an, E.dreps, E.d_blk_rep, E.nblk, cur, sbar, wE, wm, gD, part,
                             E.st));
     // backward
     const double dt = p->dt;
@@ -1140,7 +1142,7 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
             if (op[j] == 0) {
                 const State y[4] = {slot(sl, 0), slot(sl, 1), slot(sl, 2), slot(sl, 3)};
                 HIP_TRY(launch_adj_step(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, y, dt, sbar, xbar,
-                                        kb, q, loc, gD, part, acc5, E.st));
+                                        kb, q2, loc2, gD, part, E.st));
                 std::swap(sbar, xbar);
             } else {
                 HIP_TRY(launch_adj_kick(pr, E.dreps, E.d_blk_rep, E.nblk, slot(sl, 0), sbar, opk[j],
@@ -1148,6 +1150,7 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
             }
         }
     }
+    HIP_TRY(launch_adj_finish(part, E.nblk, acc5, E.st));
     if (g_s0) {
         State dst{g_s0, (char*)g_s0 + cb, (char*)g_s0 + 2 * cb};
         HIP_TRY(launch_copy(pr, dst, sbar, E.nsites, E.st));

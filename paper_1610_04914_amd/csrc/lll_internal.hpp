@@ -114,15 +114,18 @@ hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* r
                              State y4, State acc, State xnext, hipStream_t st);
 
 // Adjoint kernels (256-site blocks, the same block table as the per-site kernels).
-// part: [nblk][5] fp64 partials; acc: [5] fp64 {Hbar x3, Jbar, Dbar}; gD: per-site
-// fp64 Dbar_i (per-site anisotropy) or unused.
+// part: [nblk][5] fp64 running partials {Hbar x3, Jbar, Dbar} (zeroed by the
+// caller, added to by every pass, reduced in block order into acc[5] by
+// launch_adj_finish); gD: per-site fp64 Dbar_i (per-site anisotropy) or unused.
 hipError_t launch_adj_loss(int prec, int anis, const RepDev* reps, const int32_t* blk, int nblk,
                            State s, State sbar, double wE, const double wm[3], double* gD,
-                           double* part, double* acc, hipStream_t st);
+                           double* part, hipStream_t st);
+// q[2], loc[2]: two scratch pairs used alternately.
 hipError_t launch_adj_step(int prec, int precession, int anis, const RepDev* reps,
                            const int32_t* blk, int nblk, const State y[4], double dt, State sbar,
-                           State xbar, State kb, State q, State loc, double* gD, double* part,
-                           double* acc, hipStream_t st);
+                           State xbar, State kb, const State q[2], const State loc[2], double* gD,
+                           double* part, hipStream_t st);
+hipError_t launch_adj_finish(const double* part, int nblk, double* acc, hipStream_t st);
 hipError_t launch_adj_kick(int prec, const RepDev* reps, const int32_t* blk, int nblk, State spre,
                            State sbar, uint64_t k, double sigma_override, hipStream_t st);
 }  // namespace lll

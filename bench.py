@@ -335,6 +335,48 @@ def extra_escape(n_runs: int = 65536):
             "single_spin_steps_per_s": tot_steps / tot_s, "points": rows}
 
 
+def extra_precision(L: int = 64, intervals: int = 4):
+    """Error of the GPU path against the FP64 oracle for every observable:
+    the headline physics on an L^3 lattice, fp32 and fp64 state; each
+    interval (10 RK4 steps with the kick) is run by the GPU and by the oracle
+    started from the GPU's state before it, and the largest error over the
+    intervals is reported: spin components (absolute; spins are unit
+    vectors), energies and magnetisation components (relative to the total
+    energy per site and to 1), and the norm deviation (absolute)."""
+    import numpy as np
+    import torch
+    import paper_1610_04914_amd as P
+    import oracle as orc
+    shape = (L, L, L)
+    g = orc.geom(shape)
+    op = orc.Params(J=PHYS["J"], H=PHYS["H"], D=PHYS["D"], e=PHYS["e"], lam=PHYS["lam"], T=PHYS["T"],
+                    dt=PHYS["dt"], Dt=PHYS["Dt"], precession=True)
+    gp = P.Params(**PHYS)
+    N = float(L**3)
+    out = {"workload": f"{L}^3, headline physics, {intervals} intervals of 10 RK4 steps"}
+    for prec in ("fp32", "fp64"):
+        lat = P.Lattice(shape, precision=prec, init="random", seed=0)
+        err = {k: 0.0 for k in ("state", "E_total", "E_exch", "E_zeeman", "E_anis", "m",
+                                "max_norm_dev")}
+        for q in range(intervals):
+            torch.cuda.synchronize()
+            s0 = lat.state.double().cpu().numpy()
+            tr = lat.run(gp, first_pulse=q, n_pulses=1, obs_every=1)[0]
+            s1 = lat.state.double().cpu().numpy()
+            want, otr, _ = orc.run(g, op, s0, seed=PHYS["seed"], first_pulse=q, n_pulses=1,
+                                   obs_every=1)
+            o = otr[0]
+            err["state"] = max(err["state"], float(np.max(np.abs(s1 - want))))
+            scale = abs(o["E_total"]) / N
+            for k in ("E_total", "E_exch", "E_zeeman", "E_anis"):
+                err[k] = max(err[k], abs(tr[k] - o[k]) / N / scale)
+            err["m"] = max(err["m"], float(np.max(np.abs(np.array(tr["m"]) - np.array(o["m"])))))
+            err["max_norm_dev"] = max(err["max_norm_dev"], abs(tr["max_norm_dev"] - o["max_norm_dev"]))
+        out[prec] = err
+        lat.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,7 +474,7 @@ def main():
     if args.extras:
         out["extras"] = {"batched": extra_batched(), "adjoint": extra_adjoint(),
                          "overdamped_256": extra_overdamped(), "integrators": extra_integrators(),
-                         "escape": extra_escape()}
+                         "escape": extra_escape(), "precision": extra_precision()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out))

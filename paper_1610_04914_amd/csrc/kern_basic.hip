@@ -236,14 +236,63 @@ __device__ __forceinline__ void block_reduce8(double q[8], double* out) {
     }
 }
 
+// Planes per observables work item.  A work item is a run of kObsBlock
+// consecutive (x, y) columns over kObsZ consecutive z-planes; each thread
+// marches up its column, so the +z neighbour of a plane is the next plane's
+// own spin, already in registers, and only the +x and +y neighbours (same
+// and adjacent rows, cache hits) are loaded besides it.
+constexpr int kObsZ = 8;
+
+__host__ __device__ inline int64_t obs_items(int Lx, int Ly, int Lz) {
+    const int64_t Lxy = (int64_t)Lx * Ly;
+    return ((Lxy + kObsBlock - 1) / kObsBlock) * ((Lz + kObsZ - 1) / kObsZ);
+}
+
+int64_t obs_item_count(int Lx, int Ly, int Lz) { return obs_items(Lx, Ly, Lz); }
+
+// Per-thread quantities of the observables pass: q[0] sum of s_i.s_j over the
+// bonds, q[1] unused (0), q[2] the anisotropy sum before its constant D
+// (sum (s.e)^2; per-site D included for site-dependent axes), q[3..5] sum s,
+// q[6] / q[7] max / min of |s|^2 ignoring NaN (a NaN is kept in a flag).  The
+// Zeeman sum H.(sum s) and the factor D are applied once per replica.
+template <typename T, int ANIS>
+__device__ __forceinline__ void obs_site(const RepDev& R, double sx, double sy, double sz, double bx,
+                                         double by, double bz, const T* Ds, const T* es, int64_t N,
+                                         int64_t g, double q[8], bool& nan) {
+    q[0] += sx * bx + sy * by + sz * bz;
+    if constexpr (ANIS == ANIS_Z) {
+        q[2] += sz * sz;
+    } else if constexpr (ANIS == ANIS_AXIS) {
+        const double se = sx * R.e[0] + sy * R.e[1] + sz * R.e[2];
+        q[2] += se * se;
+    } else if constexpr (ANIS == ANIS_SITE) {
+        const double se = sx * (double)es[g] + sy * (double)es[N + g] + sz * (double)es[2 * N + g];
+        q[2] += (double)Ds[g] * se * se;
+    }
+    q[3] += sx;
+    q[4] += sy;
+    q[5] += sz;
+    const double n2 = sx * sx + sy * sy + sz * sz;
+    q[6] = __builtin_fmax(q[6], n2);
+    q[7] = __builtin_fmin(q[7], n2);
+    nan |= n2 != n2;
+}
+
+// Load at a wave-uniform base plus a 32-bit per-lane byte offset.  The base
+// is pinned to scalar registers and hidden from the optimiser, which would
+// otherwise fold the offset into a 64-bit per-lane address.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off) {
+    asm volatile("" : "+s"(base));
+    const __attribute__((address_space(1))) char* g = (const __attribute__((address_space(1))) char*)base;
+    return *(const __attribute__((address_space(1))) T*)(g + byte_off);
+}
+
 template <typename T, int ANIS>
 __global__ void __launch_bounds__(kObsBlock)
     obs_partial_kernel(const RepDev* reps, const int32_t* oblk_rep, State s, double* partials) {
-    // sites per thread and pass; their loads are issued together
-    constexpr int U = sizeof(T) == 4 ? 4 : 2;
     const int b = blockIdx.x;
-    const int r = oblk_rep[b];
-    const RepDev& R = reps[r];
+    const RepDev& R = reps[oblk_rep[b]];
     const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
     const int64_t Lxy = (int64_t)Lx * Ly;
     const int64_t N = Lxy * Lz;
@@ -251,79 +300,115 @@ __global__ void __launch_bounds__(kObsBlock)
     const T* __restrict__ px = static_cast<const T*>(s.x) + R.off;
     const T* __restrict__ py = static_cast<const T*>(s.y) + R.off;
     const T* __restrict__ pz = static_cast<const T*>(s.z) + R.off;
-    const int64_t stride = (int64_t)R.nob * kObsBlock;
-    int64_t i = (int64_t)(b - R.ob0) * kObsBlock + threadIdx.x;
-    // coordinates of i; they advance by those of the stride with carries, so
-    // no division runs per site
-    int x = (int)(i % Lx), y = (int)((i / Lx) % Ly), z = (int)(i / Lxy);
-    const int dx = (int)(stride % Lx), dy = (int)((stride / Lx) % Ly), dz = (int)(stride / Lxy);
+    const T* Ds = static_cast<const T*>(R.D_site);
+    const T* es = static_cast<const T*>(R.e_site);
+    // plane-relative byte offsets fit 32 bits: loads take a uniform plane
+    // base plus a 32-bit lane offset (no 64-bit address arithmetic per load)
+    const bool off32 = Lxy * (int64_t)sizeof(T) <= (int64_t)0x7fffffff;
+    // items are numbered slab-major; block h takes a contiguous range of
+    // them.  Workgroups are dealt out to the eight XCDs round-robin, so when
+    // the replica's blocks start on an XCD boundary the hardware index is
+    // permuted to give each XCD a contiguous range of slabs: the +y rows of
+    // a column run and the +z plane of a slab then sit in the same L2.
+    const int64_t ncb = (Lxy + kObsBlock - 1) / kObsBlock;
+    const int64_t nitems = obs_items(Lx, Ly, Lz);
+    const int nob = R.nob;
+    int h = b - R.ob0;
+    if ((nob & 7) == 0 && (R.ob0 & 7) == 0) h = (h & 7) * (nob >> 3) + (h >> 3);
+    const int64_t per = (nitems + nob - 1) / nob;
+    const int64_t it0 = (int64_t)h * per;
+    const int64_t it1 = it0 + per < nitems ? it0 + per : nitems;
     double q[8] = {0, 0, 0, 0, 0, 0, 0, __builtin_huge_val()};
-    for (; i < N; i += U * stride) {
-        // site and +x, +y, +z neighbour indices; every index is a valid site
-        // (lanes past the end read site 0, missing free-boundary bonds read a
-        // wrapped site), the flags drop what does not count
-        int64_t g[U];
-        int dn[U][3];
-        bool ok[U], hx[U], hy[U], hz[U];
-        int64_t ci = i;
+    bool nan = false;
+    for (int64_t it = it0; it < it1; ++it) {
+        const int slab = (int)(it / ncb);
+        const int64_t cb = it - (int64_t)slab * ncb;
+        const int z0 = slab * kObsZ;
+        // every load of the item is issued before any arithmetic
+        T v[kObsZ + 1][3], a[kObsZ][3], bq[kObsZ][3];
+        if (pbc && off32 && z0 + kObsZ <= Lz && (cb + 1) * kObsBlock <= Lxy) {
+            // whole item inside the lattice, every bond present (uniform
+            // branch); column indices and byte offsets in 32 bits
+            const uint32_t c = (uint32_t)cb * kObsBlock + threadIdx.x;
+            const uint32_t y = c / (uint32_t)Lx, x = c - y * (uint32_t)Lx;
+            const uint32_t cx = x + 1 < (uint32_t)Lx ? c + 1 : c + 1 - (uint32_t)Lx;
+            const uint32_t cy = y + 1 < (uint32_t)Ly ? c + (uint32_t)Lx : c + (uint32_t)Lx - (uint32_t)Lxy;
+            const uint32_t o0 = c * (uint32_t)sizeof(T);
+            const uint32_t o1 = cx * (uint32_t)sizeof(T);
+            const uint32_t o2 = cy * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            ok[k] = ci < N;
-            const int xx = ok[k] ? x : 0, yy = ok[k] ? y : 0, zz = ok[k] ? z : 0;
-            g[k] = ok[k] ? ci : 0;
-            dn[k][0] = xx + 1 < Lx ? 1 : 1 - Lx;
-            dn[k][1] = yy + 1 < Ly ? Lx : (int)(Lx - Lxy);
-            dn[k][2] = zz + 1 < Lz ? (int)Lxy : (int)(Lxy - N);
-            hx[k] = pbc || xx + 1 < Lx;
-            hy[k] = pbc || yy + 1 < Ly;
-            hz[k] = pbc || zz + 1 < Lz;
-            ci += stride;
-            x += dx;
-            if (x >= Lx) { x -= Lx; ++y; }
-            y += dy;
-            if (y >= Ly) { y -= Ly; ++z; }
-            z += dz;
-        }
-        T v[U][4][3];
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int64_t c = g[k] + (m == 0 ? 0 : dn[k][m - 1]);
-                v[k][m][0] = px[c];
-                v[k][m][1] = py[c];
-                v[k][m][2] = pz[c];
+            for (int j = 0; j <= kObsZ; ++j) {
+                const int64_t po = (int64_t)(z0 + j < Lz ? z0 + j : 0) * Lxy;
+                v[j][0] = ld_off(px + po, o0);
+                v[j][1] = ld_off(py + po, o0);
+                v[j][2] = ld_off(pz + po, o0);
             }
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            if (!ok[k]) continue;
-            const double sx = (double)v[k][0][0], sy = (double)v[k][0][1], sz = (double)v[k][0][2];
-            double bx = 0, by = 0, bz = 0;
-            if (hx[k]) { bx += (double)v[k][1][0]; by += (double)v[k][1][1]; bz += (double)v[k][1][2]; }
-            if (hy[k]) { bx += (double)v[k][2][0]; by += (double)v[k][2][1]; bz += (double)v[k][2][2]; }
-            if (hz[k]) { bx += (double)v[k][3][0]; by += (double)v[k][3][1]; bz += (double)v[k][3][2]; }
-            q[0] += sx * bx + sy * by + sz * bz;
-            q[1] += R.H[0] * sx + R.H[1] * sy + R.H[2] * sz;
-            if constexpr (ANIS == ANIS_Z) {
-                q[2] += R.D * sz * sz;
-            } else if constexpr (ANIS == ANIS_AXIS) {
-                const double se = sx * R.e[0] + sy * R.e[1] + sz * R.e[2];
-                q[2] += R.D * se * se;
-            } else if constexpr (ANIS == ANIS_SITE) {
-                const T* Ds = static_cast<const T*>(R.D_site);
-                const T* es = static_cast<const T*>(R.e_site);
-                const int64_t c = g[k];
-                const double se = sx * (double)es[c] + sy * (double)es[N + c] + sz * (double)es[2 * N + c];
-                q[2] += (double)Ds[c] * se * se;
+            for (int j = 0; j < kObsZ; ++j) {
+                const int64_t po = (int64_t)(z0 + j) * Lxy;
+                a[j][0] = ld_off(px + po, o1);
+                a[j][1] = ld_off(py + po, o1);
+                a[j][2] = ld_off(pz + po, o1);
+                bq[j][0] = ld_off(px + po, o2);
+                bq[j][1] = ld_off(py + po, o2);
+                bq[j][2] = ld_off(pz + po, o2);
             }
-            q[3] += sx;
-            q[4] += sy;
-            q[5] += sz;
-            const double n2 = sx * sx + sy * sy + sz * sz;
-            q[6] = nan_max(q[6], n2);
-            q[7] = nan_min(q[7], n2);
+#pragma unroll
+            for (int j = 0; j < kObsZ; ++j) {
+                double bn[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    bn[m] = (double)a[j][m] + (double)bq[j][m] + (double)v[j + 1][m];
+                obs_site<T, ANIS>(R, (double)v[j][0], (double)v[j][1], (double)v[j][2], bn[0], bn[1],
+                                  bn[2], Ds, es, N, (int64_t)(z0 + j) * Lxy + c, q, nan);
+            }
+        } else {
+            // general item: planes past Lz (last slab) address plane 0, lanes
+            // past the last column address column 0; both count nothing
+            const int64_t c = cb * kObsBlock + threadIdx.x;
+            const bool okc = c < Lxy;
+            const int64_t cc = okc ? c : 0;
+            const int y = (int)(cc / Lx), x = (int)(cc - (int64_t)y * Lx);
+            // +x and +y offsets (wrapped at the far face; a missing
+            // free-boundary bond still reads a valid site and is dropped)
+            const int64_t ox = x + 1 < Lx ? 1 : 1 - Lx;
+            const int64_t oy = y + 1 < Ly ? (int64_t)Lx : (int64_t)Lx - Lxy;
+            const bool hx = pbc || x + 1 < Lx, hy = pbc || y + 1 < Ly;
+            int64_t gp[kObsZ + 1];
+            gp[0] = (int64_t)z0 * Lxy + cc;
+#pragma unroll
+            for (int j = 0; j < kObsZ; ++j) gp[j + 1] = z0 + j + 1 < Lz ? gp[j] + Lxy : cc;
+#pragma unroll
+            for (int j = 0; j <= kObsZ; ++j) {
+                v[j][0] = px[gp[j]];
+                v[j][1] = py[gp[j]];
+                v[j][2] = pz[gp[j]];
+            }
+#pragma unroll
+            for (int j = 0; j < kObsZ; ++j) {
+                a[j][0] = px[gp[j] + ox];
+                a[j][1] = py[gp[j] + ox];
+                a[j][2] = pz[gp[j] + ox];
+                bq[j][0] = px[gp[j] + oy];
+                bq[j][1] = py[gp[j] + oy];
+                bq[j][2] = pz[gp[j] + oy];
+            }
+#pragma unroll
+            for (int j = 0; j < kObsZ; ++j) {
+                const int z = z0 + j;
+                if (!(okc && z < Lz)) continue;
+                const bool hz = pbc || z + 1 < Lz;
+                double bn[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    bn[m] = (hx ? (double)a[j][m] : 0.0) + (hy ? (double)bq[j][m] : 0.0) +
+                            (hz ? (double)v[j + 1][m] : 0.0);
+                obs_site<T, ANIS>(R, (double)v[j][0], (double)v[j][1], (double)v[j][2], bn[0], bn[1],
+                                  bn[2], Ds, es, N, gp[j], q, nan);
+            }
         }
     }
+    if (nan) q[6] = q[7] = __builtin_nan("");
     block_reduce8<kObsBlock>(q, partials + (int64_t)b * 8);
 }
 
@@ -333,19 +418,34 @@ constexpr int kObsFinal = 256;
 // also folds the pending kick maxima (per-site blocks 0, fused tiles 1) of the
 // replica into kickdev, saving a launch after a kick.
 __global__ void __launch_bounds__(kObsFinal)
-    obs_final_kernel(const RepDev* reps, const double* partials, double* result, double* accum,
-                     int accumulate, const double* kickpart, int kick_mode,
+    obs_final_kernel(const RepDev* reps, int anis, const double* partials, double* result,
+                     double* accum, int accumulate, const double* kickpart, int kick_mode,
                      unsigned long long* kickdev) {
     const int r = blockIdx.x;
     const RepDev& R = reps[r];
-    if (kick_mode >= 0) {
-        kickmax_fold(R, kickpart, kick_mode, kickdev + r);
-        __syncthreads();
-    }
+    // at most kFinalU partials per thread and pass, loaded together (and
+    // before the kick fold, whose barriers would otherwise serialise them)
+    constexpr int kFinalU = 8;
     double q[8] = {0, 0, 0, 0, 0, 0, 0, __builtin_huge_val()};
-    for (int b = R.ob0 + threadIdx.x; b < R.ob0 + R.nob; b += kObsFinal) {
-        const double* p = partials + (int64_t)b * 8;
-        for (int j = 0; j < 8; ++j) q[j] = red8(j, q[j], p[j]);
+    const int pend = R.ob0 + R.nob;
+    for (int b0 = R.ob0; b0 < pend; b0 += kFinalU * kObsFinal) {
+        double v[kFinalU][8];
+#pragma unroll
+        for (int u = 0; u < kFinalU; ++u) {
+            const int bb = b0 + u * kObsFinal + (int)threadIdx.x;
+            const double* p = partials + (int64_t)(bb < pend ? bb : R.ob0) * 8;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[u][j] = p[j];
+        }
+        if (b0 == R.ob0 && kick_mode >= 0) {
+            kickmax_fold(R, kickpart, kick_mode, kickdev + r);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < kFinalU; ++u)
+            if (b0 + u * kObsFinal + (int)threadIdx.x < pend)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) q[j] = red8(j, q[j], v[u][j]);
     }
     __shared__ double tot[8];
     block_reduce8<kObsFinal>(q, tot);
@@ -353,8 +453,8 @@ __global__ void __launch_bounds__(kObsFinal)
     if (threadIdx.x == 0) {
         const double N = (double)R.Lx * R.Ly * R.Lz;
         const double Eex = -R.J * tot[0];
-        const double Ez = -tot[1];
-        const double Ea = -tot[2];
+        const double Ez = -(R.H[0] * tot[3] + R.H[1] * tot[4] + R.H[2] * tot[5]);
+        const double Ea = -(anis == ANIS_Z || anis == ANIS_AXIS ? R.D * tot[2] : tot[2]);
         const double Et = Eex + Ez + Ea;
         const double mx = tot[3] / N, my = tot[4] / N, mz = tot[5] / N;
         double* o = result + (int64_t)r * 8;
@@ -415,7 +515,7 @@ hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* obl
         launch_obs_t<float>(anis, reps, oblk_rep, nobblk, s, partials, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(obs_final_kernel, dim3(nrep), dim3(kObsFinal), 0, st, reps, partials,
+    hipLaunchKernelGGL(obs_final_kernel, dim3(nrep), dim3(kObsFinal), 0, st, reps, anis, partials,
                        result, accum, accumulate, kickpart, kick_mode, kickdev);
     return hipGetLastError();
 }

@@ -152,7 +152,7 @@ lll_status build_tables(Engine& E) {
         R.nsb = (int32_t)((N + 255) / 256);
         for (int b = 0; b < R.nsb; ++b) blk.push_back(r);
         R.ob0 = (int32_t)oblk.size();
-        R.nob = (int32_t)std::min<int64_t>(std::max<int64_t>((N + 1023) / 1024, 1), 2048);
+        R.nob = (int32_t)std::min<int64_t>(obs_item_count(R.Lx, R.Ly, R.Lz), 2048);
         for (int b = 0; b < R.nob; ++b) oblk.push_back(r);
     }
     E.nsites = off;

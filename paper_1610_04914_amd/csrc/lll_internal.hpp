@@ -52,6 +52,9 @@ hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int
 // blocks (by_tiles = 0) or its fused-step tiles in tile order (by_tiles = 1).
 hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part, int by_tiles,
                                  unsigned long long* kickdev, hipStream_t st);
+// Work items of the observables pass for an Lx x Ly x Lz lattice (runs of
+// columns over z-slabs); a replica needs at most this many blocks.
+int64_t obs_item_count(int Lx, int Ly, int Lz);
 // Observables of every replica into result[r][8] (and accum when accumulate);
 // partials: [nobblk][8] scratch.  kick_mode >= 0 also folds pending kick maxima
 // (as launch_kickmax_reduce with by_tiles = kick_mode) into kickdev.

@@ -20,10 +20,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        // one 32 x 32 -> 64-bit product per multiplier gives both halves
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -108,8 +109,45 @@ __device__ __forceinline__ void angle_of<float>(float ph2, float& inv, float& sn
     cs = __builtin_amdgcn_cosf(rev);
 }
 
+// Renormalisation s = s'/|s'| after a kick; returns | |s'| - 1 | in fp64.
+// fp64 state: the norm and the quotient in fp64.  fp32 state: |s'|^2 of the
+// fp32 components is formed in fp64 (each square exact, so the deviation
+// |s'|^2 - 1 keeps its relative accuracy however small it is), and
+// | |s'| - 1 | = | |s'|^2 - 1 | / (|s'| + 1) takes the well-conditioned
+// denominator from the fp32 reciprocal square root, which also rescales the
+// spin (about 1 ulp).
+template <typename T>
+__device__ __forceinline__ double renorm(T ox, T oy, T oz, T& sx, T& sy, T& sz);
+
+template <>
+__device__ __forceinline__ double renorm<double>(double ox, double oy, double oz, double& sx,
+                                                 double& sy, double& sz) {
+#pragma clang fp contract(off)
+    const double nrm = sqrt(ox * ox + oy * oy + oz * oz);
+    const double inv = 1.0 / nrm;
+    sx = ox * inv;
+    sy = oy * inv;
+    sz = oz * inv;
+    return fabs(nrm - 1.0);
+}
+
+template <>
+__device__ __forceinline__ double renorm<float>(float ox, float oy, float oz, float& sx, float& sy,
+                                                float& sz) {
+#pragma clang fp contract(off)
+    const double dx = (double)ox, dy = (double)oy, dz = (double)oz;
+    const double n2 = dx * dx + dy * dy + dz * dz;
+    const float n2f = (float)n2;
+    const float r = __builtin_amdgcn_rsqf(n2f);
+    sx = ox * r;
+    sy = oy * r;
+    sz = oz * r;
+    const float den = n2f * r + 1.0f;
+    return fabs(n2 - 1.0) * (double)__builtin_amdgcn_rcpf(den);
+}
+
 // Kick of one spin: rotation by phi = sigma G about n = phi/|phi| (Eq. (6)),
-// identity when phi = 0, then renormalisation with the norm taken in fp64.
+// identity when phi = 0, then renormalisation (renorm above).
 // Returns | |s'| - 1 | (fp64).  Contraction is fixed here so that the kick
 // gives identical bits wherever it is inlined (separate kernel or epilogue).
 template <typename T>
@@ -133,13 +171,7 @@ __device__ __forceinline__ double kick_spin(T& sx, T& sy, T& sz, uint4 w, T sigm
         oy = sy * cs + cy * sn + ny * sdn * omc;
         oz = sz * cs + cz * sn + nz * sdn * omc;
     }
-    const double dx = (double)ox, dy = (double)oy, dz = (double)oz;
-    const double nrm = sqrt(dx * dx + dy * dy + dz * dz);
-    const double inv = 1.0 / nrm;
-    sx = (T)(dx * inv);
-    sy = (T)(dy * inv);
-    sz = (T)(dz * inv);
-    return fabs(nrm - 1.0);
+    return renorm<T>(ox, oy, oz, sx, sy, sz);
 }
 
 // Stage coefficients of one replica in the working precision.

@@ -278,16 +278,6 @@ __device__ __forceinline__ void obs_site(const RepDev& R, double sx, double sy, 
     nan |= n2 != n2;
 }
 
-// Load at a wave-uniform base plus a 32-bit per-lane byte offset.  The base
-// is pinned to scalar registers and hidden from the optimiser, which would
-// otherwise fold the offset into a 64-bit per-lane address.
-template <typename T>
-__device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off) {
-    asm volatile("" : "+s"(base));
-    const __attribute__((address_space(1))) char* g = (const __attribute__((address_space(1))) char*)base;
-    return *(const __attribute__((address_space(1))) T*)(g + byte_off);
-}
-
 template <typename T, int ANIS>
 __global__ void __launch_bounds__(kObsBlock)
     obs_partial_kernel(const RepDev* reps, const int32_t* oblk_rep, State s, double* partials) {

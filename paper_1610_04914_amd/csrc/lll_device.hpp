@@ -122,7 +122,6 @@ __device__ __forceinline__ double renorm(T ox, T oy, T oz, T& sx, T& sy, T& sz);
 template <>
 __device__ __forceinline__ double renorm<double>(double ox, double oy, double oz, double& sx,
                                                  double& sy, double& sz) {
-#pragma clang fp contract(off)
     const double nrm = sqrt(ox * ox + oy * oy + oz * oz);
     const double inv = 1.0 / nrm;
     sx = ox * inv;
@@ -134,7 +133,6 @@ __device__ __forceinline__ double renorm<double>(double ox, double oy, double oz
 template <>
 __device__ __forceinline__ double renorm<float>(float ox, float oy, float oz, float& sx, float& sy,
                                                 float& sz) {
-#pragma clang fp contract(off)
     const double dx = (double)ox, dy = (double)oy, dz = (double)oz;
     const double n2 = dx * dx + dy * dy + dz * dz;
     const float n2f = (float)n2;
@@ -148,11 +146,11 @@ __device__ __forceinline__ double renorm<float>(float ox, float oy, float oz, fl
 
 // Kick of one spin: rotation by phi = sigma G about n = phi/|phi| (Eq. (6)),
 // identity when phi = 0, then renormalisation (renorm above).
-// Returns | |s'| - 1 | (fp64).  Contraction is fixed here so that the kick
-// gives identical bits wherever it is inlined (separate kernel or epilogue).
+// Returns | |s'| - 1 | (fp64).  Multiply-adds contract only within one
+// expression (the library's build setting), so the kick gives identical bits
+// wherever it is inlined (separate kernel or epilogue).
 template <typename T>
 __device__ __forceinline__ double kick_spin(T& sx, T& sy, T& sz, uint4 w, T sigma) {
-#pragma clang fp contract(off)
     T G[3];
     gauss3<T>(w, G);
     const T px = sigma * G[0], py = sigma * G[1], pz = sigma * G[2];
@@ -173,6 +171,17 @@ __device__ __forceinline__ double kick_spin(T& sx, T& sy, T& sz, uint4 w, T sigm
     }
     return renorm<T>(ox, oy, oz, sx, sy, sz);
 }
+
+// Load at a wave-uniform base plus a 32-bit per-lane byte offset.  The base
+// (pinned to scalar registers) and the offset are hidden from the optimiser,
+// which would otherwise fold them into a 64-bit per-lane address.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off) {
+    asm volatile("" : "+s"(base), "+v"(byte_off));
+    const __attribute__((address_space(1))) char* g = (const __attribute__((address_space(1))) char*)base;
+    return *(const __attribute__((address_space(1))) T*)(g + byte_off);
+}
+
 
 // Stage coefficients of one replica in the working precision.
 template <typename T>

@@ -377,11 +377,35 @@ def extra_precision(L: int = 64, intervals: int = 4):
     return out
 
 
+def extra_headline_variants(lat, p, n_pulses: int = 400, repeats: int = 5):
+    """The headline lattice after its timed run: `repeats` runs of `n_pulses`
+    intervals with the observables measured every interval (as timed above) and
+    with them measured once at the end only; median and range of each."""
+    import torch
+    n = int(round(PHYS["Dt"] / PHYS["dt"]))
+    out = {}
+    q = 10**6
+    for name, every in (("obs_every_interval", 1), ("obs_at_end_only", 0)):
+        rates = []
+        for _ in range(repeats):
+            def go():
+                lat.run(p, first_pulse=q, n_pulses=n_pulses, obs_every=every)
+                if every == 0:
+                    lat.observables(p)
+            el, _ = _timed(go)
+            rates.append(lat.N * n * n_pulses / el)
+        rates.sort()
+        out[name] = {"spin_steps_per_s_median": rates[len(rates) // 2], "min": rates[0],
+                     "max": rates[-1], "repeats": repeats, "intervals_each": n_pulses}
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000, help="timed intervals (pulses)")
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10)
@@ -472,7 +496,8 @@ def main():
         "final_obs": trace[-1] if trace else None,
     }
     if args.extras:
-        out["extras"] = {"batched": extra_batched(), "adjoint": extra_adjoint(),
+        out["extras"] = {"headline_variants": extra_headline_variants(lat, p),
+                         "batched": extra_batched(), "adjoint": extra_adjoint(),
                          "overdamped_256": extra_overdamped(), "integrators": extra_integrators(),
                          "escape": extra_escape(), "precision": extra_precision()}
     if not args.no_cpu_baseline:

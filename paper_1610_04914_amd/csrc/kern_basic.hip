@@ -94,49 +94,53 @@ hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int
 }
 
 // ------------------------------------------------------------------ kick ---
-// Block-wide max of a non-negative double (a NaN compares above all) into
-// part[blockIdx.x]; kickmax_reduce folds the parts of every replica into its
-// running maximum (one writer per replica, no atomics).
-__device__ __forceinline__ void block_max_part(double v, double* part) {
-    __shared__ double red[kSiteBlock];
-    red[threadIdx.x] = v;
+// NaN-propagating max / min (a NaN operand wins).
+__device__ __forceinline__ double nan_max(double a, double c) { return (c > a || c != c) ? c : a; }
+__device__ __forceinline__ double nan_min(double a, double c) { return (c < a || c != c) ? c : a; }
+
+// Maximum over a block of 256 threads (a NaN compares above all): butterfly
+// over each wave, then the four wave results; valid in every thread.
+__device__ __forceinline__ double block_max256(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = nan_max(v, __shfl_xor(v, o, 64));
+    __shared__ double wred[4];
+    if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = kSiteBlock / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            const double a = red[threadIdx.x], b = red[threadIdx.x + o];
-            red[threadIdx.x] = (b > a || b != b) ? b : a;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    return nan_max(nan_max(wred[0], wred[1]), nan_max(wred[2], wred[3]));
+}
+
+// Block-wide max of a non-negative double into part[blockIdx.x];
+// kickmax_reduce folds the parts of every replica into its running maximum
+// (one writer per replica, no atomics).
+__device__ __forceinline__ void block_max_part(double v, double* part) {
+    static_assert(kSiteBlock == 256, "block_max256 assumes 256 threads");
+    const double m = block_max256(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
 // Maximum over the parts of replica R (its per-site blocks, or its fused-step
 // tiles in tile order) folded into *kickdev by thread 0; the whole block of
-// 256 threads takes part.
+// 256 threads takes part, each thread with up to eight loads in flight.
 __device__ __forceinline__ void kickmax_fold(const RepDev& R, const double* part, int by_tiles,
                                              unsigned long long* kickdev) {
     const int p0 = by_tiles ? R.tile0 : R.sb0;
     const int np = by_tiles ? R.tx * R.ty * R.tz : R.nsb;
+    constexpr int U = 8;
     double m = 0.0;
-    for (int q = threadIdx.x; q < np; q += 256) {
-        const double d = part[p0 + q];
-        m = (d > m || d != d) ? d : m;
-    }
-    __shared__ double red[256];
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            const double a = red[threadIdx.x], b = red[threadIdx.x + o];
-            red[threadIdx.x] = (b > a || b != b) ? b : a;
+    for (int q0 = threadIdx.x; q0 < np; q0 += 256 * U) {
+        double d[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + 256 * u;
+            d[u] = q < np ? part[p0 + q] : 0.0;
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) m = nan_max(m, d[u]);
     }
+    m = block_max256(m);
     if (threadIdx.x == 0) {
         const double old = __longlong_as_double((long long)*kickdev);
-        const double nw = red[0];
-        if (nw > old || nw != nw) *kickdev = (unsigned long long)__double_as_longlong(nw);
+        if (m > old || m != m) *kickdev = (unsigned long long)__double_as_longlong(m);
     }
 }
 
@@ -197,8 +201,6 @@ hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int
 // last block finish would need a device-scope release per block, which
 // writes back the L2 of its XCD each time and costs far more than a launch.)  Each site owns its bonds to its +x, +y and
 // +z neighbours (Eq. (2) counts every bond once).
-__device__ __forceinline__ double nan_max(double a, double c) { return (c > a || c != c) ? c : a; }
-__device__ __forceinline__ double nan_min(double a, double c) { return (c < a || c != c) ? c : a; }
 
 // The 8 reduced quantities: sums 0..5, max (6) and min (7) of |s|^2.  The
 // norm deviation max_i | |s_i| - 1 | follows from the extremes alone (sqrt and
@@ -412,6 +414,11 @@ __global__ void __launch_bounds__(kObsFinal)
                      double* accum, int accumulate, const double* kickpart, int kick_mode,
                      unsigned long long* kickdev) {
     const int r = blockIdx.x;
+    // the running sums are fetched first: their address needs nothing else
+    double a_old[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (accumulate && threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a_old[j] = accum[(int64_t)r * 8 + j];
     const RepDev& R = reps[r];
     // at most kFinalU partials per thread and pass, loaded together (and
     // before the kick fold, whose barriers would otherwise serialise them)
@@ -459,14 +466,14 @@ __global__ void __launch_bounds__(kObsFinal)
         if (accumulate) {
             double* a = accum + (int64_t)r * 8;
             const double m2 = mx * mx + my * my + mz * mz;
-            a[0] += 1.0;
-            a[1] += Et;
-            a[2] += Et * Et;
-            a[3] += sqrt(m2);
-            a[4] += m2;
-            a[5] += mx;
-            a[6] += my;
-            a[7] += mz;
+            a[0] = a_old[0] + 1.0;
+            a[1] = a_old[1] + Et;
+            a[2] = a_old[2] + Et * Et;
+            a[3] = a_old[3] + sqrt(m2);
+            a[4] = a_old[4] + m2;
+            a[5] = a_old[5] + mx;
+            a[6] = a_old[6] + my;
+            a[7] = a_old[7] + mz;
         }
     }
 }

@@ -848,10 +848,13 @@ extern "C" lll_status lll_kernel_timing(lll_lattice* L, int32_t enable, double* 
         if (E.kt_ev.empty()) {
             E.kt_ev.resize(64);
             E.kt_busy.assign(64, 0);
+            // timestamps only: no system-scope fence (cache writeback and
+            // invalidation) when the events complete, which would otherwise
+            // lengthen the timed launch and delay the next one
             for (auto& e : E.kt_ev) {
                 e.start = e.stop = nullptr;
-                HIP_TRY(hipEventCreate(&e.start));
-                HIP_TRY(hipEventCreate(&e.stop));
+                HIP_TRY(hipEventCreateWithFlags(&e.start, hipEventDisableSystemFence));
+                HIP_TRY(hipEventCreateWithFlags(&e.stop, hipEventDisableSystemFence));
             }
         }
         for (size_t j = 0; j < E.kt_ev.size(); ++j) E.kt_busy[j] = 0;

@@ -162,7 +162,10 @@ def test_kick_parity(P, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("kind", ["axis", "zaxis", "none"])
 @pytest.mark.parametrize("shape,bc", [((40, 24, 20), "periodic"), ((17, 5, 3), "free"),
-                                      ((1, 1, 1), "periodic"), ((2, 2, 2), "periodic")])
+                                      ((1, 1, 1), "periodic"), ((2, 2, 2), "periodic"),
+                                      # more work items than blocks, ragged last column run
+                                      # and ragged last z-slab
+                                      ((300, 100, 170), "periodic"), ((300, 100, 170), "free")])
 def test_observables_parity(P, prec, kind, shape, bc):
     N = int(np.prod(shape))
     s0 = rounded(inputs.unit_spins(N, 21) * 1.001, prec)
@@ -473,6 +476,13 @@ def test_full_size_overdamped_sampled(P):
         i = c[0] + 256 * (c[1] + 256 * c[2])
         err = np.max(np.abs(st[:, mid] - s1[:, i]))
         assert err < TOL["fp32"], (c, err)
+    # observables at full size (several work items per observables block)
+    got = lat.observables(gp)
+    want = orc.observables(orc.geom(shape), op, s1)
+    for k in ("E_total", "E_exch", "E_anis"):
+        assert got[k] == pytest.approx(want[k], rel=1e-12, abs=1e-13 * 256**3), k
+    np.testing.assert_allclose(got["m"], want["m"], rtol=1e-11, atol=1e-14)
+    assert got["max_norm_dev"] == pytest.approx(want["max_norm_dev"], rel=1e-12, abs=1e-16)
     lat.close()
 
 

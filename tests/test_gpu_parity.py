@@ -487,12 +487,13 @@ def test_full_size_overdamped_sampled(P):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_kick_maximum_same_on_every_fold_path(P, prec):
+@pytest.mark.parametrize("shape", [(40, 24, 20), (96, 96, 64)])  # 75 / 2304 per-site blocks
+def test_kick_maximum_same_on_every_fold_path(P, prec, shape):
     """The running maximum of | |s'| - 1 | over the kicks of a run is the same,
     bit for bit, whether each kick's maximum is folded by the next measurement,
     by a reduction before the next kick, or at the end of the run, for both
-    kick placements; and it matches the oracle's over the same interval."""
-    shape = (40, 24, 20)
+    kick placements; and it matches the oracle's over the same interval.  The
+    larger lattice has more per-block maxima than one pass of the fold loads."""
     op, gp = both_params("zaxis", dt=0.1, Dt=0.4, seed=21)
     got = {}
     for v in (0, 1):

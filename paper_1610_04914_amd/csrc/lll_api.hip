@@ -614,6 +614,15 @@ static lll_status lattice_params(lll_lattice* L, const lll_params* p, bool need_
     return LLL_OK;
 }
 
+// Sites of an Lx x Ly x Lz lattice (sizes >= 1), or -1 beyond 2^31 - 1; the
+// product is formed in two checked steps so that it cannot overflow.
+static int64_t checked_sites(int32_t Lx, int32_t Ly, int32_t Lz) {
+    const int64_t xy = (int64_t)Lx * Ly;  // < 2^62
+    if (xy > 0x7FFFFFFFLL) return -1;
+    const int64_t n = xy * Lz;            // < 2^62
+    return n > 0x7FFFFFFFLL ? -1 : n;
+}
+
 extern "C" lll_status lll_init_lattice(int32_t Lx, int32_t Ly, int32_t Lz, lll_bc bc,
                                        lll_precision prec, lll_init mode, const double dir[3],
                                        uint64_t seed, void* sx, void* sy, void* sz,
@@ -621,8 +630,8 @@ extern "C" lll_status lll_init_lattice(int32_t Lx, int32_t Ly, int32_t Lz, lll_b
     if (!out) return set_err(LLL_EINVAL, "out is NULL");
     *out = nullptr;
     if (Lx < 1 || Ly < 1 || Lz < 1) return set_err(LLL_EINVAL, "lattice sizes must be >= 1");
-    const int64_t N = (int64_t)Lx * Ly * Lz;
-    if (N > 0x7FFFFFFFLL) return set_err(LLL_EINVAL, "at most 2^31-1 sites");
+    const int64_t N = checked_sites(Lx, Ly, Lz);
+    if (N < 0) return set_err(LLL_EINVAL, "at most 2^31-1 sites");
     if (bc != LLL_BC_PERIODIC && bc != LLL_BC_FREE) return set_err(LLL_EINVAL, "bad boundary");
     if (prec != LLL_FP64 && prec != LLL_FP32) return set_err(LLL_EINVAL, "bad precision");
     if (mode != LLL_INIT_RANDOM_SPHERE && mode != LLL_INIT_DIRECTION && mode != LLL_INIT_KEEP)
@@ -1212,7 +1221,9 @@ extern "C" lll_status lll_batch_create(int32_t n_rep, const lll_replica_desc* re
         const lll_replica_desc& d = reps[r];
         if (d.Lx < 1 || d.Ly < 1 || d.Lz < 1) { delete B; return set_err(LLL_EINVAL, "replica %d: bad size", r); }
         if (d.bc != LLL_BC_PERIODIC && d.bc != LLL_BC_FREE) { delete B; return set_err(LLL_EINVAL, "replica %d: bad bc", r); }
-        total += (int64_t)d.Lx * d.Ly * d.Lz;
+        const int64_t nr = checked_sites(d.Lx, d.Ly, d.Lz);
+        if (nr < 0) { delete B; return set_err(LLL_EINVAL, "replica %d: at most 2^31-1 sites", r); }
+        total += nr;  // at most n_rep * 2^31, no overflow
         Phys ph{};
         ph.J = d.J;
         for (int c = 0; c < 3; ++c) { ph.H[c] = d.H[c]; ph.e[c] = d.e[c]; }

@@ -103,6 +103,11 @@ def test_validation_before_device_use(P):
     assert st == P.LLL_EINVAL
     st = L.lll_init_lattice(4, 4, 4, 0, 9, 0, None, 0, None, None, None, None, C.byref(h))
     assert st == P.LLL_EINVAL
+    # more than 2^31 - 1 sites, including products that overflow 64 bits
+    for shape in ((2048, 2048, 512), (46341, 46341, 1), (2**31 - 1, 2, 1),
+                  (2**21, 2**21, 2**21), (2**31 - 1, 2**31 - 1, 2**31 - 1)):
+        st = L.lll_init_lattice(*shape, 0, 1, 0, None, 0, None, None, None, None, C.byref(h))
+        assert st == P.LLL_EINVAL and b"2^31-1" in L.lll_last_error()
     st = L.lll_init_lattice(4, 4, 4, 0, 1, 0, None, 0, C.c_void_p(16), None, None, None, C.byref(h))
     assert st == P.LLL_EINVAL and b"all three" in L.lll_last_error()
     st = L.lll_init_lattice(4, 4, 4, 0, 1, P.LLL_INIT_KEEP, None, 0, None, None, None, None, C.byref(h))
@@ -122,6 +127,18 @@ def test_validation_before_device_use(P):
     desc[0].T = 1.0
     assert L.lll_batch_create(1, desc, 1, 0.3, 1.0, 1, None, C.byref(h)) == P.LLL_EINVAL
     assert b"not a positive integer" in L.lll_last_error()
+    big = (P.lll_replica_desc * 2)()
+    for d in big:
+        d.Lx = d.Ly = d.Lz = 2**21  # 2^63 sites each
+        d.lambda_ = 0.01
+        d.T = 1.0
+    big[0].Lx = big[0].Ly = big[0].Lz = 4
+    assert L.lll_batch_create(2, big, 1, 0.1, 1.0, 1, None, C.byref(h)) == P.LLL_EINVAL
+    assert b"replica 1" in L.lll_last_error()
+    for d in big:
+        d.Lx, d.Ly, d.Lz = 1024, 1024, 1024  # 2^30 each, 2^31 in all
+    assert L.lll_batch_create(2, big, 1, 0.1, 1.0, 1, None, C.byref(h)) == P.LLL_EINVAL
+    assert b"too many sites" in L.lll_last_error()
 
 
 def test_variant_table(P):

@@ -95,7 +95,26 @@ def cpu_baseline(steps: int = 4):
     el = time.perf_counter() - t0
     N = int(np.prod(SHAPE))
     return {"value": N * steps / el, "unit": "spin-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} RK4 steps of the 128^3 fp64 lattice ({el:.1f} s, one host thread)"}
+            "sample": f"{steps} RK4 steps of the 128^3 fp64 lattice ({el:.1f} s, one host thread)",
+            "host": host_info()}
+
+
+def host_info() -> dict:
+    """CPU model and the number of cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count()
+    return {"cpu_model": model, "affinity_cores": n}
 
 
 def _timed(fn):

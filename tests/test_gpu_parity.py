@@ -595,3 +595,51 @@ def test_rk2_fused_all_variants(P, prec, kind, precession):
                 err = np.max(np.abs(np_state(lat) - want))
                 assert err < TOL[prec], (shape, bc, v, bz, fused, err)
                 lat.close()
+
+
+# --------------------------------------------------------------- autotuner ---
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_autotune_restores_state_and_reuses_its_cache(P, prec, tmp_path):
+    """The autotuner times candidate step configurations on the lattice itself;
+    afterwards the state and the running kick maximum are exactly what they
+    were, the chosen configuration is written to the cache, a second lattice
+    of the same key takes it from the cache, a lattice of another key gets a
+    line of its own, and a malformed line is ignored.  Runs after tuning give
+    the same bits as runs on an untuned lattice set to the same configuration."""
+    cache = tmp_path / "tune.txt"
+    cache.write_text("this line is not a cache entry\n")
+    shape = (48, 40, 36)
+    op, gp = both_params("zaxis", dt=0.1, Dt=0.4, seed=5)
+    lat = P.Lattice(shape, precision=prec, init="random", seed=8)
+    lat.run(gp, first_pulse=0, n_pulses=2)  # leaves a non-zero kick maximum
+    s_before = lat.state.clone()
+    dev_before = lat.kick_norm_dev()
+    v, b = lat.autotune(gp, cache_path=str(cache))
+    torch.cuda.synchronize()
+    assert torch.equal(lat.state, s_before)
+    assert lat.kick_norm_dev() == dev_before
+    assert lat.step_config() == (v, b)
+    lines = [l.split() for l in cache.read_text().splitlines()]
+    entries = [l for l in lines if len(l) >= 3 and l[0] != "this"]
+    assert len(entries) == 1 and (int(entries[0][1]), int(entries[0][2])) == (v, b)
+    # same key: read from the cache, no new line
+    lat2 = P.Lattice(shape, precision=prec, init="random", seed=9)
+    assert lat2.autotune(gp, cache_path=str(cache)) == (v, b)
+    lines2 = [l for l in cache.read_text().splitlines() if l.strip()]
+    assert len(lines2) == len([l for l in lines if l])
+    # another key (other shape): one more line
+    lat3 = P.Lattice((16, 24, 20), precision=prec, init="random", seed=9)
+    lat3.autotune(gp, cache_path=str(cache))
+    assert len([l for l in cache.read_text().splitlines() if l.strip()]) == len(lines2) + 1
+    # tuned lattice vs an untuned one set to the same configuration: same bits
+    ref = P.Lattice(shape, precision=prec, state=s_before.clone())
+    ref.set_step_config(v, b)
+    fused = [l for l in entries if len(l) >= 4]
+    if fused:
+        ref.set_kick_fusion(int(fused[0][3]) != 0)
+    lat.run(gp, first_pulse=2, n_pulses=2)
+    ref.run(gp, first_pulse=2, n_pulses=2)
+    torch.cuda.synchronize()
+    assert torch.equal(lat.state, ref.state)
+    for L_ in (lat, lat2, lat3, ref):
+        L_.close()

@@ -15,7 +15,7 @@ fraction alongside), the batched and adjoint ratios and the 256^3 overdamped
 run ("extras", skipped with --no-extras), and the FP64 oracle timed on a
 bounded sample on the host ("cpu_baseline").
 
-Prints ONE JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
+Prints ONE JSON line.  --gpus above 1 is rejected: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -445,7 +445,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
-              "not part of this build", file=sys.stderr)
+              "not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

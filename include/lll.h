@@ -54,7 +54,7 @@ typedef enum {
     LLL_EINVAL = -1,        /* invalid argument (null pointer, bad size, non-integral Dt/dt, ...) */
     LLL_ENOMEM = -2,        /* device allocation failed */
     LLL_EDEVICE = -3,       /* a HIP runtime call failed */
-    LLL_EUNSUPPORTED = -4,  /* valid request this build or device does not support */
+    LLL_EUNSUPPORTED = -4,  /* valid request the library or the device does not support */
     LLL_ENONFINITE = -5,    /* a NaN/Inf was found in the state by a reduction */
     LLL_WARN_APPLICABILITY = 1 /* work done, but Eq. (8)/(9) or the step-size rule is violated */
 } lll_status;

@@ -161,3 +161,23 @@ def test_binding_fails_loudly_without_gpu(P):
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         P.Lattice((4, 4, 4))
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """No CPU fallback: with liblll.so absent every entry point raises."""
+    import subprocess
+    import sys
+    code = (
+        "import paper_1610_04914_amd as P\n"
+        f"P.LIB_PATH = {str(tmp_path / 'missing.so')!r}\n"
+        "for f in (P.lib, lambda: P.Lattice((8, 8, 8)), lambda: P.step_variants('fp32')):\n"
+        "    try:\n"
+        "        f()\n"
+        "    except (ImportError, RuntimeError):\n"
+        "        continue\n"
+        "    raise SystemExit('did not raise')\n"
+        "print('ok')\n")
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__file__))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr

@@ -56,8 +56,15 @@ typedef enum {
     LLL_EDEVICE = -3,       /* a HIP runtime call failed */
     LLL_EUNSUPPORTED = -4,  /* valid request the library or the device does not support */
     LLL_ENONFINITE = -5,    /* a NaN/Inf was found in the state by a reduction */
-    LLL_WARN_APPLICABILITY = 1 /* work done, but Eq. (8)/(9) or the step-size rule is violated */
+    LLL_WARN_APPLICABILITY = 1, /* work done, but Eq. (8)/(9) or the step-size rule is violated */
+    LLL_WARN_NORM = 2       /* work done, but a measured state has some | |s_i| - 1 | above
+                               LLL_NORM_WARN_LEVEL: the spin length, conserved by Eq. (1), has
+                               drifted that far within an interval (delta t too large for the
+                               local fields); takes precedence over LLL_WARN_APPLICABILITY */
 } lll_status;
+
+/* Threshold of LLL_WARN_NORM on max_i | |s_i| - 1 | of a measured state. */
+#define LLL_NORM_WARN_LEVEL 0.5
 
 typedef enum { LLL_FP64 = 0, LLL_FP32 = 1 } lll_precision;
 typedef enum { LLL_BC_PERIODIC = 0, LLL_BC_FREE = 1 } lll_bc;

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "liblll.so")
 
 LLL_OK = 0
 LLL_EINVAL, LLL_ENOMEM, LLL_EDEVICE, LLL_EUNSUPPORTED, LLL_ENONFINITE = -1, -2, -3, -4, -5
-LLL_WARN_APPLICABILITY = 1
+LLL_WARN_APPLICABILITY, LLL_WARN_NORM = 1, 2
 LLL_FP64, LLL_FP32 = 0, 1
 LLL_BC_PERIODIC, LLL_BC_FREE = 0, 1
 LLL_INIT_RANDOM_SPHERE, LLL_INIT_DIRECTION, LLL_INIT_KEEP = 0, 1, 2
@@ -34,7 +34,14 @@ class LLLError(RuntimeError):
 
 
 class ApplicabilityWarning(UserWarning):
-    pass
+    """LLL_WARN_APPLICABILITY: Eq. (8)/(9) or the step-size rule is violated."""
+
+
+class NormDriftWarning(UserWarning):
+    """LLL_WARN_NORM: a measured state's | |s_i| - 1 | exceeds NORM_WARN_LEVEL."""
+
+
+NORM_WARN_LEVEL = 0.5
 
 
 class lll_params(C.Structure):
@@ -131,7 +138,8 @@ def _check(status: int, what: str = "") -> int:
     if status < 0:
         raise LLLError(status, (lib().lll_last_error() or b"").decode() + (f" ({what})" if what else ""))
     if status > 0:
-        warnings.warn((lib().lll_last_error() or b"").decode(), ApplicabilityWarning, stacklevel=3)
+        cat = NormDriftWarning if status == LLL_WARN_NORM else ApplicabilityWarning
+        warnings.warn((lib().lll_last_error() or b"").decode(), cat, stacklevel=3)
     return status
 
 

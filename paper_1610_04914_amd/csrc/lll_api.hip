@@ -552,6 +552,21 @@ bool obs_finite(const double* r) {
     return true;
 }
 
+// Largest | |s_i| - 1 | of n measured records (slot 7); NaN records are reported
+// by obs_finite instead.
+double max_norm_dev_of(const double* h, int64_t n) {
+    double m = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+        if (h[8 * j + 7] > m) m = h[8 * j + 7];
+    return m;
+}
+
+lll_status norm_warning(double dev) {
+    return set_err(LLL_WARN_NORM,
+                   "spin length drifted: max | |s_i| - 1 | = %.3g exceeds %.2g (delta t too large "
+                   "for the local fields)", dev, (double)LLL_NORM_WARN_LEVEL);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- lattice ----
@@ -724,6 +739,7 @@ extern "C" lll_status lll_observables(lll_lattice* L, const lll_params* p, lll_o
     HIP_TRY(hipStreamSynchronize(E.st));
     obs_from(r, out);
     if (!obs_finite(r)) return set_err(LLL_ENONFINITE, "state contains NaN or Inf");
+    if (r[7] > LLL_NORM_WARN_LEVEL) return norm_warning(r[7]);
     return LLL_OK;
 }
 
@@ -775,6 +791,8 @@ extern "C" lll_status lll_run(lll_lattice* L, const lll_params* p, uint64_t firs
             fin = fin && obs_finite(&h[8 * j]);
         }
         if (!fin) return set_err(LLL_ENONFINITE, "state became NaN or Inf during the run");
+        const double dev = max_norm_dev_of(h.data(), nmeas);
+        if (dev > LLL_NORM_WARN_LEVEL) return norm_warning(dev);
     }
     if (applicability_warning(L->phys, p->dt, p->Dt, L->precession, Tmax))
         return set_err(LLL_WARN_APPLICABILITY,
@@ -1328,6 +1346,8 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
             fin = fin && obs_finite(&h[8 * j]);
         }
         if (!fin) return set_err(LLL_ENONFINITE, "a replica became NaN or Inf");
+        const double dev = max_norm_dev_of(h.data(), (int64_t)nmeas * E.nrep);
+        if (dev > LLL_NORM_WARN_LEVEL) return norm_warning(dev);
     }
     return LLL_OK;
 }
@@ -1347,6 +1367,8 @@ extern "C" lll_status lll_batch_observables(lll_batch* B, lll_obs* out) {
         fin = fin && obs_finite(&h[8 * r]);
     }
     if (!fin) return set_err(LLL_ENONFINITE, "a replica holds NaN or Inf");
+    const double dev = max_norm_dev_of(h.data(), E.nrep);
+    if (dev > LLL_NORM_WARN_LEVEL) return norm_warning(dev);
     return LLL_OK;
 }
 

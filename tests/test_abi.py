@@ -181,3 +181,16 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
+
+
+def test_status_codes_and_constants_match_header(P):
+    """Every lll_status value and the norm-warning threshold as the binding
+    spells them are the header's."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    enum = re.search(r"typedef enum \{(.*?)\} lll_status;", txt, re.S).group(1)
+    vals = dict((k, int(v)) for k, v in re.findall(r"(LLL_\w+)\s*=\s*(-?\d+)", enum))
+    assert len(vals) >= 8
+    for k, v in vals.items():
+        assert getattr(P, k) == v, k
+    lvl = float(re.search(r"#define LLL_NORM_WARN_LEVEL\s+([0-9.eE+-]+)", txt).group(1))
+    assert P.NORM_WARN_LEVEL == lvl

@@ -54,3 +54,37 @@ def test_independent_spins_reach_the_langevin_function(P):
     lat.close()
     got = float(np.mean([o["m"][2] for o in tr]))
     assert got == pytest.approx(want, abs=0.01), got
+
+
+def test_spin_length_drift_warns(P):
+    """RK4 does not conserve |s|: for precession about H = 2 z at delta t = 1
+    (H delta t = 2) each step shrinks the transverse component by |R(2i)| =
+    0.745, so half an interval (5 steps) leaves | |s| - 1 | near 0.77 at the
+    measurement; run and observables report LLL_WARN_NORM (a warning: the work
+    is done, the state stays finite), which outranks the applicability warning
+    the same parameters raise.  A well-resolved run does not warn."""
+    import warnings
+    p = P.Params(J=0.0, H=(0.0, 0.0, 2.0), lam=0.0, T=0.0, dt=1.0, Dt=10.0, seed=1)
+    lat = P.Lattice((8, 8, 8), precision="fp64", init="random", seed=4)
+    with pytest.warns(P.NormDriftWarning):
+        tr = lat.run(p, first_pulse=0, n_pulses=2, obs_every=1)
+    assert all(math.isfinite(o["max_norm_dev"]) for o in tr)
+    assert max(o["max_norm_dev"] for o in tr) > P.NORM_WARN_LEVEL
+    with pytest.warns(P.NormDriftWarning):
+        lat.observables(p)
+    lat.close()
+    # the status itself, through the C ABI, on a fresh lattice (each renormalisation
+    # tilts these spins towards the field axis, so later intervals drift less)
+    import ctypes
+    fresh = P.Lattice((8, 8, 8), precision="fp64", init="random", seed=4)
+    pc = p.c()
+    st = P.lib().lll_run(fresh.h, ctypes.byref(pc), 0, 1, None, 1, (P.lll_obs * 1)())
+    assert st == P.LLL_WARN_NORM
+    fresh.close()
+    q = P.Params(J=0.0, H=(0.0, 0.0, 2.0), lam=0.0, T=0.0, dt=0.05, Dt=0.5, seed=1)
+    ok = P.Lattice((8, 8, 8), precision="fp64", init="random", seed=4)
+    with warnings.catch_warnings():
+        warnings.simplefilter("error", P.NormDriftWarning)
+        ok.run(q, first_pulse=0, n_pulses=2, obs_every=1)
+        ok.observables(q)
+    ok.close()

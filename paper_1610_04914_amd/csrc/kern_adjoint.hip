@@ -32,9 +32,7 @@ __device__ __forceinline__ bool adj_site(const RepDev* reps, const int32_t* blk_
     c.i = (int64_t)(b - R.sb0) * kAdjBlock + threadIdx.x;
     c.gi = R.off + c.i;
     if (c.i >= N) return false;
-    c.x = (int)(c.i % R.Lx);
-    c.y = (int)((c.i / R.Lx) % R.Ly);
-    c.z = (int)(c.i / ((int64_t)R.Lx * R.Ly));
+    site_xyz(c.i, R.Lx, R.Ly, c.x, c.y, c.z);
     return true;
 }
 

@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(kObsBlock)
             const int64_t c = cb * kObsBlock + threadIdx.x;
             const bool okc = c < Lxy;
             const int64_t cc = okc ? c : 0;
-            const int y = (int)(cc / Lx), x = (int)(cc - (int64_t)y * Lx);
+            const int y = (int)((uint32_t)cc / (uint32_t)Lx), x = (int)(cc - (int64_t)y * Lx);
             // +x and +y offsets (wrapped at the far face; a missing
             // free-boundary bond still reads a valid site and is dropped)
             const int64_t ox = x + 1 < Lx ? 1 : 1 - Lx;
@@ -529,9 +529,8 @@ __device__ __forceinline__ void site_k(const RepDev& R, const SiteCtx& c, const 
                                        T& ky, T& kz) {
     const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
     const int64_t N = (int64_t)Lx * Ly * Lz;
-    const int x = (int)(c.i % Lx);
-    const int y = (int)((c.i / Lx) % Ly);
-    const int z = (int)(c.i / ((int64_t)Lx * Ly));
+    int x, y, z;
+    site_xyz(c.i, Lx, Ly, x, y, z);
     const bool pbc = R.bc == 0;
     const T* yx = static_cast<const T*>(yin.x);
     const T* yy = static_cast<const T*>(yin.y);

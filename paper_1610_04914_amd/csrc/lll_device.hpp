@@ -183,6 +183,18 @@ __device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off) {
 }
 
 
+// Coordinates of site i of an Lx x Ly x Lz lattice.  Sites number fewer than
+// 2^31, so two 32-bit unsigned divisions suffice (a 64-bit division is a long
+// software sequence on the GPU).
+__device__ __forceinline__ void site_xyz(int64_t i, int Lx, int Ly, int& x, int& y, int& z) {
+    const uint32_t u = (uint32_t)i, lx = (uint32_t)Lx, ly = (uint32_t)Ly;
+    const uint32_t q = u / lx;
+    const uint32_t zz = q / ly;
+    x = (int)(u - q * lx);
+    y = (int)(q - zz * ly);
+    z = (int)zz;
+}
+
 // Stage coefficients of one replica in the working precision.
 template <typename T>
 struct Coef {

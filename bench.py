@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -420,6 +421,31 @@ def extra_headline_variants(lat, p, n_pulses: int = 400, repeats: int = 5):
     return out
 
 
+def extra_temperatures(n_pulses: int = 1000, tail: int = 500):
+    """The headline workload at the three temperatures of its specification
+    (T = 0.5, 1.0, 1.4; fp32, random start, seed 0): rate, and the time averages
+    of E/N and |m| over the last `tail` intervals."""
+    import torch
+    import paper_1610_04914_amd as P
+    out = {}
+    for T in (0.5, 1.0, 1.4):
+        p = P.Params(**dict(PHYS, T=T))
+        lat = P.Lattice(SHAPE, precision="fp32", init="random", seed=0)
+        configure_lattice(lat, "fp32", SHAPE)
+        n = int(round(PHYS["Dt"] / PHYS["dt"]))
+        el, tr = _timed(lambda: lat.run(p, first_pulse=0, n_pulses=n_pulses, obs_every=1))
+        last = tr[-tail:]
+        N = lat.N
+        out[f"T={T}"] = {
+            "spin_steps_per_s": N * n * n_pulses / el,
+            "E_per_site": sum(o["E_total"] for o in last) / (len(last) * N),
+            "abs_m": sum(math.sqrt(sum(c * c for c in o["m"])) for o in last) / len(last),
+            "intervals": n_pulses, "averaged_over": tail}
+        lat.close()
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -516,6 +542,7 @@ def main():
     }
     if args.extras:
         out["extras"] = {"headline_variants": extra_headline_variants(lat, p),
+                         "temperatures": extra_temperatures(),
                          "batched": extra_batched(), "adjoint": extra_adjoint(),
                          "overdamped_256": extra_overdamped(), "integrators": extra_integrators(),
                          "escape": extra_escape(), "precision": extra_precision()}

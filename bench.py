@@ -421,6 +421,32 @@ def extra_headline_variants(lat, p, n_pulses: int = 400, repeats: int = 5):
     return out
 
 
+def extra_headline_256(n_pulses: int = 100):
+    """The headline physics on 256^3 (fp32, 201 MB per state copy, so the two
+    copies a step reads and writes exceed the 256 MB Infinity Cache): rate, and
+    the fused step's mean duration from dispatch events as algorithmic HBM
+    bandwidth."""
+    import torch
+    import paper_1610_04914_amd as P
+    shape = (256, 256, 256)
+    p = P.Params(**PHYS)
+    lat = P.Lattice(shape, precision="fp32", init="random", seed=0)
+    variant, bz = configure_lattice(lat, "fp32", shape)
+    n = int(round(PHYS["Dt"] / PHYS["dt"]))
+    lat.run(p, first_pulse=0, n_pulses=20, obs_every=1)
+    lat.kernel_timing_start()
+    el, _ = _timed(lambda: lat.run(p, first_pulse=20, n_pulses=n_pulses, obs_every=1))
+    ms, nt = lat.kernel_timing_stop()
+    N = lat.N
+    lat.close()
+    torch.cuda.synchronize()
+    gbs = BYTES_PER_SPIN_STEP["fp32"] * N / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"workload": "256^3, headline physics, fp32, obs every interval",
+            "spin_steps_per_s": N * n * n_pulses / el, "step_variant": variant, "bz": bz,
+            "fused_launch_us": ms * 1e3, "launches_timed": nt,
+            "alg_hbm_gbs": gbs, "alg_hbm_frac": gbs / HBM_PEAK_GBS}
+
+
 def extra_temperatures(n_pulses: int = 1000, tail: int = 500):
     """The headline workload at the three temperatures of its specification
     (T = 0.5, 1.0, 1.4; fp32, random start, seed 0): rate, and the time averages
@@ -543,6 +569,7 @@ def main():
     if args.extras:
         out["extras"] = {"headline_variants": extra_headline_variants(lat, p),
                          "temperatures": extra_temperatures(),
+                         "headline_256": extra_headline_256(),
                          "batched": extra_batched(), "adjoint": extra_adjoint(),
                          "overdamped_256": extra_overdamped(), "integrators": extra_integrators(),
                          "escape": extra_escape(), "precision": extra_precision()}

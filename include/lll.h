@@ -122,7 +122,7 @@ typedef struct lll_batch lll_batch;
  * mode/dir/seed: initial state (dir is read for LLL_INIT_DIRECTION only; the
  * seed keys the random sphere, replica 0).
  * On success *out receives the handle.  Errors: LLL_EINVAL (L < 1, null out,
- * partial buffers, dir zero), LLL_ENOMEM, LLL_EDEVICE. */
+ * partial buffers, dir zero, more than 2^31 - 1 sites), LLL_ENOMEM, LLL_EDEVICE. */
 lll_status lll_init_lattice(int32_t Lx, int32_t Ly, int32_t Lz, lll_bc bc, lll_precision prec,
                             lll_init mode, const double dir[3], uint64_t seed, void* sx, void* sy,
                             void* sz, void* hip_stream, lll_lattice** out);
@@ -137,7 +137,8 @@ lll_status lll_step_conservative(lll_lattice* lat, const lll_params* params, int
 lll_status lll_noise_pulse(lll_lattice* lat, const lll_params* params, uint64_t pulse_index);
 
 /* Observables of the current state into *out_host (synchronises the stream).
- * LLL_ENONFINITE when the state holds a NaN or Inf (out_host is still filled). */
+ * LLL_ENONFINITE when the state holds a NaN or Inf; LLL_WARN_NORM when its
+ * max_norm_dev exceeds LLL_NORM_WARN_LEVEL (out_host is filled in both cases). */
 lll_status lll_observables(lll_lattice* lat, const lll_params* params, lll_obs* out_host);
 
 /* n_pulses intervals (n1 steps, kick k, n2 steps) for k = first_pulse ...
@@ -146,8 +147,10 @@ lll_status lll_observables(lll_lattice* lat, const lll_params* params, lll_obs* 
  * the observables after every obs_every-th interval are written to
  * trace[0 .. n_pulses/obs_every) (host memory; the call then synchronises).
  * Calling step(n1), pulse(k), step(n2) in order gives the same result bit for
- * bit.  Returns LLL_WARN_APPLICABILITY (> 0) after doing the work when the
- * parameters violate the applicability conditions. */
+ * bit.  Returns LLL_ENONFINITE when a traced measurement holds a NaN or Inf;
+ * after doing the work, LLL_WARN_NORM (> 0) when a traced measurement's
+ * max_norm_dev exceeds LLL_NORM_WARN_LEVEL, else LLL_WARN_APPLICABILITY (> 0)
+ * when the parameters violate the applicability conditions. */
 lll_status lll_run(lll_lattice* lat, const lll_params* params, uint64_t first_pulse,
                    int64_t n_pulses, const double* T_per_pulse, int32_t obs_every,
                    lll_obs* trace);
@@ -230,9 +233,12 @@ lll_status lll_batch_create(int32_t n_rep, const lll_replica_desc* reps, lll_pre
                             double dt, double Dt, int32_t precession, void* hip_stream,
                             lll_batch** out);
 /* Runs n_pulses intervals on every replica.  trace (optional, host):
- * [n_pulses/obs_every][n_rep] lll_obs. */
+ * [n_pulses/obs_every][n_rep] lll_obs; with a trace the call synchronises and
+ * returns LLL_ENONFINITE or LLL_WARN_NORM as lll_run does, over all replicas. */
 lll_status lll_batch_run(lll_batch* b, uint64_t first_pulse, int64_t n_pulses, int32_t obs_every,
                          lll_obs* trace);
+/* Observables of every replica's current state (synchronises); statuses as
+ * lll_observables, over all replicas. */
 lll_status lll_batch_observables(lll_batch* b, lll_obs* out_host /* [n_rep] */);
 lll_status lll_batch_state(lll_batch* b, int32_t rep, void** sx, void** sy, void** sz);
 /* FP64 running sums of every replica since creation: out_host[8*n_rep] as in lll_accumulators. */

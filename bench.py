@@ -218,6 +218,7 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
     rate_s = sites * 10 * n_seq / el_s
     return {"workload": "96 replicas (32 x 24^3, 48^3, 64^3), fp32 batch vs fp64 single-lattice path",
             "batched_fp32_spin_steps_per_s": rate_b,
+            "batched_alg_hbm_frac": rate_b * BYTES_PER_SPIN_STEP["fp32"] / (HBM_PEAK_GBS * 1e9),
             "sequential_fp64_spin_steps_per_s": rate_s,
             "speedup": rate_b / rate_s,
             "pulses_timed": {"batch": n_pulses, "sequential": n_seq},

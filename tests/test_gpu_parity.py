@@ -324,13 +324,27 @@ def test_full_size_sampled(P, prec):
 
 
 # ------------------------------------------------------------------ batch ---
+BATCH_SETS = {
+    "mixed": [dict(L=(8, 8, 8), T=0.5, lam=0.02, seed=11, replica=0),
+              dict(L=(12, 12, 12), T=1.5, lam=0.005, seed=12, replica=1),
+              dict(L=(5, 6, 7), T=1.0, lam=0.05, seed=13, replica=2, H=(0, 0, 0.2)),
+              dict(L=(24, 24, 24), T=0.3, lam=0.01, seed=14, replica=3, D=0.05),
+              dict(L=(17, 9, 3), T=2.0, lam=0.03, seed=15, replica=4, bc="free")],
+    # degenerate and flat replicas next to one large enough for the fused step
+    # and for several observables blocks: a single spin, an open chain, a
+    # periodic 2-D plane, a free 1-site-thick slab
+    "degenerate": [dict(L=(1, 1, 1), T=1.0, lam=0.05, seed=21, replica=0, H=(0, 0, 0.3)),
+                   dict(L=(7, 1, 1), T=0.8, lam=0.02, seed=22, replica=1, bc="free"),
+                   dict(L=(40, 36, 1), T=1.2, lam=0.01, seed=23, replica=2),
+                   dict(L=(9, 11, 1), T=0.4, lam=0.03, seed=24, replica=3, bc="free", D=0.05),
+                   dict(L=(64, 48, 40), T=1.0, lam=0.01, seed=25, replica=4, H=(0.1, 0, 0))],
+}
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_batch_matches_oracle(P, prec):
-    reps = [dict(L=(8, 8, 8), T=0.5, lam=0.02, seed=11, replica=0),
-            dict(L=(12, 12, 12), T=1.5, lam=0.005, seed=12, replica=1),
-            dict(L=(5, 6, 7), T=1.0, lam=0.05, seed=13, replica=2, H=(0, 0, 0.2)),
-            dict(L=(24, 24, 24), T=0.3, lam=0.01, seed=14, replica=3, D=0.05),
-            dict(L=(17, 9, 3), T=2.0, lam=0.03, seed=15, replica=4, bc="free")]
+@pytest.mark.parametrize("which", sorted(BATCH_SETS))
+def test_batch_matches_oracle(P, prec, which):
+    reps = BATCH_SETS[which]
     dt, Dt = 0.1, 0.4
     B = P.Batch(reps, precision=prec, dt=dt, Dt=Dt)
     prev = []

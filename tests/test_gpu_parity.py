@@ -93,7 +93,8 @@ def test_init_random_sphere(P, prec, shape):
 # ------------------------------------------------------------------ steps ---
 STEP_SHAPES = [((40, 24, 20), "periodic", 7), ((40, 24, 20), "free", 0), ((17, 5, 3), "periodic", 0),
                ((3, 3, 3), "periodic", 0), ((2, 3, 5), "free", 2), ((1, 1, 1), "periodic", 0),
-               ((2, 2, 2), "periodic", 0), ((33, 17, 9), "periodic", 4)]
+               ((2, 2, 2), "periodic", 0), ((33, 17, 9), "periodic", 4),
+               ((40, 36, 1), "periodic", 0), ((7, 1, 1), "free", 0), ((1, 9, 2), "periodic", 0)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

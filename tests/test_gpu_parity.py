@@ -194,15 +194,17 @@ def test_observables_nonfinite(P):
 # ------------------------------------------------------------- schedule -----
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("dt,Dt", [(0.1, 0.4), (0.1, 0.3), (0.2, 0.2)])
-def test_run_per_segment(P, prec, dt, Dt):
+@pytest.mark.parametrize("shape,bc", [((40, 24, 20), "periodic"), ((40, 36, 1), "periodic"),
+                                      ((23, 9, 5), "free")])
+def test_run_per_segment(P, prec, dt, Dt, shape, bc):
     """Each interval (n1 steps, kick, n2 steps) of lll_run against the oracle
-    started from the GPU's state before that interval."""
-    shape = (40, 24, 20)
+    started from the GPU's state before that interval, on every step variant
+    (kick as the fused epilogue where the step is fused)."""
     N = int(np.prod(shape))
     op, gp = both_params("zaxis", dt=dt, Dt=Dt, seed=5)
-    g = orc.geom(shape)
+    g = orc.geom(shape, bc)
     for v in variants(P, prec):
-        lat = P.Lattice(shape, precision=prec, init="random", seed=9)
+        lat = P.Lattice(shape, bc=bc, precision=prec, init="random", seed=9)
         lat.set_step_config(v, 0)
         prev = np_state(lat)
         for q in range(3):

@@ -43,6 +43,8 @@ CASES = [
     ((7, 3, 5), "free", True, False, 0.1, 0.3, 2, 4),
     ((5, 5, 5), "periodic", False, True, 0.2, 0.4, 3, 5),
     ((4, 4, 4), "periodic", True, False, 0.1, 0.1, 3, 1),
+    # a thin free lattice with one checkpoint block longer than the whole run
+    ((2, 1, 3), "free", True, True, 0.1, 0.2, 2, 100),
 ]
 
 

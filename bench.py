@@ -59,11 +59,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def configure_lattice(lat, prec: str, shape) -> tuple:
+def configure_lattice(lat, prec: str, shape, p=None) -> tuple:
     """Step configuration used by the benchmark: the committed tuning table
-    entry for this lattice when there is one, else an autotune run."""
+    entry for this lattice (and physics p, default the headline's) when there is
+    one, else an autotune run."""
     import paper_1610_04914_amd as P
-    p = P.Params(**PHYS)
+    if p is None:
+        p = P.Params(**PHYS)
     return lat.autotune(p, cache_path=TUNE_CACHE)
 
 
@@ -448,6 +450,41 @@ def extra_headline_256(n_pulses: int = 100):
             "alg_hbm_gbs": gbs, "alg_hbm_frac": gbs / HBM_PEAK_GBS}
 
 
+def extra_config_16():
+    """The small-lattice configuration in full: 16^3 periodic, J = 1, H = D = 0,
+    lambda = 0.01, T = 1, fp64, RK4 dt = 0.1, a pulse every Dt = 1 (10 steps),
+    1000 pulses from a random start (seed 0), observables every interval; on
+    the GPU and with the FP64 oracle on one host thread (the same work; the
+    trajectories part ways after a few intervals, as chaotic ones do, so only
+    the final energies' magnitude is comparable).  Latency-bound on the GPU:
+    4096 sites are 16 workgroups of the fused step."""
+    import numpy as np
+    import paper_1610_04914_amd as P
+    import oracle as orc
+    shape = (16, 16, 16)
+    kw = dict(J=1.0, H=(0.0, 0.0, 0.0), D=0.0, e=(0.0, 0.0, 1.0), lam=0.01, T=1.0, dt=0.1, Dt=1.0)
+    n_pulses = 1000
+    lat = P.Lattice(shape, precision="fp64", init="random", seed=0)
+    s0 = lat.state.double().cpu().numpy()
+    variant, bz = configure_lattice(lat, "fp64", shape, P.Params(seed=0, **kw))
+    lat.run(P.Params(seed=0, **kw), first_pulse=0, n_pulses=20)  # first launches
+    lat.state.copy_(lat.state.new_tensor(s0))
+    el_g, tr = _timed(lambda: lat.run(P.Params(seed=0, **kw), first_pulse=0, n_pulses=n_pulses,
+                                      obs_every=1))
+    lat.close()
+    t0 = time.perf_counter()
+    _, otr, _ = orc.run(orc.geom(shape), orc.Params(**kw), s0, seed=0, n_pulses=n_pulses,
+                        obs_every=n_pulses)
+    el_c = time.perf_counter() - t0
+    N = int(np.prod(shape))
+    steps = 10 * n_pulses
+    return {"workload": "16^3 fp64, 1000 pulses of 10 RK4 steps", "step_variant": variant, "bz": bz,
+            "gpu_spin_steps_per_s": N * steps / el_g,
+            "oracle_spin_steps_per_s": N * steps / el_c, "oracle_seconds": el_c,
+            "gpu_final_E_per_site": tr[-1]["E_total"] / N,
+            "oracle_final_E_per_site": otr[-1]["E_total"] / N}
+
+
 def extra_temperatures(n_pulses: int = 1000, tail: int = 500):
     """The headline workload at the three temperatures of its specification
     (T = 0.5, 1.0, 1.4; fp32, random start, seed 0): rate, and the time averages
@@ -581,6 +618,7 @@ def main():
         out["extras"] = {"headline_variants": extra_headline_variants(lat, p),
                          "temperatures": extra_temperatures(),
                          "headline_256": extra_headline_256(),
+                         "config_16": extra_config_16(),
                          "batched": extra_batched(), "adjoint": extra_adjoint(),
                          "overdamped_256": extra_overdamped(), "integrators": extra_integrators(),
                          "escape": extra_escape(), "precision": extra_precision()}

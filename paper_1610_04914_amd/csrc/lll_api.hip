@@ -78,6 +78,11 @@ struct Engine {
     // -1 none, 0 per-site blocks, 1 fused-step tiles (folded by the next
     // measurement, or by a reduction launch before the next kick / run end)
     int kick_pending = -1;
+    // With n = 1 (kick first in every interval) the next interval's kick can be
+    // applied as the epilogue of this interval's step; carried_k then names
+    // the pulse already applied, which the next interval skips.
+    bool carried = false;
+    uint64_t carried_k = 0;
     double* d_trace = nullptr;
     size_t trace_cap = 0;         // doubles
     int variant = 0, bz = 0;      // step configuration (0 = unfused)
@@ -505,15 +510,36 @@ lll_status settle(Engine& E) {
 }
 
 // One interval of Eq. (7): n1 steps, kick, n2 steps.
-lll_status do_interval(Engine& E, int64_t n, uint64_t k, double sigma_override) {
+// look: the caller runs interval k_next (kick scale so_next) right after this
+// one with no measurement in between; when that interval starts with its kick
+// (n1 = 0), the kick is done here, as the epilogue of this interval's last step
+// where the fused step is used (the same state at the same point of the
+// schedule, so the same bits).
+lll_status do_interval(Engine& E, int64_t n, uint64_t k, double sigma_override, bool look,
+                       uint64_t k_next, double so_next) {
     const int64_t n1 = n / 2, n2 = n - n1;
     lll_status s;
     if (n1 > 0) {
+        E.carried = false;
         if ((s = do_steps(E, n1, true, k, sigma_override)) != LLL_OK) return s;
+    } else if (E.carried && E.carried_k == k) {
+        E.carried = false;  // applied at the end of the previous interval
     } else {
+        E.carried = false;
         if ((s = do_kick(E, k, sigma_override)) != LLL_OK) return s;
     }
-    return do_steps(E, n2, false, 0, -1.0);
+    const bool carry = look && n1 == 0;
+    if ((s = do_steps(E, n2, carry, k_next, so_next)) != LLL_OK) return s;
+    if (carry) {
+        E.carried = true;
+        E.carried_k = k_next;
+    }
+    return LLL_OK;
+}
+
+lll_status do_interval(Engine& E, int64_t n, uint64_t k, double sigma_override) {
+    E.carried = false;
+    return do_interval(E, n, k, sigma_override, false, 0, -1.0);
 }
 
 // Observables into result; folds a pending kick maximum in the same launches.
@@ -768,11 +794,16 @@ extern "C" lll_status lll_run(lll_lattice* L, const lll_params* p, uint64_t firs
     if (want_trace && (s = ensure_trace(E, (size_t)nmeas * 8)) != LLL_OK) return s;
     if ((s = settle(E)) != LLL_OK) return s;
     int64_t m = 0;
+    E.carried = false;
     for (int64_t q = 0; q < n_pulses; ++q) {
         const uint64_t k = first_pulse + (uint64_t)q;
         const double so = T_per_pulse ? sqrt(2.0 * p->lambda * T_per_pulse[q] * L->Dt) : -1.0;
-        if ((s = do_interval(E, n, k, so)) != LLL_OK) return s;
-        if (obs_every > 0 && (q + 1) % obs_every == 0) {
+        const bool measure = obs_every > 0 && (q + 1) % obs_every == 0;
+        const bool look = q + 1 < n_pulses && !measure;
+        const double so_next =
+            look && T_per_pulse ? sqrt(2.0 * p->lambda * T_per_pulse[q + 1] * L->Dt) : -1.0;
+        if ((s = do_interval(E, n, k, so, look, k + 1, so_next)) != LLL_OK) return s;
+        if (measure) {
             double* dst = want_trace ? E.d_trace + 8 * m : E.d_result;
             if ((s = do_obs(E, dst, 1)) != LLL_OK) return s;
             ++m;
@@ -1306,9 +1337,12 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         int64_t m = 0;
         lll_status cap = LLL_OK;
+        E.carried = false;
         for (int64_t q = 0; q < n_pulses && cap == LLL_OK; ++q) {
-            cap = do_interval(E, B->n, first_pulse + (uint64_t)q, -1.0);
-            if (cap == LLL_OK && obs_every > 0 && (q + 1) % obs_every == 0) {
+            const uint64_t k = first_pulse + (uint64_t)q;
+            const bool measure = obs_every > 0 && (q + 1) % obs_every == 0;
+            cap = do_interval(E, B->n, k, -1.0, q + 1 < n_pulses && !measure, k + 1, -1.0);
+            if (cap == LLL_OK && measure) {
                 cap = do_obs(E, E.d_trace + (size_t)8 * E.nrep * m, 1);
                 ++m;
             }

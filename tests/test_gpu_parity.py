@@ -7,6 +7,8 @@ starting the oracle from the GPU's own state (chaotic dynamics forbids whole
 trajectory comparisons).  Random words and the sphere's z component are
 compared bit for bit.  Observables: relative 1e-12 (fp64 reductions).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -258,6 +260,65 @@ def test_schedule_identity_bitexact(P, prec):
         torch.cuda.synchronize()
         assert torch.equal(a.state, e.state), v
         assert e.kick_norm_dev() == a2.kick_norm_dev(), v
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_schedule_identity_one_step_intervals(P, prec):
+    """Delta t = delta t (n = 1: kick, then the step).  A run of K intervals,
+    which applies each next interval's kick as the epilogue of the step before
+    it (with that interval's temperature), equals K runs of one interval and
+    the pulse/step sequence, bit for bit, with or without measurements in
+    between and with the kick fused or in its own launch; the running kick
+    maximum is the same too."""
+    shape = (40, 24, 20)
+    _, gp = both_params("zaxis", dt=0.2, Dt=0.2, lam=0.1, seed=6, precession=False)
+    Ts = [2.0, 1.4, 0.9, 0.5, 0.3]
+    K = len(Ts)
+    for v in variants(P, prec):
+        for fused in (True, False):
+            lats = [P.Lattice(shape, precision=prec, seed=2) for _ in range(4)]
+            for L in lats:
+                L.set_step_config(v, 0)
+                L.set_kick_fusion(fused)
+                L.kick_norm_dev(reset=True)
+            a, b, c, d = lats
+            a.run(gp, first_pulse=30, n_pulses=K, T_per_pulse=Ts)
+            for q in range(K):
+                b.run(gp, first_pulse=30 + q, n_pulses=1, T_per_pulse=[Ts[q]])
+                c.pulse(dataclasses.replace(gp, T=Ts[q]), 30 + q)
+                c.step(gp, 1)
+            tr = d.run(gp, first_pulse=30, n_pulses=K, T_per_pulse=Ts, obs_every=2)
+            torch.cuda.synchronize()
+            for o in (b, c, d):
+                assert torch.equal(a.state, o.state), (v, fused)
+            assert len({L.kick_norm_dev() for L in lats}) == 1, (v, fused)
+            assert len(tr) == K // 2
+            o2 = P.Lattice(shape, precision=prec, seed=2)
+            o2.set_step_config(v, 0)
+            o2.run(gp, first_pulse=30, n_pulses=2, T_per_pulse=Ts[:2])
+            assert tr[0]["E_total"] == pytest.approx(o2.observables(gp)["E_total"], rel=1e-14)
+            for L in lats + [o2]:
+                L.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_one_step_intervals_bitexact(P, prec):
+    """Batch with n = 1: one replay of K intervals equals K replays of one
+    interval, bit for bit, with and without measurements in between."""
+    reps = BATCH_SETS["mixed"]
+    A = P.Batch(reps, precision=prec, dt=0.2, Dt=0.2)
+    B = P.Batch(reps, precision=prec, dt=0.2, Dt=0.2)
+    C = P.Batch(reps, precision=prec, dt=0.2, Dt=0.2)
+    A.run(first_pulse=5, n_pulses=4)
+    for q in range(4):
+        B.run(first_pulse=5 + q, n_pulses=1)
+    C.run(first_pulse=5, n_pulses=4, obs_every=3)
+    torch.cuda.synchronize()
+    for r in range(len(reps)):
+        assert torch.equal(A.state(r), B.state(r)), r
+        assert torch.equal(A.state(r), C.state(r)), r
+    for X in (A, B, C):
+        X.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

@@ -510,6 +510,12 @@ def extra_temperatures(n_pulses: int = 1000, tail: int = 500):
     return out
 
 
+EXTRAS = {"temperatures": extra_temperatures, "headline_256": extra_headline_256,
+          "config_16": extra_config_16, "batched": extra_batched, "adjoint": extra_adjoint,
+          "overdamped_256": extra_overdamped, "integrators": extra_integrators,
+          "escape": extra_escape, "precision": extra_precision}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -524,7 +530,18 @@ def main():
                     help="skip the batched, adjoint and 256^3 overdamped workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--extra", default=None, metavar="NAME",
+                    help="only run the named extra workload (one of: " + ", ".join(EXTRAS) +
+                         ") and print its JSON")
     args = ap.parse_args()
+    if args.extra is not None:
+        if args.extra not in EXTRAS:
+            ap.error(f"unknown extra {args.extra!r}")
+        import warnings
+        import paper_1610_04914_amd as P
+        warnings.simplefilter("ignore", P.ApplicabilityWarning)
+        print(json.dumps({args.extra: EXTRAS[args.extra]()}))
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * 2**20 // 4
@@ -616,12 +633,7 @@ def main():
     }
     if args.extras:
         out["extras"] = {"headline_variants": extra_headline_variants(lat, p),
-                         "temperatures": extra_temperatures(),
-                         "headline_256": extra_headline_256(),
-                         "config_16": extra_config_16(),
-                         "batched": extra_batched(), "adjoint": extra_adjoint(),
-                         "overdamped_256": extra_overdamped(), "integrators": extra_integrators(),
-                         "escape": extra_escape(), "precision": extra_precision()}
+                         **{name: fn() for name, fn in EXTRAS.items()}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out))

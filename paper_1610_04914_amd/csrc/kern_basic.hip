@@ -118,13 +118,13 @@ __device__ __forceinline__ void block_max_part(double v, double* part) {
     if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
-// Maximum over the parts of replica R (its per-site blocks, or its fused-step
-// tiles in tile order) folded into *kickdev by thread 0; the whole block of
-// 256 threads takes part, each thread with up to eight loads in flight.
-__device__ __forceinline__ void kickmax_fold(const RepDev& R, const double* part, int by_tiles,
+// Maximum over the parts of replica R (its per-site blocks) folded into
+// *kickdev by thread 0; the whole block of 256 threads takes part, each thread
+// with up to eight loads in flight.
+__device__ __forceinline__ void kickmax_fold(const RepDev& R, const double* part,
                                              unsigned long long* kickdev) {
-    const int p0 = by_tiles ? R.tile0 : R.sb0;
-    const int np = by_tiles ? R.tx * R.ty * R.tz : R.nsb;
+    const int p0 = R.sb0;
+    const int np = R.nsb;
     constexpr int U = 8;
     double m = 0.0;
     for (int q0 = threadIdx.x; q0 < np; q0 += 256 * U) {
@@ -146,15 +146,14 @@ __device__ __forceinline__ void kickmax_fold(const RepDev& R, const double* part
 
 // Block r: kick maximum of replica r folded into kickdev[r].
 __global__ void __launch_bounds__(256)
-    kickmax_reduce(const RepDev* reps, const double* part, int by_tiles,
-                   unsigned long long* kickdev) {
-    kickmax_fold(reps[blockIdx.x], part, by_tiles, kickdev + blockIdx.x);
+    kickmax_reduce(const RepDev* reps, const double* part, unsigned long long* kickdev) {
+    kickmax_fold(reps[blockIdx.x], part, kickdev + blockIdx.x);
 }
 
-hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part, int by_tiles,
+hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part,
                                  unsigned long long* kickdev, hipStream_t st) {
     if (nrep <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kickmax_reduce, dim3(nrep), dim3(256), 0, st, reps, part, by_tiles, kickdev);
+    hipLaunchKernelGGL(kickmax_reduce, dim3(nrep), dim3(256), 0, st, reps, part, kickdev);
     return hipGetLastError();
 }
 
@@ -406,12 +405,12 @@ __global__ void __launch_bounds__(kObsBlock)
 
 constexpr int kObsFinal = 256;
 
-// Sums the partials of replica blockIdx.x in block order.  kick_mode >= 0:
-// also folds the pending kick maxima (per-site blocks 0, fused tiles 1) of the
-// replica into kickdev, saving a launch after a kick.
+// Sums the partials of replica blockIdx.x in block order.  kick_fold > 0:
+// also folds the pending per-block kick maxima of the replica into kickdev,
+// saving a launch after a kick in its own launch.
 __global__ void __launch_bounds__(kObsFinal)
     obs_final_kernel(const RepDev* reps, int anis, const double* partials, double* result,
-                     double* accum, int accumulate, const double* kickpart, int kick_mode,
+                     double* accum, int accumulate, const double* kickpart, int kick_fold,
                      unsigned long long* kickdev) {
     const int r = blockIdx.x;
     // the running sums are fetched first: their address needs nothing else
@@ -434,8 +433,8 @@ __global__ void __launch_bounds__(kObsFinal)
 #pragma unroll
             for (int j = 0; j < 8; ++j) v[u][j] = p[j];
         }
-        if (b0 == R.ob0 && kick_mode >= 0) {
-            kickmax_fold(R, kickpart, kick_mode, kickdev + r);
+        if (b0 == R.ob0 && kick_fold > 0) {
+            kickmax_fold(R, kickpart, kickdev + r);
             __syncthreads();
         }
 #pragma unroll
@@ -503,8 +502,9 @@ static void launch_obs_t(int anis, const RepDev* reps, const int32_t* oblk_rep, 
 
 hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
                       int nobblk, int nrep, State s, double* partials, double* result,
-                      double* accum, int accumulate, const double* kickpart, int kick_mode,
+                      double* accum, int accumulate, const double* kickpart, int kick_fold,
                       unsigned long long* kickdev, hipStream_t st) {
+    if (!kickpart || !kickdev) kick_fold = 0;  // nothing to fold from or into
     if (nobblk <= 0 || nrep <= 0) return hipSuccess;
     if (prec == 0)
         launch_obs_t<double>(anis, reps, oblk_rep, nobblk, s, partials, st);
@@ -513,7 +513,7 @@ hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* obl
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(obs_final_kernel, dim3(nrep), dim3(kObsFinal), 0, st, reps, anis, partials,
-                       result, accum, accumulate, kickpart, kick_mode, kickdev);
+                       result, accum, accumulate, kickpart, kick_fold, kickdev);
     return hipGetLastError();
 }
 

@@ -129,7 +129,7 @@ template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, bool KICK, in
 __global__ void __launch_bounds__(NT)
     rk4_fused_kernel(const RepDev* __restrict__ reps, const int4* __restrict__ tiles, State in,
                      State out, int bz_arg, uint64_t kpulse, double sigma_override,
-                     double* kickpart) {
+                     unsigned long long* kickdev) {
     // Region Rs = the tile grown by 4-s sites in x and y (R0: loaded points).
     constexpr int R0 = (BX + 8) * (BY + 8);
     constexpr int R1 = (BX + 6) * (BY + 6);
@@ -473,32 +473,36 @@ __global__ void __launch_bounds__(NT)
 #undef LLL_ITEM_WAVE_IN
 #undef LLL_ITEM_LANE_IN
     if constexpr (KICK) {
-        // block max of the renormalisation deviation, one integer atomic per block
-        // (NT need not be a power of two: fold the top NT - P2 entries first)
-        constexpr int P2 = (NT >= 512) ? 512 : (NT >= 256) ? 256 : (NT >= 128) ? 128 : 64;
+        // Tile maximum of the renormalisation deviation (a NaN compares above
+        // all): butterfly over each wave, thread 0 over the wave maxima, then one
+        // integer atomic max per tile into the replica's running maximum.  The
+        // deviation is >= 0 (or NaN with the sign bit clear), and such doubles
+        // order as their bit patterns do, NaN above +inf.
         static_assert(NT >= 64 && NT <= 1024 && NT % 64 == 0, "threads per block");
-        __shared__ double red[NT];
-        red[tid] = kmax;
-        __syncthreads();
-        if (P2 < NT && tid < NT - P2) {
-            const double a = red[tid], b = red[tid + P2];
-            red[tid] = (b > a || b != b) ? b : a;
+        double v = kmax;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double c = __shfl_xor(v, o, 64);
+            v = (c > v || c != c) ? c : v;
         }
+        __shared__ double wred[NT / 64];
+        if ((tid & 63) == 0) wred[tid >> 6] = v;
         __syncthreads();
-        for (int o = P2 / 2; o > 0; o >>= 1) {
-            if (tid < o) {
-                const double a = red[tid], b = red[tid + o];
-                red[tid] = (b > a || b != b) ? b : a;
+        if (tid == 0) {
+            double m = wred[0];
+#pragma unroll
+            for (int w = 1; w < NT / 64; ++w) {
+                const double c = wred[w];
+                m = (c > m || c != c) ? c : m;
             }
-            __syncthreads();
+            atomicMax(kickdev + tl.x, (unsigned long long)__double_as_longlong(m));
         }
-        if (tid == 0) kickpart[R.tile0 + tl.y + R.tx * (tl.z + R.ty * tl.w)] = red[0];
     }
 }
 
 template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, int SCHEME>
 inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, State in, State out,
-                           int bz, int kick, uint64_t k, double so, double* kd,
+                           int bz, int kick, uint64_t k, double so, unsigned long long* kd,
                            const LaunchEvents* ev, hipStream_t st) {
     if (kick)
         hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, true, SCHEME>), dim3(ntiles),
@@ -516,7 +520,7 @@ inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, St
 template <typename T, int BX, int BY, int NT, bool PREC, int SCHEME>
 inline hipError_t launch_a(int anis, const RepDev* reps, const int4* tiles, int ntiles, State in,
                            State out, int bz, int kick, uint64_t k, double so,
-                           double* kd, const LaunchEvents* ev, hipStream_t st) {
+                           unsigned long long* kd, const LaunchEvents* ev, hipStream_t st) {
     switch (anis) {
         case ANIS_NONE: return launch_v<T, BX, BY, NT, PREC, ANIS_NONE, SCHEME>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
         case ANIS_Z: return launch_v<T, BX, BY, NT, PREC, ANIS_Z, SCHEME>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
@@ -528,7 +532,7 @@ inline hipError_t launch_a(int anis, const RepDev* reps, const int4* tiles, int 
 template <typename T, int BX, int BY, int NT, int SCHEME>
 inline hipError_t launch_p(int precession, int anis, const RepDev* reps, const int4* tiles,
                            int ntiles, State in, State out, int bz, int kick, uint64_t k,
-                           double so, double* kd, const LaunchEvents* ev, hipStream_t st) {
+                           double so, unsigned long long* kd, const LaunchEvents* ev, hipStream_t st) {
     if (precession)
         return launch_a<T, BX, BY, NT, true, SCHEME>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
     return launch_a<T, BX, BY, NT, false, SCHEME>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
@@ -538,7 +542,7 @@ inline hipError_t launch_p(int precession, int anis, const RepDev* reps, const i
 // lists give the variant table (kern_fused_f32.hip).
 #define LLL_FUSED_ARGS                                                                    \
     int precession, int anis, int variant, int bz, const RepDev *reps, const int4 *tiles, \
-        int ntiles, State in, State out, int kick, uint64_t k, double so, double *kd,     \
+        int ntiles, State in, State out, int kick, uint64_t k, double so, unsigned long long *kd,     \
         const LaunchEvents *ev, hipStream_t st
 #define LLL_FUSED_PASS precession, anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st
 

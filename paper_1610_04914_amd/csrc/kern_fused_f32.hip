@@ -40,7 +40,7 @@ hipError_t fused_f32_rk4(LLL_FUSED_ARGS) { return fused_f32<0>(precession, anis,
 hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz, int scheme,
                              const RepDev* reps, const int4* tiles, int ntiles, State in,
                              State out, int kick, uint64_t k, double so,
-                             double* kd, const LaunchEvents* ev, hipStream_t st) {
+                             unsigned long long* kd, const LaunchEvents* ev, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     if (scheme == 0)
         return prec == 0 ? fused_f64_rk4(precession, anis, variant, bz, reps, tiles, ntiles, in, out, kick, k, so, kd, ev, st)

@@ -71,13 +71,13 @@ struct Engine {
     double* d_result = nullptr;   // [nrep][8]
     double* d_accum = nullptr;    // [nrep][8]
     unsigned long long* d_kickdev = nullptr;  // [nrep]
-    double* d_kickpart = nullptr;  // per-block / per-tile maxima of the kick deviation
-    int kickpart_cap = 0;
+    double* d_kickpart = nullptr;  // [nblk] per-block maxima of the kick deviation
     bool kick_epilogue = true;     // kick as the fused step's epilogue (else its own launch)
-    // kick maxima written to d_kickpart but not yet folded into d_kickdev:
-    // -1 none, 0 per-site blocks, 1 fused-step tiles (folded by the next
-    // measurement, or by a reduction launch before the next kick / run end)
-    int kick_pending = -1;
+    // per-block kick maxima written to d_kickpart by a kick in its own launch
+    // and not yet folded into d_kickdev (folded by the next measurement, or by
+    // a reduction launch before the next such kick / at the end of a run); the
+    // fused step's kick epilogue folds its tile maxima itself
+    bool kick_pending = false;
     // With n = 1 (kick first in every interval) the next interval's kick can be
     // applied as the epilogue of this interval's step; carried_k then names
     // the pulse already applied, which the next interval skips.
@@ -175,7 +175,6 @@ lll_status build_tables(Engine& E) {
     HIP_TRY(hipMemset(E.d_kickdev, 0, sizeof(unsigned long long) * E.nrep));
     HIP_TRY(hipMalloc(&E.dreps, sizeof(RepDev) * E.nrep));
     HIP_TRY(hipMalloc(&E.d_kickpart, sizeof(double) * E.nblk));
-    E.kickpart_cap = E.nblk;
     return LLL_OK;
 }
 
@@ -381,13 +380,6 @@ lll_status ensure_tiles(Engine& E) {
     }
     HIP_TRY(hipStreamSynchronize(E.st));
     HIP_TRY(hipMemcpy(E.d_tiles, ord.data(), sizeof(int4) * n, hipMemcpyHostToDevice));
-    if (n > E.kickpart_cap) {
-        if (E.d_kickpart) (void)hipFree(E.d_kickpart);
-        E.d_kickpart = nullptr;
-        E.kickpart_cap = 0;
-        HIP_TRY(hipMalloc(&E.d_kickpart, sizeof(double) * n));
-        E.kickpart_cap = n;
-    }
     E.ntiles = n;
     E.tiles_variant = E.variant;
     E.tiles_bz = E.bz;
@@ -420,10 +412,9 @@ const LaunchEvents* kt_take(Engine& E) {
 }
 
 lll_status kick_flush(Engine& E) {
-    if (E.kick_pending >= 0) {
-        HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, E.kick_pending, E.d_kickdev,
-                                      E.st));
-        E.kick_pending = -1;
+    if (E.kick_pending) {
+        HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, E.d_kickdev, E.st));
+        E.kick_pending = false;
     }
     return LLL_OK;
 }
@@ -443,7 +434,7 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
             if ((s = kick_flush(E)) != LLL_OK) return s;
             HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k,
                                 sigma_override, E.d_kickpart, E.st));
-            E.kick_pending = 0;
+            E.kick_pending = true;
         }
         return LLL_OK;
     }
@@ -457,7 +448,7 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
             if ((s = kick_flush(E)) != LLL_OK) return s;
             HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k,
                                 sigma_override, E.d_kickpart, E.st));
-            E.kick_pending = 0;
+            E.kick_pending = true;
         }
         return LLL_OK;
     }
@@ -473,13 +464,11 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
             adv = n - q >= 2 ? 2 : 1;
         }
         const bool kk = kick_last && q + adv == n && E.kick_epilogue;
-        if (kk && (s = kick_flush(E)) != LLL_OK) return s;
         State in = cur_state(E);
         State out = E.cur ? E.s : E.alt;
         HIP_TRY(launch_step_fused(E.prec, E.precession, E.anis, E.variant, eff_bz(E), scheme,
                                   E.dreps, E.d_tiles, E.ntiles, in, out, kk ? 1 : 0, k,
-                                  sigma_override, E.d_kickpart, kk ? nullptr : kt_take(E), E.st));
-        if (kk) E.kick_pending = 1;
+                                  sigma_override, E.d_kickdev, kk ? nullptr : kt_take(E), E.st));
         E.cur ^= 1;
         q += adv;
     }
@@ -487,7 +476,7 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
         if ((s = kick_flush(E)) != LLL_OK) return s;
         HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k, sigma_override,
                             E.d_kickpart, E.st));
-        E.kick_pending = 0;
+        E.kick_pending = true;
     }
     return LLL_OK;
 }
@@ -497,7 +486,7 @@ lll_status do_kick(Engine& E, uint64_t k, double sigma_override) {
     if (s != LLL_OK) return s;
     HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k, sigma_override,
                         E.d_kickpart, E.st));
-    E.kick_pending = 0;
+    E.kick_pending = true;
     return LLL_OK;
 }
 
@@ -545,9 +534,9 @@ lll_status do_interval(Engine& E, int64_t n, uint64_t k, double sigma_override) 
 // Observables into result; folds a pending kick maximum in the same launches.
 lll_status do_obs(Engine& E, double* result, int accumulate) {
     HIP_TRY(launch_obs(E.prec, E.anis, E.dreps, E.d_oblk_rep, E.nobblk, E.nrep, cur_state(E),
-                       E.d_partials, result, E.d_accum, accumulate, E.d_kickpart, E.kick_pending,
-                       E.d_kickdev, E.st));
-    E.kick_pending = -1;
+                       E.d_partials, result, E.d_accum, accumulate, E.d_kickpart,
+                       E.kick_pending ? 1 : 0, E.d_kickdev, E.st));
+    E.kick_pending = false;
     return LLL_OK;
 }
 
@@ -1049,7 +1038,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
         bk = tk[1] <= tk[0];
     }
     E.kick_epilogue = bk;
-    E.kick_pending = -1;  // maxima of the timing runs are dropped (kickdev is restored below)
+    E.kick_pending = false;  // maxima of the timing runs are dropped (kickdev is restored below)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     hipError_t ce = launch_copy(E.prec, E.s, save, E.nsites, E.st);
@@ -1172,12 +1161,12 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
         } else {
             HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, cur, opk[j], -1.0, E.d_kickpart,
                                 E.st));
-            HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, 0, E.d_kickdev, E.st));
+            HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, E.d_kickdev, E.st));
         }
     }
     // loss and its cotangent
     HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, cur, E.d_partials, E.d_result,
-                       E.d_accum, 0, nullptr, -1, nullptr, E.st));
+                       E.d_accum, 0, nullptr, 0, nullptr, E.st));
     HIP_TRY(launch_adj_loss(pr, an, E.dreps, E.d_blk_rep, E.nblk, cur, sbar, wE, wm, gD, part,
                             E.st));
     // backward
@@ -1195,7 +1184,7 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
                 HIP_TRY(launch_copy(pr, nx, slot(sl, 0), E.nsites, E.st));
                 HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, opk[j], -1.0, E.d_kickpart,
                                     E.st));
-                HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, 0, E.d_kickdev, E.st));
+                HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, E.d_kickdev, E.st));
             }
         }
         for (int64_t j = j1 - 1; j >= j0; --j) {

@@ -48,19 +48,18 @@ hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int
 // into the running maxima by launch_kickmax_reduce (or by launch_obs).
 hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
                        uint64_t k, double sigma_override, double* kickpart, hipStream_t st);
-// Folds per-block maxima into kickdev: parts of replica r are its per-site
-// blocks (by_tiles = 0) or its fused-step tiles in tile order (by_tiles = 1).
-hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part, int by_tiles,
+// Folds the per-block maxima of each replica (its per-site blocks) into kickdev.
+hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part,
                                  unsigned long long* kickdev, hipStream_t st);
 // Work items of the observables pass for an Lx x Ly x Lz lattice (runs of
 // columns over z-slabs); a replica needs at most this many blocks.
 int64_t obs_item_count(int Lx, int Ly, int Lz);
 // Observables of every replica into result[r][8] (and accum when accumulate);
-// partials: [nobblk][8] scratch.  kick_mode >= 0 also folds pending kick maxima
-// (as launch_kickmax_reduce with by_tiles = kick_mode) into kickdev.
+// partials: [nobblk][8] scratch.  kick_fold > 0 also folds the pending
+// per-block kick maxima (as launch_kickmax_reduce) into kickdev.
 hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
                       int nobblk, int nrep, State s, double* partials, double* result,
-                      double* accum, int accumulate, const double* kickpart, int kick_mode,
+                      double* accum, int accumulate, const double* kickpart, int kick_fold,
                       unsigned long long* kickdev, hipStream_t st);
 // Unfused RK4 step: four stage launches; scratch yA, yB, acc of the same shape.
 hipError_t launch_step_unfused(int prec, int precession, int anis, const RepDev* reps,
@@ -101,15 +100,16 @@ bool fused_variant_info(int prec, int variant, FusedInfo* out);
 struct LaunchEvents {
     hipEvent_t start, stop;
 };
-// kick != 0: apply kick number k to the step's output (epilogue), writing each
-// tile's maximum of | |s'| - 1 | to kickpart[tile0 + tile]; sigma_override >= 0
+// kick != 0: apply kick number k to the step's output (epilogue), folding each
+// tile's maximum of | |s'| - 1 | into kickdev[replica] (integer atomic max on
+// the non-negative double's bits); sigma_override >= 0
 // replaces every replica's kick scale.  ev (optional, steps without kick only)
 // times the launch.
 // scheme: 0 one RK4 step, 1 two RK2-midpoint steps, 2 one RK2-midpoint step.
 hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz, int scheme,
                              const RepDev* reps, const int4* tiles, int ntiles, State in,
                              State out, int kick, uint64_t k, double sigma_override,
-                             double* kickpart, const LaunchEvents* ev, hipStream_t st);
+                             unsigned long long* kickdev, const LaunchEvents* ev, hipStream_t st);
 
 // RK4 step keeping the stage inputs y2, y3, y4 (per-stage launches).
 hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* reps,

@@ -405,20 +405,36 @@ __global__ void __launch_bounds__(kObsBlock)
 
 constexpr int kObsFinal = 256;
 
-// Sums the partials of replica blockIdx.x in block order.  kick_fold > 0:
-// also folds the pending per-block kick maxima of the replica into kickdev,
-// saving a launch after a kick in its own launch.
-__global__ void __launch_bounds__(kObsFinal)
-    obs_final_kernel(const RepDev* reps, int anis, const double* partials, double* result,
-                     double* accum, int accumulate, const double* kickpart, int kick_fold,
-                     unsigned long long* kickdev) {
-    const int r = blockIdx.x;
+// Running sums of one measurement o[8] (result layout) added to a[8]: count,
+// E, E^2, |m|, m^2, m.  One definition for every caller, so the sums do not
+// depend on which launch adds them.
+__device__ __forceinline__ void accum_add(double a[8], const double o[8]) {
+    const double Et = o[0], mx = o[4], my = o[5], mz = o[6];
+    const double m2 = mx * mx + my * my + mz * mz;
+    a[0] = a[0] + 1.0;
+    a[1] = a[1] + Et;
+    a[2] = a[2] + Et * Et;
+    a[3] = a[3] + sqrt(m2);
+    a[4] = a[4] + m2;
+    a[5] = a[5] + mx;
+    a[6] = a[6] + my;
+    a[7] = a[7] + mz;
+}
+
+// One block: sums the partials of replica R (global blocks ob0 .. ob0+nob-1 of
+// `partials`) in block order into o[8].  accum (optional): the replica's
+// running sums, updated.  kick_fold > 0: also folds the replica's pending
+// per-block kick maxima into *kickdev, saving a launch after a kick in its
+// own launch.
+__device__ __forceinline__ void obs_final_block(const RepDev& R, int anis, const double* partials,
+                                                double* o, double* accum,
+                                                const double* kickpart, int kick_fold,
+                                                unsigned long long* kickdev) {
     // the running sums are fetched first: their address needs nothing else
     double a_old[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (accumulate && threadIdx.x == 0)
+    if (accum && threadIdx.x == 0)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) a_old[j] = accum[(int64_t)r * 8 + j];
-    const RepDev& R = reps[r];
+        for (int j = 0; j < 8; ++j) a_old[j] = accum[j];
     // at most kFinalU partials per thread and pass, loaded together (and
     // before the kick fold, whose barriers would otherwise serialise them)
     constexpr int kFinalU = 8;
@@ -434,7 +450,7 @@ __global__ void __launch_bounds__(kObsFinal)
             for (int j = 0; j < 8; ++j) v[u][j] = p[j];
         }
         if (b0 == R.ob0 && kick_fold > 0) {
-            kickmax_fold(R, kickpart, kickdev + r);
+            kickmax_fold(R, kickpart, kickdev);
             __syncthreads();
         }
 #pragma unroll
@@ -448,33 +464,70 @@ __global__ void __launch_bounds__(kObsFinal)
     __syncthreads();
     if (threadIdx.x == 0) {
         const double N = (double)R.Lx * R.Ly * R.Lz;
-        const double Eex = -R.J * tot[0];
-        const double Ez = -(R.H[0] * tot[3] + R.H[1] * tot[4] + R.H[2] * tot[5]);
-        const double Ea = -(anis == ANIS_Z || anis == ANIS_AXIS ? R.D * tot[2] : tot[2]);
-        const double Et = Eex + Ez + Ea;
-        const double mx = tot[3] / N, my = tot[4] / N, mz = tot[5] / N;
-        double* o = result + (int64_t)r * 8;
-        o[0] = Et;
-        o[1] = Eex;
-        o[2] = Ez;
-        o[3] = Ea;
-        o[4] = mx;
-        o[5] = my;
-        o[6] = mz;
-        o[7] = nan_max(sqrt(tot[6]) - 1.0, 1.0 - sqrt(tot[7]));
-        if (accumulate) {
-            double* a = accum + (int64_t)r * 8;
-            const double m2 = mx * mx + my * my + mz * mz;
-            a[0] = a_old[0] + 1.0;
-            a[1] = a_old[1] + Et;
-            a[2] = a_old[2] + Et * Et;
-            a[3] = a_old[3] + sqrt(m2);
-            a[4] = a_old[4] + m2;
-            a[5] = a_old[5] + mx;
-            a[6] = a_old[6] + my;
-            a[7] = a_old[7] + mz;
+        double r8[8];
+        r8[1] = -R.J * tot[0];
+        r8[2] = -(R.H[0] * tot[3] + R.H[1] * tot[4] + R.H[2] * tot[5]);
+        r8[3] = -(anis == ANIS_Z || anis == ANIS_AXIS ? R.D * tot[2] : tot[2]);
+        r8[0] = r8[1] + r8[2] + r8[3];
+        r8[4] = tot[3] / N;
+        r8[5] = tot[4] / N;
+        r8[6] = tot[5] / N;
+        r8[7] = nan_max(sqrt(tot[6]) - 1.0, 1.0 - sqrt(tot[7]));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = r8[j];
+        if (accum) {
+            accum_add(a_old, r8);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) accum[j] = a_old[j];
         }
     }
+}
+
+// Block r: observables of replica r into result[r] (and its running sums when
+// accumulate).
+__global__ void __launch_bounds__(kObsFinal)
+    obs_final_kernel(const RepDev* reps, int anis, const double* partials, double* result,
+                     double* accum, int accumulate, const double* kickpart, int kick_fold,
+                     unsigned long long* kickdev) {
+    const int r = blockIdx.x;
+    obs_final_block(reps[r], anis, partials, result + (int64_t)r * 8,
+                    accumulate ? accum + (int64_t)r * 8 : nullptr, kickpart, kick_fold,
+                    kickdev + r);
+}
+
+// Block (r, j): observables of replica r in staged measurement j, whose
+// partials start at stage + j * nobblk * 8, into out + j * ostride + r * 8.
+__global__ void __launch_bounds__(kObsFinal)
+    obs_final_staged_kernel(const RepDev* reps, int anis, const double* stage, int nobblk,
+                            double* out, int64_t ostride) {
+    const int r = blockIdx.x, j = blockIdx.y;
+    obs_final_block(reps[r], anis, stage + (int64_t)j * nobblk * 8,
+                    out + (int64_t)j * ostride + (int64_t)r * 8, nullptr, nullptr, 0, nullptr);
+}
+
+// Thread r: the n staged measurements of replica r added to its running sums
+// in measurement order; the last one is also copied to result[r].
+__global__ void __launch_bounds__(64)
+    accum_staged_kernel(int nrep, const double* out, int64_t ostride, int n, double* accum,
+                        double* result) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    double a[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = accum[(int64_t)r * 8 + j];
+#pragma unroll 4
+    for (int m = 0; m < n; ++m) {
+        double o[8];
+        const double* src = out + (int64_t)m * ostride + (int64_t)r * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = src[j];
+        accum_add(a, o);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) accum[(int64_t)r * 8 + j] = a[j];
+    const double* last = out + (int64_t)(n - 1) * ostride + (int64_t)r * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) result[(int64_t)r * 8 + j] = last[j];
 }
 
 template <typename T>
@@ -514,6 +567,29 @@ hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* obl
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(obs_final_kernel, dim3(nrep), dim3(kObsFinal), 0, st, reps, anis, partials,
                        result, accum, accumulate, kickpart, kick_fold, kickdev);
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_partials(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
+                               int nobblk, State s, double* partials, hipStream_t st) {
+    if (nobblk <= 0) return hipSuccess;
+    if (prec == 0)
+        launch_obs_t<double>(anis, reps, oblk_rep, nobblk, s, partials, st);
+    else
+        launch_obs_t<float>(anis, reps, oblk_rep, nobblk, s, partials, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_staged(int anis, const RepDev* reps, int nrep, int nobblk, int n,
+                             const double* stage, double* out, int64_t ostride, double* accum,
+                             double* result, hipStream_t st) {
+    if (n <= 0 || nrep <= 0 || nobblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(obs_final_staged_kernel, dim3(nrep, n), dim3(kObsFinal), 0, st, reps, anis,
+                       stage, nobblk, out, ostride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(accum_staged_kernel, dim3((nrep + 63) / 64), dim3(64), 0, st, nrep, out,
+                       ostride, n, accum, result);
     return hipGetLastError();
 }
 

@@ -85,6 +85,15 @@ struct Engine {
     uint64_t carried_k = 0;
     double* d_trace = nullptr;
     size_t trace_cap = 0;         // doubles
+    // Measurements of a run are staged: each leaves its per-block partials in
+    // d_obs_stage, and obs_fold reduces all staged ones in one launch (plus
+    // the running sums), instead of one reduction launch per measurement.
+    double* d_obs_stage = nullptr;  // [obs_cap][nobblk][8]
+    double* d_obs_vals = nullptr;   // [obs_cap][nrep][8], values when no trace is kept
+    int obs_cap = 0;
+    int obs_n = 0;                  // staged and not yet reduced
+    double* obs_out = nullptr;      // where the next reduced measurement goes (trace) or null
+    int64_t obs_stride = 0;         // doubles between consecutive measurements in obs_out
     int variant = 0, bz = 0;      // step configuration (0 = unfused)
     int integrator = 0;           // lll_integrator; other than RK4 runs the per-stage tableau path
     State Kt[6]{};                // stage increments of the tableau path
@@ -123,10 +132,12 @@ struct Engine {
             k = State{};
         }
         fr(dreps); fr(d_blk_rep); fr(d_oblk_rep); fr(d_tiles); fr(d_partials); fr(d_result);
-        fr(d_accum); fr(d_kickdev); fr(d_trace); fr(d_kickpart);
+        fr(d_accum); fr(d_kickdev); fr(d_trace); fr(d_kickpart); fr(d_obs_stage); fr(d_obs_vals);
         s = alt = yA = yB = acc = State{};
         dreps = nullptr; d_blk_rep = d_oblk_rep = nullptr; d_tiles = nullptr;
         d_partials = d_result = d_accum = d_trace = d_kickpart = nullptr; d_kickdev = nullptr;
+        d_obs_stage = d_obs_vals = nullptr;
+        obs_cap = obs_n = 0;
     }
 };
 
@@ -550,6 +561,56 @@ lll_status ensure_trace(Engine& E, size_t doubles) {
     return LLL_OK;
 }
 
+// Staging buffers for the measurements of a run: up to 1024 measurements, and
+// at most 32 MiB for the partials and for the values each.  Allocated once
+// (a captured batch schedule keeps their addresses).
+lll_status ensure_obs_stage(Engine& E) {
+    if (E.d_obs_stage) return LLL_OK;
+    const int64_t lim = (int64_t)32 << 20;
+    const int64_t per_part = std::max<int64_t>(1, (int64_t)E.nobblk) * 8 * (int64_t)sizeof(double);
+    const int64_t per_val = std::max<int64_t>(1, (int64_t)E.nrep) * 8 * (int64_t)sizeof(double);
+    const int64_t cap = std::max<int64_t>(
+        1, std::min<int64_t>(1024, std::min(lim / per_part, lim / per_val)));
+    HIP_TRY(hipMalloc(&E.d_obs_stage, per_part * cap));
+    HIP_TRY(hipMalloc(&E.d_obs_vals, per_val * cap));
+    E.obs_cap = (int)cap;
+    E.obs_n = 0;
+    return LLL_OK;
+}
+
+// Starts staging: reduced measurements go to out, out + stride, ... (doubles;
+// measurement of replica r at + 8 r), or, with out null, only the last one to
+// d_result.
+void obs_begin(Engine& E, double* out, int64_t stride) {
+    E.obs_n = 0;
+    E.obs_out = out;
+    E.obs_stride = stride;
+}
+
+// Reduces the staged measurements, adds them to the running sums in order and
+// leaves the last one in d_result.
+lll_status obs_fold(Engine& E) {
+    if (E.obs_n == 0) return LLL_OK;
+    double* out = E.obs_out ? E.obs_out : E.d_obs_vals;
+    const int64_t stride = E.obs_out ? E.obs_stride : (int64_t)8 * E.nrep;
+    HIP_TRY(launch_obs_staged(E.anis, E.dreps, E.nrep, E.nobblk, E.obs_n, E.d_obs_stage, out,
+                              stride, E.d_accum, E.d_result, E.st));
+    if (E.obs_out) E.obs_out += (int64_t)E.obs_n * E.obs_stride;
+    E.obs_n = 0;
+    return LLL_OK;
+}
+
+// One measurement of the current state, staged (a pending kick maximum is
+// folded first: its per-block maxima would be overwritten by the next kick).
+lll_status obs_stage(Engine& E) {
+    lll_status s;
+    if ((s = kick_flush(E)) != LLL_OK) return s;
+    HIP_TRY(launch_obs_partials(E.prec, E.anis, E.dreps, E.d_oblk_rep, E.nobblk, cur_state(E),
+                                E.d_obs_stage + (size_t)E.obs_n * E.nobblk * 8, E.st));
+    if (++E.obs_n == E.obs_cap) return obs_fold(E);
+    return LLL_OK;
+}
+
 void obs_from(const double* r, lll_obs* o) {
     o->E_total = r[0];
     o->E_exch = r[1];
@@ -781,8 +842,9 @@ extern "C" lll_status lll_run(lll_lattice* L, const lll_params* p, uint64_t firs
     const int64_t nmeas = obs_every > 0 ? n_pulses / obs_every : 0;
     const bool want_trace = trace && nmeas > 0;
     if (want_trace && (s = ensure_trace(E, (size_t)nmeas * 8)) != LLL_OK) return s;
+    if (nmeas > 0 && (s = ensure_obs_stage(E)) != LLL_OK) return s;
     if ((s = settle(E)) != LLL_OK) return s;
-    int64_t m = 0;
+    obs_begin(E, want_trace ? E.d_trace : nullptr, 8);
     E.carried = false;
     for (int64_t q = 0; q < n_pulses; ++q) {
         const uint64_t k = first_pulse + (uint64_t)q;
@@ -792,12 +854,9 @@ extern "C" lll_status lll_run(lll_lattice* L, const lll_params* p, uint64_t firs
         const double so_next =
             look && T_per_pulse ? sqrt(2.0 * p->lambda * T_per_pulse[q + 1] * L->Dt) : -1.0;
         if ((s = do_interval(E, n, k, so, look, k + 1, so_next)) != LLL_OK) return s;
-        if (measure) {
-            double* dst = want_trace ? E.d_trace + 8 * m : E.d_result;
-            if ((s = do_obs(E, dst, 1)) != LLL_OK) return s;
-            ++m;
-        }
+        if (measure && (s = obs_stage(E)) != LLL_OK) return s;
     }
+    if ((s = obs_fold(E)) != LLL_OK) return s;
     if ((s = kick_flush(E)) != LLL_OK) return s;
     if ((s = settle(E)) != LLL_OK) return s;
     if (want_trace) {
@@ -1302,8 +1361,9 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
     const int64_t nmeas = obs_every > 0 ? n_pulses / obs_every : 0;
     lll_status s;
     if (nmeas > 0 && (s = ensure_trace(E, (size_t)nmeas * 8 * E.nrep)) != LLL_OK) return s;
+    if (nmeas > 0 && (s = ensure_obs_stage(E)) != LLL_OK) return s;
     if ((s = settle(E)) != LLL_OK) return s;
-    // Tables must exist before capture (their uploads synchronise).
+    // Tables and buffers must exist before capture (their uploads synchronise).
     if (E.variant == 0 || E.anis == ANIS_SITE) {
         if ((s = ensure_unfused_scratch(E)) != LLL_OK) return s;
     } else {
@@ -1324,18 +1384,16 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
         hipStream_t saved = E.st;
         E.st = cs;
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        int64_t m = 0;
         lll_status cap = LLL_OK;
         E.carried = false;
+        obs_begin(E, E.d_trace, (int64_t)8 * E.nrep);
         for (int64_t q = 0; q < n_pulses && cap == LLL_OK; ++q) {
             const uint64_t k = first_pulse + (uint64_t)q;
             const bool measure = obs_every > 0 && (q + 1) % obs_every == 0;
             cap = do_interval(E, B->n, k, -1.0, q + 1 < n_pulses && !measure, k + 1, -1.0);
-            if (cap == LLL_OK && measure) {
-                cap = do_obs(E, E.d_trace + (size_t)8 * E.nrep * m, 1);
-                ++m;
-            }
+            if (cap == LLL_OK && measure) cap = obs_stage(E);
         }
+        if (cap == LLL_OK) cap = obs_fold(E);
         if (cap == LLL_OK) cap = kick_flush(E);  // every replay starts and ends with nothing pending
         if (cap == LLL_OK) cap = settle(E);
         hipGraph_t g = nullptr;

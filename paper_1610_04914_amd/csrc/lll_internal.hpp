@@ -61,6 +61,18 @@ hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* obl
                       int nobblk, int nrep, State s, double* partials, double* result,
                       double* accum, int accumulate, const double* kickpart, int kick_fold,
                       unsigned long long* kickdev, hipStream_t st);
+// Staged observables: launch_obs_partials writes the per-block partials of one
+// measurement ([nobblk][8], the first pass of launch_obs); launch_obs_staged
+// then reduces n staged measurements at once (measurement j's partials at
+// stage + j * nobblk * 8) into out + j * ostride + r * 8, adds them to the
+// running sums accum[r] in measurement order and copies the last one to
+// result[r].  The values and sums equal those of n launch_obs calls with
+// accumulate.
+hipError_t launch_obs_partials(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
+                               int nobblk, State s, double* partials, hipStream_t st);
+hipError_t launch_obs_staged(int anis, const RepDev* reps, int nrep, int nobblk, int n,
+                             const double* stage, double* out, int64_t ostride, double* accum,
+                             double* result, hipStream_t st);
 // Unfused RK4 step: four stage launches; scratch yA, yB, acc of the same shape.
 hipError_t launch_step_unfused(int prec, int precession, int anis, const RepDev* reps,
                                const int32_t* blk_rep, int nblk, State s, State yA, State yB,

@@ -302,6 +302,35 @@ def test_schedule_identity_one_step_intervals(P, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_staged_measurements_match_one_by_one(P, prec):
+    """The measurements of a run are reduced in groups (at most 1024 per
+    launch, here more than one group); the trace and the running sums equal,
+    bit for bit, those of one-interval runs measured one at a time.  Through
+    the C ABI without a trace buffer, the running sums are the same too."""
+    import ctypes
+    shape = (8, 8, 8)
+    _, gp = both_params("zaxis", dt=0.1, Dt=0.1, seed=3)
+    K = 1100
+    a = P.Lattice(shape, precision=prec, seed=1)
+    b = P.Lattice(shape, precision=prec, seed=1)
+    c = P.Lattice(shape, precision=prec, seed=1)
+    ta = a.run(gp, first_pulse=0, n_pulses=K, obs_every=1)
+    tb = [b.run(gp, first_pulse=q, n_pulses=1, obs_every=1)[0] for q in range(K)]
+    pc = gp.c()
+    st = P.lib().lll_run(c.h, ctypes.byref(pc), ctypes.c_uint64(0), K, None, 1, None)
+    assert st in (P.LLL_OK, P.LLL_WARN_APPLICABILITY), st
+    torch.cuda.synchronize()
+    assert len(ta) == K
+    assert ta == tb
+    acc = a.accumulators()
+    assert acc == b.accumulators() == c.accumulators()
+    assert acc[0] == K
+    assert torch.equal(a.state, b.state) and torch.equal(a.state, c.state)
+    for L in (a, b, c):
+        L.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_one_step_intervals_bitexact(P, prec):
     """Batch with n = 1: one replay of K intervals equals K replays of one
     interval, bit for bit, with and without measurements in between."""

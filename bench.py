@@ -510,6 +510,14 @@ def extra_temperatures(n_pulses: int = 1000, tail: int = 500):
     return out
 
 
+def _progress(name, fn):
+    """Runs one extra workload and reports its wall time on stderr."""
+    t0 = time.perf_counter()
+    r = fn()
+    print(f"extra {name}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return r
+
+
 EXTRAS = {"temperatures": extra_temperatures, "headline_256": extra_headline_256,
           "config_16": extra_config_16, "batched": extra_batched, "adjoint": extra_adjoint,
           "overdamped_256": extra_overdamped, "integrators": extra_integrators,
@@ -633,7 +641,7 @@ def main():
     }
     if args.extras:
         out["extras"] = {"headline_variants": extra_headline_variants(lat, p),
-                         **{name: fn() for name, fn in EXTRAS.items()}}
+                         **{name: _progress(name, fn) for name, fn in EXTRAS.items()}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out))

@@ -144,10 +144,10 @@ __device__ __forceinline__ void kickmax_fold(const RepDev& R, const double* part
     }
 }
 
-// Block r: kick maximum of replica r folded into kickdev[r].
+// Block r: kick maximum of replica r folded into its slot 0.
 __global__ void __launch_bounds__(256)
     kickmax_reduce(const RepDev* reps, const double* part, unsigned long long* kickdev) {
-    kickmax_fold(reps[blockIdx.x], part, kickdev + blockIdx.x);
+    kickmax_fold(reps[blockIdx.x], part, kickdev + (int64_t)blockIdx.x * kKickSlots);
 }
 
 hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part,
@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(kObsFinal)
     const int r = blockIdx.x;
     obs_final_block(reps[r], anis, partials, result + (int64_t)r * 8,
                     accumulate ? accum + (int64_t)r * 8 : nullptr, kickpart, kick_fold,
-                    kickdev + r);
+                    kickdev + (int64_t)r * kKickSlots);
 }
 
 // Block (r, j): observables of replica r in staged measurement j, whose

@@ -475,9 +475,10 @@ __global__ void __launch_bounds__(NT)
     if constexpr (KICK) {
         // Tile maximum of the renormalisation deviation (a NaN compares above
         // all): butterfly over each wave, thread 0 over the wave maxima, then one
-        // integer atomic max per tile into the replica's running maximum.  The
-        // deviation is >= 0 (or NaN with the sign bit clear), and such doubles
-        // order as their bit patterns do, NaN above +inf.
+        // integer atomic max per tile into one of the replica's running-maximum
+        // slots (spread by workgroup, so that the tiles finishing together do
+        // not queue on one address).  The deviation is >= 0 (or NaN), and such
+        // doubles order as their bit patterns do, NaN above +inf.
         static_assert(NT >= 64 && NT <= 1024 && NT % 64 == 0, "threads per block");
         double v = kmax;
 #pragma unroll
@@ -495,7 +496,8 @@ __global__ void __launch_bounds__(NT)
                 const double c = wred[w];
                 m = (c > m || c != c) ? c : m;
             }
-            atomicMax(kickdev + tl.x, (unsigned long long)__double_as_longlong(m));
+            atomicMax(kickdev + (int64_t)tl.x * kKickSlots + (blockIdx.x & (kKickSlots - 1)),
+                      (unsigned long long)__double_as_longlong(m));
         }
     }
 }

@@ -70,7 +70,7 @@ struct Engine {
     double* d_partials = nullptr;
     double* d_result = nullptr;   // [nrep][8]
     double* d_accum = nullptr;    // [nrep][8]
-    unsigned long long* d_kickdev = nullptr;  // [nrep]
+    unsigned long long* d_kickdev = nullptr;  // [nrep][kKickSlots]
     double* d_kickpart = nullptr;  // [nblk] per-block maxima of the kick deviation
     bool kick_epilogue = true;     // kick as the fused step's epilogue (else its own launch)
     // per-block kick maxima written to d_kickpart by a kick in its own launch
@@ -182,8 +182,8 @@ lll_status build_tables(Engine& E) {
     HIP_TRY(hipMalloc(&E.d_result, sizeof(double) * 8 * E.nrep));
     HIP_TRY(hipMalloc(&E.d_accum, sizeof(double) * 8 * E.nrep));
     HIP_TRY(hipMemset(E.d_accum, 0, sizeof(double) * 8 * E.nrep));
-    HIP_TRY(hipMalloc(&E.d_kickdev, sizeof(unsigned long long) * E.nrep));
-    HIP_TRY(hipMemset(E.d_kickdev, 0, sizeof(unsigned long long) * E.nrep));
+    HIP_TRY(hipMalloc(&E.d_kickdev, sizeof(unsigned long long) * kKickSlots * E.nrep));
+    HIP_TRY(hipMemset(E.d_kickdev, 0, sizeof(unsigned long long) * kKickSlots * E.nrep));
     HIP_TRY(hipMalloc(&E.dreps, sizeof(RepDev) * E.nrep));
     HIP_TRY(hipMalloc(&E.d_kickpart, sizeof(double) * E.nblk));
     return LLL_OK;
@@ -891,12 +891,15 @@ extern "C" lll_status lll_kick_norm_dev(lll_lattice* L, double* out, int32_t res
     if (!L || !out) return set_err(LLL_EINVAL, "NULL argument");
     lll_status s = kick_flush(L->E);
     if (s != LLL_OK) return s;
-    unsigned long long v = 0;
-    HIP_TRY(hipMemcpyAsync(&v, L->E.d_kickdev, sizeof v, hipMemcpyDeviceToHost, L->E.st));
+    // the running maximum is the largest slot (bit patterns of doubles >= 0)
+    unsigned long long slots[kKickSlots];
+    HIP_TRY(hipMemcpyAsync(slots, L->E.d_kickdev, sizeof slots, hipMemcpyDeviceToHost, L->E.st));
     HIP_TRY(hipStreamSynchronize(L->E.st));
+    unsigned long long v = 0;
+    for (unsigned long long x : slots) v = std::max(v, x);
     memcpy(out, &v, sizeof v);
     if (reset) {
-        HIP_TRY(hipMemsetAsync(L->E.d_kickdev, 0, sizeof v, L->E.st));
+        HIP_TRY(hipMemsetAsync(L->E.d_kickdev, 0, sizeof slots, L->E.st));
         HIP_TRY(hipStreamSynchronize(L->E.st));
     }
     return LLL_OK;
@@ -1034,8 +1037,8 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     if ((s = alloc_state(E, save)) != LLL_OK) return s;
     HIP_TRY(launch_copy(E.prec, save, E.s, E.nsites, E.st));
     if ((s = kick_flush(E)) != LLL_OK) return s;
-    std::vector<unsigned long long> kd_save(E.nrep);
-    HIP_TRY(hipMemcpyAsync(kd_save.data(), E.d_kickdev, sizeof(unsigned long long) * E.nrep,
+    std::vector<unsigned long long> kd_save((size_t)kKickSlots * E.nrep);
+    HIP_TRY(hipMemcpyAsync(kd_save.data(), E.d_kickdev, sizeof(unsigned long long) * kd_save.size(),
                            hipMemcpyDeviceToHost, E.st));
     HIP_TRY(hipStreamSynchronize(E.st));
     hipEvent_t e0, e1;
@@ -1102,7 +1105,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     (void)hipEventDestroy(e1);
     hipError_t ce = launch_copy(E.prec, E.s, save, E.nsites, E.st);
     if (ce == hipSuccess)
-        ce = hipMemcpyAsync(E.d_kickdev, kd_save.data(), sizeof(unsigned long long) * E.nrep,
+        ce = hipMemcpyAsync(E.d_kickdev, kd_save.data(), sizeof(unsigned long long) * kd_save.size(),
                             hipMemcpyHostToDevice, E.st);
     (void)hipStreamSynchronize(E.st);
     (void)hipFree(save.x);

@@ -9,6 +9,12 @@ namespace lll {
 
 enum AnisMode : int32_t { ANIS_NONE = 0, ANIS_Z = 1, ANIS_AXIS = 2, ANIS_SITE = 3 };
 
+// Running maximum of the kick deviation | |s'| - 1 | of each replica: kKickSlots
+// unsigned 64-bit slots holding bit patterns of non-negative doubles (which
+// order as their bits, NaN above +inf); the maximum is the largest slot.
+// Tiles of the fused step spread their atomic maxima over the slots.
+constexpr int kKickSlots = 64;
+
 // One replica (a single lattice is a batch of one).  Lives in device memory;
 // every kernel reads the descriptor of the replica it works on.
 struct RepDev {
@@ -48,7 +54,8 @@ hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int
 // into the running maxima by launch_kickmax_reduce (or by launch_obs).
 hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
                        uint64_t k, double sigma_override, double* kickpart, hipStream_t st);
-// Folds the per-block maxima of each replica (its per-site blocks) into kickdev.
+// Folds the per-block maxima of each replica (its per-site blocks) into slot 0
+// of its kickdev slots.
 hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part,
                                  unsigned long long* kickdev, hipStream_t st);
 // Work items of the observables pass for an Lx x Ly x Lz lattice (runs of
@@ -113,8 +120,8 @@ struct LaunchEvents {
     hipEvent_t start, stop;
 };
 // kick != 0: apply kick number k to the step's output (epilogue), folding each
-// tile's maximum of | |s'| - 1 | into kickdev[replica] (integer atomic max on
-// the non-negative double's bits); sigma_override >= 0
+// tile's maximum of | |s'| - 1 | into one of the replica's kKickSlots slots
+// of kickdev (integer atomic max); sigma_override >= 0
 // replaces every replica's kick scale.  ev (optional, steps without kick only)
 // times the launch.
 // scheme: 0 one RK4 step, 1 two RK2-midpoint steps, 2 one RK2-midpoint step.

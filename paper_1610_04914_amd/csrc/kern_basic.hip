@@ -109,58 +109,10 @@ __device__ __forceinline__ double block_max256(double v) {
     return nan_max(nan_max(wred[0], wred[1]), nan_max(wred[2], wred[3]));
 }
 
-// Block-wide max of a non-negative double into part[blockIdx.x];
-// kickmax_reduce folds the parts of every replica into its running maximum
-// (one writer per replica, no atomics).
-__device__ __forceinline__ void block_max_part(double v, double* part) {
-    static_assert(kSiteBlock == 256, "block_max256 assumes 256 threads");
-    const double m = block_max256(v);
-    if (threadIdx.x == 0) part[blockIdx.x] = m;
-}
-
-// Maximum over the parts of replica R (its per-site blocks) folded into
-// *kickdev by thread 0; the whole block of 256 threads takes part, each thread
-// with up to eight loads in flight.
-__device__ __forceinline__ void kickmax_fold(const RepDev& R, const double* part,
-                                             unsigned long long* kickdev) {
-    const int p0 = R.sb0;
-    const int np = R.nsb;
-    constexpr int U = 8;
-    double m = 0.0;
-    for (int q0 = threadIdx.x; q0 < np; q0 += 256 * U) {
-        double d[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int q = q0 + 256 * u;
-            d[u] = q < np ? part[p0 + q] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) m = nan_max(m, d[u]);
-    }
-    m = block_max256(m);
-    if (threadIdx.x == 0) {
-        const double old = __longlong_as_double((long long)*kickdev);
-        if (m > old || m != m) *kickdev = (unsigned long long)__double_as_longlong(m);
-    }
-}
-
-// Block r: kick maximum of replica r folded into its slot 0.
-__global__ void __launch_bounds__(256)
-    kickmax_reduce(const RepDev* reps, const double* part, unsigned long long* kickdev) {
-    kickmax_fold(reps[blockIdx.x], part, kickdev + (int64_t)blockIdx.x * kKickSlots);
-}
-
-hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part,
-                                 unsigned long long* kickdev, hipStream_t st) {
-    if (nrep <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kickmax_reduce, dim3(nrep), dim3(256), 0, st, reps, part, kickdev);
-    return hipGetLastError();
-}
-
 template <typename T>
 __global__ void __launch_bounds__(kSiteBlock)
     kick_kernel(const RepDev* reps, const int32_t* blk_rep, State s, uint64_t k,
-                double sigma_override, double* kickpart) {
+                double sigma_override, unsigned long long* kickdev) {
     SiteCtx c;
     const bool live = site_of_thread(reps, blk_rep, c);
     double dev = 0.0;
@@ -177,18 +129,26 @@ __global__ void __launch_bounds__(kSiteBlock)
         py[c.gi] = y;
         pz[c.gi] = z;
     }
-    block_max_part(dev, kickpart);
+    // block maximum of the deviation, then one integer atomic max into one of
+    // the replica's running-maximum slots (spread by block index)
+    static_assert(kSiteBlock == 256, "block_max256 assumes 256 threads");
+    const double m = block_max256(dev);
+    if (threadIdx.x == 0)
+        atomicMax(kickdev + (int64_t)blk_rep[blockIdx.x] * kKickSlots +
+                      (blockIdx.x & (kKickSlots - 1)),
+                  (unsigned long long)__double_as_longlong(m));
 }
 
 hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
-                       uint64_t k, double sigma_override, double* kickpart, hipStream_t st) {
+                       uint64_t k, double sigma_override, unsigned long long* kickdev,
+                       hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
     if (prec == 0)
         hipLaunchKernelGGL(kick_kernel<double>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
-                           s, k, sigma_override, kickpart);
+                           s, k, sigma_override, kickdev);
     else
         hipLaunchKernelGGL(kick_kernel<float>, dim3(nblk), dim3(kSiteBlock), 0, st, reps, blk_rep,
-                           s, k, sigma_override, kickpart);
+                           s, k, sigma_override, kickdev);
     return hipGetLastError();
 }
 
@@ -423,20 +383,15 @@ __device__ __forceinline__ void accum_add(double a[8], const double o[8]) {
 
 // One block: sums the partials of replica R (global blocks ob0 .. ob0+nob-1 of
 // `partials`) in block order into o[8].  accum (optional): the replica's
-// running sums, updated.  kick_fold > 0: also folds the replica's pending
-// per-block kick maxima into *kickdev, saving a launch after a kick in its
-// own launch.
+// running sums, updated.
 __device__ __forceinline__ void obs_final_block(const RepDev& R, int anis, const double* partials,
-                                                double* o, double* accum,
-                                                const double* kickpart, int kick_fold,
-                                                unsigned long long* kickdev) {
+                                                double* o, double* accum) {
     // the running sums are fetched first: their address needs nothing else
     double a_old[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (accum && threadIdx.x == 0)
 #pragma unroll
         for (int j = 0; j < 8; ++j) a_old[j] = accum[j];
-    // at most kFinalU partials per thread and pass, loaded together (and
-    // before the kick fold, whose barriers would otherwise serialise them)
+    // at most kFinalU partials per thread and pass, loaded together
     constexpr int kFinalU = 8;
     double q[8] = {0, 0, 0, 0, 0, 0, 0, __builtin_huge_val()};
     const int pend = R.ob0 + R.nob;
@@ -448,10 +403,6 @@ __device__ __forceinline__ void obs_final_block(const RepDev& R, int anis, const
             const double* p = partials + (int64_t)(bb < pend ? bb : R.ob0) * 8;
 #pragma unroll
             for (int j = 0; j < 8; ++j) v[u][j] = p[j];
-        }
-        if (b0 == R.ob0 && kick_fold > 0) {
-            kickmax_fold(R, kickpart, kickdev);
-            __syncthreads();
         }
 #pragma unroll
         for (int u = 0; u < kFinalU; ++u)
@@ -487,12 +438,10 @@ __device__ __forceinline__ void obs_final_block(const RepDev& R, int anis, const
 // accumulate).
 __global__ void __launch_bounds__(kObsFinal)
     obs_final_kernel(const RepDev* reps, int anis, const double* partials, double* result,
-                     double* accum, int accumulate, const double* kickpart, int kick_fold,
-                     unsigned long long* kickdev) {
+                     double* accum, int accumulate) {
     const int r = blockIdx.x;
     obs_final_block(reps[r], anis, partials, result + (int64_t)r * 8,
-                    accumulate ? accum + (int64_t)r * 8 : nullptr, kickpart, kick_fold,
-                    kickdev + (int64_t)r * kKickSlots);
+                    accumulate ? accum + (int64_t)r * 8 : nullptr);
 }
 
 // Block (r, j): observables of replica r in staged measurement j, whose
@@ -502,7 +451,7 @@ __global__ void __launch_bounds__(kObsFinal)
                             double* out, int64_t ostride) {
     const int r = blockIdx.x, j = blockIdx.y;
     obs_final_block(reps[r], anis, stage + (int64_t)j * nobblk * 8,
-                    out + (int64_t)j * ostride + (int64_t)r * 8, nullptr, nullptr, 0, nullptr);
+                    out + (int64_t)j * ostride + (int64_t)r * 8, nullptr);
 }
 
 // Thread r: the n staged measurements of replica r added to its running sums
@@ -555,9 +504,7 @@ static void launch_obs_t(int anis, const RepDev* reps, const int32_t* oblk_rep, 
 
 hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
                       int nobblk, int nrep, State s, double* partials, double* result,
-                      double* accum, int accumulate, const double* kickpart, int kick_fold,
-                      unsigned long long* kickdev, hipStream_t st) {
-    if (!kickpart || !kickdev) kick_fold = 0;  // nothing to fold from or into
+                      double* accum, int accumulate, hipStream_t st) {
     if (nobblk <= 0 || nrep <= 0) return hipSuccess;
     if (prec == 0)
         launch_obs_t<double>(anis, reps, oblk_rep, nobblk, s, partials, st);
@@ -566,7 +513,7 @@ hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* obl
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(obs_final_kernel, dim3(nrep), dim3(kObsFinal), 0, st, reps, anis, partials,
-                       result, accum, accumulate, kickpart, kick_fold, kickdev);
+                       result, accum, accumulate);
     return hipGetLastError();
 }
 

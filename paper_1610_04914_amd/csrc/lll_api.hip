@@ -71,13 +71,7 @@ struct Engine {
     double* d_result = nullptr;   // [nrep][8]
     double* d_accum = nullptr;    // [nrep][8]
     unsigned long long* d_kickdev = nullptr;  // [nrep][kKickSlots]
-    double* d_kickpart = nullptr;  // [nblk] per-block maxima of the kick deviation
     bool kick_epilogue = true;     // kick as the fused step's epilogue (else its own launch)
-    // per-block kick maxima written to d_kickpart by a kick in its own launch
-    // and not yet folded into d_kickdev (folded by the next measurement, or by
-    // a reduction launch before the next such kick / at the end of a run); the
-    // fused step's kick epilogue folds its tile maxima itself
-    bool kick_pending = false;
     // With n = 1 (kick first in every interval) the next interval's kick can be
     // applied as the epilogue of this interval's step; carried_k then names
     // the pulse already applied, which the next interval skips.
@@ -132,10 +126,10 @@ struct Engine {
             k = State{};
         }
         fr(dreps); fr(d_blk_rep); fr(d_oblk_rep); fr(d_tiles); fr(d_partials); fr(d_result);
-        fr(d_accum); fr(d_kickdev); fr(d_trace); fr(d_kickpart); fr(d_obs_stage); fr(d_obs_vals);
+        fr(d_accum); fr(d_kickdev); fr(d_trace); fr(d_obs_stage); fr(d_obs_vals);
         s = alt = yA = yB = acc = State{};
         dreps = nullptr; d_blk_rep = d_oblk_rep = nullptr; d_tiles = nullptr;
-        d_partials = d_result = d_accum = d_trace = d_kickpart = nullptr; d_kickdev = nullptr;
+        d_partials = d_result = d_accum = d_trace = nullptr; d_kickdev = nullptr;
         d_obs_stage = d_obs_vals = nullptr;
         obs_cap = obs_n = 0;
     }
@@ -185,7 +179,6 @@ lll_status build_tables(Engine& E) {
     HIP_TRY(hipMalloc(&E.d_kickdev, sizeof(unsigned long long) * kKickSlots * E.nrep));
     HIP_TRY(hipMemset(E.d_kickdev, 0, sizeof(unsigned long long) * kKickSlots * E.nrep));
     HIP_TRY(hipMalloc(&E.dreps, sizeof(RepDev) * E.nrep));
-    HIP_TRY(hipMalloc(&E.d_kickpart, sizeof(double) * E.nblk));
     return LLL_OK;
 }
 
@@ -422,14 +415,6 @@ const LaunchEvents* kt_take(Engine& E) {
     return &E.kt_ev[j];
 }
 
-lll_status kick_flush(Engine& E) {
-    if (E.kick_pending) {
-        HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, E.d_kickdev, E.st));
-        E.kick_pending = false;
-    }
-    return LLL_OK;
-}
-
 lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sigma_override) {
     if (n <= 0) return LLL_OK;
     const bool fused_ok = E.variant != 0 && E.anis != ANIS_SITE;
@@ -441,12 +426,9 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
         for (int64_t q = 0; q < n; ++q)
             HIP_TRY(launch_step_tableau(E.prec, E.precession, E.anis, E.dreps, E.d_blk_rep, E.nblk,
                                         tb, cur_state(E), E.yA, E.yB, ks, E.st));
-        if (kick_last) {
-            if ((s = kick_flush(E)) != LLL_OK) return s;
+        if (kick_last)
             HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k,
-                                sigma_override, E.d_kickpart, E.st));
-            E.kick_pending = true;
-        }
+                                sigma_override, E.d_kickdev, E.st));
         return LLL_OK;
     }
     if (!fused_ok) {
@@ -455,12 +437,9 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
         for (int64_t q = 0; q < n; ++q)
             HIP_TRY(launch_step_unfused(E.prec, E.precession, E.anis, E.dreps, E.d_blk_rep, E.nblk,
                                         cur_state(E), E.yA, E.yB, E.acc, E.st));
-        if (kick_last) {
-            if ((s = kick_flush(E)) != LLL_OK) return s;
+        if (kick_last)
             HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k,
-                                sigma_override, E.d_kickpart, E.st));
-            E.kick_pending = true;
-        }
+                                sigma_override, E.d_kickdev, E.st));
         return LLL_OK;
     }
     lll_status s = alloc_state(E, E.alt);
@@ -483,21 +462,15 @@ lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sig
         E.cur ^= 1;
         q += adv;
     }
-    if (kick_last && !E.kick_epilogue) {
-        if ((s = kick_flush(E)) != LLL_OK) return s;
+    if (kick_last && !E.kick_epilogue)
         HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k, sigma_override,
-                            E.d_kickpart, E.st));
-        E.kick_pending = true;
-    }
+                            E.d_kickdev, E.st));
     return LLL_OK;
 }
 
 lll_status do_kick(Engine& E, uint64_t k, double sigma_override) {
-    lll_status s = kick_flush(E);
-    if (s != LLL_OK) return s;
     HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k, sigma_override,
-                        E.d_kickpart, E.st));
-    E.kick_pending = true;
+                        E.d_kickdev, E.st));
     return LLL_OK;
 }
 
@@ -542,12 +515,10 @@ lll_status do_interval(Engine& E, int64_t n, uint64_t k, double sigma_override) 
     return do_interval(E, n, k, sigma_override, false, 0, -1.0);
 }
 
-// Observables into result; folds a pending kick maximum in the same launches.
+// Observables into result (and the running sums when accumulate).
 lll_status do_obs(Engine& E, double* result, int accumulate) {
     HIP_TRY(launch_obs(E.prec, E.anis, E.dreps, E.d_oblk_rep, E.nobblk, E.nrep, cur_state(E),
-                       E.d_partials, result, E.d_accum, accumulate, E.d_kickpart,
-                       E.kick_pending ? 1 : 0, E.d_kickdev, E.st));
-    E.kick_pending = false;
+                       E.d_partials, result, E.d_accum, accumulate, E.st));
     return LLL_OK;
 }
 
@@ -600,11 +571,8 @@ lll_status obs_fold(Engine& E) {
     return LLL_OK;
 }
 
-// One measurement of the current state, staged (a pending kick maximum is
-// folded first: its per-block maxima would be overwritten by the next kick).
+// One measurement of the current state, staged.
 lll_status obs_stage(Engine& E) {
-    lll_status s;
-    if ((s = kick_flush(E)) != LLL_OK) return s;
     HIP_TRY(launch_obs_partials(E.prec, E.anis, E.dreps, E.d_oblk_rep, E.nobblk, cur_state(E),
                                 E.d_obs_stage + (size_t)E.obs_n * E.nobblk * 8, E.st));
     if (++E.obs_n == E.obs_cap) return obs_fold(E);
@@ -799,8 +767,7 @@ extern "C" lll_status lll_noise_pulse(lll_lattice* L, const lll_params* p, uint6
     lll_status s = lattice_params(L, p, true);
     if (s != LLL_OK) return s;
     if ((s = settle(L->E)) != LLL_OK) return s;
-    if ((s = do_kick(L->E, pulse_index, -1.0)) != LLL_OK) return s;
-    return kick_flush(L->E);
+    return do_kick(L->E, pulse_index, -1.0);
 }
 
 extern "C" lll_status lll_observables(lll_lattice* L, const lll_params* p, lll_obs* out) {
@@ -857,7 +824,6 @@ extern "C" lll_status lll_run(lll_lattice* L, const lll_params* p, uint64_t firs
         if (measure && (s = obs_stage(E)) != LLL_OK) return s;
     }
     if ((s = obs_fold(E)) != LLL_OK) return s;
-    if ((s = kick_flush(E)) != LLL_OK) return s;
     if ((s = settle(E)) != LLL_OK) return s;
     if (want_trace) {
         std::vector<double> h((size_t)nmeas * 8);
@@ -889,8 +855,6 @@ extern "C" lll_status lll_get_state(lll_lattice* L, void** sx, void** sy, void**
 
 extern "C" lll_status lll_kick_norm_dev(lll_lattice* L, double* out, int32_t reset) {
     if (!L || !out) return set_err(LLL_EINVAL, "NULL argument");
-    lll_status s = kick_flush(L->E);
-    if (s != LLL_OK) return s;
     // the running maximum is the largest slot (bit patterns of doubles >= 0)
     unsigned long long slots[kKickSlots];
     HIP_TRY(hipMemcpyAsync(slots, L->E.d_kickdev, sizeof slots, hipMemcpyDeviceToHost, L->E.st));
@@ -1036,7 +1000,6 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     State save{};
     if ((s = alloc_state(E, save)) != LLL_OK) return s;
     HIP_TRY(launch_copy(E.prec, save, E.s, E.nsites, E.st));
-    if ((s = kick_flush(E)) != LLL_OK) return s;
     std::vector<unsigned long long> kd_save((size_t)kKickSlots * E.nrep);
     HIP_TRY(hipMemcpyAsync(kd_save.data(), E.d_kickdev, sizeof(unsigned long long) * kd_save.size(),
                            hipMemcpyDeviceToHost, E.st));
@@ -1100,7 +1063,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
         bk = tk[1] <= tk[0];
     }
     E.kick_epilogue = bk;
-    E.kick_pending = false;  // maxima of the timing runs are dropped (kickdev is restored below)
+    // maxima of the timing runs are dropped: kickdev is restored below
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     hipError_t ce = launch_copy(E.prec, E.s, save, E.nsites, E.st);
@@ -1221,14 +1184,13 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
                                       slot(0, 2), slot(0, 3), accb, nxt, E.st));
             std::swap(cur, nxt);
         } else {
-            HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, cur, opk[j], -1.0, E.d_kickpart,
+            HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, cur, opk[j], -1.0, E.d_kickdev,
                                 E.st));
-            HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, E.d_kickdev, E.st));
         }
     }
     // loss and its cotangent
     HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, cur, E.d_partials, E.d_result,
-                       E.d_accum, 0, nullptr, 0, nullptr, E.st));
+                       E.d_accum, 0, E.st));
     HIP_TRY(launch_adj_loss(pr, an, E.dreps, E.d_blk_rep, E.nblk, cur, sbar, wE, wm, gD, part,
                             E.st));
     // backward
@@ -1244,9 +1206,8 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
                                           slot(sl, 1), slot(sl, 2), slot(sl, 3), accb, nx, E.st));
             } else {
                 HIP_TRY(launch_copy(pr, nx, slot(sl, 0), E.nsites, E.st));
-                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, opk[j], -1.0, E.d_kickpart,
+                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, opk[j], -1.0, E.d_kickdev,
                                     E.st));
-                HIP_TRY(launch_kickmax_reduce(E.dreps, E.nrep, E.d_kickpart, E.d_kickdev, E.st));
             }
         }
         for (int64_t j = j1 - 1; j >= j0; --j) {
@@ -1396,8 +1357,7 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
             cap = do_interval(E, B->n, k, -1.0, q + 1 < n_pulses && !measure, k + 1, -1.0);
             if (cap == LLL_OK && measure) cap = obs_stage(E);
         }
-        if (cap == LLL_OK) cap = obs_fold(E);
-        if (cap == LLL_OK) cap = kick_flush(E);  // every replay starts and ends with nothing pending
+        if (cap == LLL_OK) cap = obs_fold(E);  // every replay ends with nothing staged
         if (cap == LLL_OK) cap = settle(E);
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(cs, &g);

@@ -12,7 +12,9 @@ enum AnisMode : int32_t { ANIS_NONE = 0, ANIS_Z = 1, ANIS_AXIS = 2, ANIS_SITE = 
 // Running maximum of the kick deviation | |s'| - 1 | of each replica: kKickSlots
 // unsigned 64-bit slots holding bit patterns of non-negative doubles (which
 // order as their bits, NaN above +inf); the maximum is the largest slot.
-// Tiles of the fused step spread their atomic maxima over the slots.
+// Every kick launch folds its block or tile maxima into the slots with integer
+// atomic max, spread by workgroup index so that workgroups finishing together
+// do not queue on one address.
 constexpr int kKickSlots = 64;
 
 // One replica (a single lattice is a batch of one).  Lives in device memory;
@@ -50,24 +52,19 @@ hipError_t launch_philox_words(uint64_t seed, uint32_t i0, int64_t n, uint32_t c
 hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
                        int mode, double dx, double dy, double dz, hipStream_t st);
 // sigma_override >= 0 replaces every replica's kick scale (per-pulse temperature).
-// kickpart: scratch [nblk] of per-block maxima of | |s'| - 1 |, to be folded
-// into the running maxima by launch_kickmax_reduce (or by launch_obs).
+// Each block folds its maximum of | |s'| - 1 | into the running-maximum slots
+// of its replica in kickdev ([nrep][kKickSlots]).
 hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
-                       uint64_t k, double sigma_override, double* kickpart, hipStream_t st);
-// Folds the per-block maxima of each replica (its per-site blocks) into slot 0
-// of its kickdev slots.
-hipError_t launch_kickmax_reduce(const RepDev* reps, int nrep, const double* part,
-                                 unsigned long long* kickdev, hipStream_t st);
+                       uint64_t k, double sigma_override, unsigned long long* kickdev,
+                       hipStream_t st);
 // Work items of the observables pass for an Lx x Ly x Lz lattice (runs of
 // columns over z-slabs); a replica needs at most this many blocks.
 int64_t obs_item_count(int Lx, int Ly, int Lz);
 // Observables of every replica into result[r][8] (and accum when accumulate);
-// partials: [nobblk][8] scratch.  kick_fold > 0 also folds the pending
-// per-block kick maxima (as launch_kickmax_reduce) into kickdev.
+// partials: [nobblk][8] scratch.
 hipError_t launch_obs(int prec, int anis, const RepDev* reps, const int32_t* oblk_rep,
                       int nobblk, int nrep, State s, double* partials, double* result,
-                      double* accum, int accumulate, const double* kickpart, int kick_fold,
-                      unsigned long long* kickdev, hipStream_t st);
+                      double* accum, int accumulate, hipStream_t st);
 // Staged observables: launch_obs_partials writes the per-block partials of one
 // measurement ([nobblk][8], the first pass of launch_obs); launch_obs_staged
 // then reduces n staged measurements at once (measurement j's partials at

@@ -134,10 +134,14 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
     [0.3, 2], lambda log-uniform in [0.005, 0.05], J = 1, H = 0, dt = 0.1,
     Dt = 1.0, random-sphere starts, per-replica noise keys.
 
-    Throughput (random starts): the fp32 batch (one graph per run) over
-    n_pulses, and the plain fp64 single-lattice path on the same replicas one
-    after another over n_seq pulses (each lattice keyed with its replica's seed
-    and index, so it draws the same noise as the batch).
+    Throughput (random starts): the fp32 batch over n_pulses, and the plain
+    fp64 single-lattice path on the same replicas one after another over n_seq
+    pulses (each lattice keyed with its replica's seed and index, so it draws
+    the same noise as the batch).  The batch captures its schedule as a graph
+    on the first call of a given length and measurement spacing and replays it
+    for any first pulse (a long run in equal chunks); the timed call is such a
+    replay, and the first call of that length, capture included, is reported
+    beside it.
 
     Accuracy: fp32 and fp64 batches from the same start and noise over n_acc
     pulses; per replica, the time averages of E/N and |m| after `burn` pulses
@@ -155,8 +159,7 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
     sites = sum(int(np.prod(r["L"])) for r in reps)
     B = P.Batch(descs, precision="fp32", dt=0.1, Dt=1.0)
     B.autotune(cache_path=TUNE_CACHE)
-    B.run(first_pulse=0, n_pulses=10)  # capture + warm-up
-    B.run(first_pulse=0, n_pulses=10)
+    el_first, _ = _timed(lambda: B.run(first_pulse=10**6, n_pulses=n_pulses, obs_every=1))
     el_b, _ = _timed(lambda: B.run(first_pulse=10, n_pulses=n_pulses, obs_every=1))
     B.close()
 
@@ -220,6 +223,7 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
     rate_s = sites * 10 * n_seq / el_s
     return {"workload": "96 replicas (32 x 24^3, 48^3, 64^3), fp32 batch vs fp64 single-lattice path",
             "batched_fp32_spin_steps_per_s": rate_b,
+            "batched_fp32_first_call_spin_steps_per_s": sites * 10 * n_pulses / el_first,
             "batched_alg_hbm_frac": rate_b * BYTES_PER_SPIN_STEP["fp32"] / (HBM_PEAK_GBS * 1e9),
             "sequential_fp64_spin_steps_per_s": rate_s,
             "speedup": rate_b / rate_s,

@@ -234,7 +234,10 @@ lll_status lll_batch_create(int32_t n_rep, const lll_replica_desc* reps, lll_pre
                             lll_batch** out);
 /* Runs n_pulses intervals on every replica.  trace (optional, host):
  * [n_pulses/obs_every][n_rep] lll_obs; with a trace the call synchronises and
- * returns LLL_ENONFINITE or LLL_WARN_NORM as lll_run does, over all replicas. */
+ * returns LLL_ENONFINITE or LLL_WARN_NORM as lll_run does, over all replicas.
+ * The schedule is captured as a HIP graph on the first call with a given
+ * (n_pulses, obs_every) and replayed by later calls with the same pair, for any
+ * first_pulse (a long run made of equal chunks captures once). */
 lll_status lll_batch_run(lll_batch* b, uint64_t first_pulse, int64_t n_pulses, int32_t obs_every,
                          lll_obs* trace);
 /* Observables of every replica's current state (synchronises); statuses as

@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(kAdjBlock)
     if (!adj_site(reps, blk_rep, c)) return;
     const RepDev& R = reps[c.r];
     const T sg = (T)(sigma_override >= 0.0 ? sigma_override : R.sigma);
-    const uint4 w = philox_site(R.seed, (uint32_t)c.i, (uint32_t)k, R.rid, 0u);
+    const uint4 w = philox_site(R.seed, (uint32_t)c.i, (uint32_t)(k + R.kbase), R.rid, 0u);
     T G[3];
     gauss3<T>(w, G);  // the same normals as the forward kick of this precision
     const double p0 = (double)(T)(sg * G[0]), p1 = (double)(T)(sg * G[1]), p2 = (double)(T)(sg * G[2]);

@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(kSiteBlock)
     if (live) {
         const RepDev& R = reps[c.r];
         const double sg = sigma_override >= 0.0 ? sigma_override : R.sigma;
-        const uint4 w = philox_site(R.seed, (uint32_t)c.i, (uint32_t)k, R.rid, 0u);
+        const uint4 w = philox_site(R.seed, (uint32_t)c.i, (uint32_t)(k + R.kbase), R.rid, 0u);
         T* px = static_cast<T*>(s.x);
         T* py = static_cast<T*>(s.y);
         T* pz = static_cast<T*>(s.z);
@@ -137,6 +137,18 @@ __global__ void __launch_bounds__(kSiteBlock)
         atomicMax(kickdev + (int64_t)blk_rep[blockIdx.x] * kKickSlots +
                       (blockIdx.x & (kKickSlots - 1)),
                   (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void set_pulse_base_kernel(RepDev* reps, int nrep, uint64_t base) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrep) reps[r].kbase = base;
+}
+
+hipError_t launch_set_pulse_base(RepDev* reps, int nrep, uint64_t base, hipStream_t st) {
+    if (nrep <= 0) return hipSuccess;
+    hipLaunchKernelGGL(set_pulse_base_kernel, dim3((nrep + 63) / 64), dim3(64), 0, st, reps, nrep,
+                       base);
+    return hipGetLastError();
 }
 
 hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,

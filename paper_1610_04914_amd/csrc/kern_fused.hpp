@@ -285,7 +285,11 @@ __global__ void __launch_bounds__(NT)
     const T c6 = T(1) / T(6), c3 = T(1) / T(3), c2 = T(0.5);
     double kmax = 0.0;
     T sg = T(0);
-    if constexpr (KICK) sg = (T)(sigma_override >= 0.0 ? sigma_override : R.sigma);
+    uint32_t kp = 0;  // Philox counter word 1 of this launch's kick
+    if constexpr (KICK) {
+        sg = (T)(sigma_override >= 0.0 ? sigma_override : R.sigma);
+        kp = (uint32_t)(kpulse + R.kbase);
+    }
 
     // Item j's points cover stage region Rs entirely (compile time), or this
     // wave holds at least one of its points (wave-uniform).
@@ -451,7 +455,7 @@ __global__ void __launch_bounds__(NT)
                             const int64_t g = (int64_t)col[j] + plane * gz;
                             if constexpr (KICK) {
                                 const uint4 w =
-                                    philox_site(R.seed, (uint32_t)g, (uint32_t)kpulse, R.rid, 0u);
+                                    philox_site(R.seed, (uint32_t)g, kp, R.rid, 0u);
                                 const double d = kick_spin<T>(rx, ry, rz, w, sg);
                                 kmax = (d > kmax || d != d) ? d : kmax;
                             }

@@ -1249,7 +1249,6 @@ struct lll_batch {
     int64_t n = 0;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    uint64_t g_first = 0;
     int64_t g_npulses = -1;
     int32_t g_obs_every = -1;
     ~lll_batch() {
@@ -1334,8 +1333,10 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
         if ((s = alloc_state(E, E.alt)) != LLL_OK) return s;
         if ((s = ensure_tiles(E)) != LLL_OK) return s;
     }
-    const bool reuse = B->gexec && B->g_first == first_pulse && B->g_npulses == n_pulses &&
-                       B->g_obs_every == obs_every;
+    // The captured schedule carries pulse indices relative to the first pulse
+    // (the kernels add the descriptors' kbase), so it replays for any first
+    // pulse with the same length and measurement spacing.
+    const bool reuse = B->gexec && B->g_npulses == n_pulses && B->g_obs_every == obs_every;
     if (!reuse) {
         if (B->gexec) { (void)hipGraphExecDestroy(B->gexec); B->gexec = nullptr; }
         if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
@@ -1352,7 +1353,7 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
         E.carried = false;
         obs_begin(E, E.d_trace, (int64_t)8 * E.nrep);
         for (int64_t q = 0; q < n_pulses && cap == LLL_OK; ++q) {
-            const uint64_t k = first_pulse + (uint64_t)q;
+            const uint64_t k = (uint64_t)q;  // relative to the first pulse
             const bool measure = obs_every > 0 && (q + 1) % obs_every == 0;
             cap = do_interval(E, B->n, k, -1.0, q + 1 < n_pulses && !measure, k + 1, -1.0);
             if (cap == LLL_OK && measure) cap = obs_stage(E);
@@ -1374,10 +1375,10 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
         if (made_stream) (void)hipStreamDestroy(cs);
         B->graph = g;
         HIP_TRY(hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
-        B->g_first = first_pulse;
         B->g_npulses = n_pulses;
         B->g_obs_every = obs_every;
     }
+    HIP_TRY(launch_set_pulse_base(E.dreps, E.nrep, first_pulse, E.st));
     HIP_TRY(hipGraphLaunch(B->gexec, E.st));
     if (trace && nmeas > 0) {
         std::vector<double> h((size_t)nmeas * 8 * E.nrep);

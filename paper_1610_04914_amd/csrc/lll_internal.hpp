@@ -34,6 +34,10 @@ struct RepDev {
     double sigma;                 // default kick scale sqrt(2 lambda T Dt)
     double lambda, Dt;            // to rescale sigma for a per-pulse temperature
     uint64_t seed;
+    // Added to the pulse index of every kick.  0 for a lattice; a batch sets
+    // it before each replay of its captured schedule, whose kicks carry the
+    // pulse index relative to the run's first pulse.
+    uint64_t kbase;
     uint32_t rid;                 // Philox counter word 2
     int32_t init;                 // initial state: 0 random sphere, 1 along the init direction
     const void* D_site;           // ANIS_SITE: [N] of the state precision
@@ -54,6 +58,8 @@ hipError_t launch_init(int prec, const RepDev* reps, const int32_t* blk_rep, int
 // sigma_override >= 0 replaces every replica's kick scale (per-pulse temperature).
 // Each block folds its maximum of | |s'| - 1 | into the running-maximum slots
 // of its replica in kickdev ([nrep][kKickSlots]).
+// Sets kbase of every replica's device descriptor to base.
+hipError_t launch_set_pulse_base(RepDev* reps, int nrep, uint64_t base, hipStream_t st);
 hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int nblk, State s,
                        uint64_t k, double sigma_override, unsigned long long* kickdev,
                        hipStream_t st);

@@ -141,7 +141,9 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
     on the first call of a given length and measurement spacing and replays it
     for any first pulse (a long run in equal chunks); the timed call is such a
     replay, and the first call of that length, capture included, is reported
-    beside it.
+    beside it.  Both paths measure every interval on the device (observables
+    and running sums) without copying a per-interval trace to Python, whose
+    conversion alone would take 0.08 s of a 0.9 s batch call.
 
     Accuracy: fp32 and fp64 batches from the same start and noise over n_acc
     pulses; per replica, the time averages of E/N and |m| after `burn` pulses
@@ -159,8 +161,9 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
     sites = sum(int(np.prod(r["L"])) for r in reps)
     B = P.Batch(descs, precision="fp32", dt=0.1, Dt=1.0)
     B.autotune(cache_path=TUNE_CACHE)
-    el_first, _ = _timed(lambda: B.run(first_pulse=10**6, n_pulses=n_pulses, obs_every=1))
-    el_b, _ = _timed(lambda: B.run(first_pulse=10, n_pulses=n_pulses, obs_every=1))
+    el_first, _ = _timed(lambda: B.run(first_pulse=10**6, n_pulses=n_pulses, obs_every=1,
+                                       trace=False))
+    el_b, _ = _timed(lambda: B.run(first_pulse=10, n_pulses=n_pulses, obs_every=1, trace=False))
     B.close()
 
     B0 = P.Batch(descs, precision="fp64", dt=0.1, Dt=1.0)
@@ -174,7 +177,8 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
         lat.run(p, first_pulse=0, n_pulses=2)
 
     def run_seq():
-        return [lat.run(p, first_pulse=2, n_pulses=n_seq, obs_every=1) for lat, p in lats]
+        return [lat.run(p, first_pulse=2, n_pulses=n_seq, obs_every=1, trace=False)
+                for lat, p in lats]
     el_s, _ = _timed(run_seq)
     for lat, _ in lats:
         lat.close()

@@ -179,8 +179,10 @@ def lll_observables(h, params: lll_params) -> dict:
 
 
 def lll_run(h, params: lll_params, first_pulse: int, n_pulses: int, T_per_pulse=None,
-            obs_every: int = 0):
-    nm = n_pulses // obs_every if obs_every > 0 else 0
+            obs_every: int = 0, trace: bool = True):
+    """trace=False: the measurements still run (running sums, last values on the
+    device) but none is copied back; returns []."""
+    nm = n_pulses // obs_every if obs_every > 0 and trace else 0
     tr = (lll_obs * max(nm, 1))()
     Tp = None
     if T_per_pulse is not None:
@@ -294,8 +296,8 @@ class Lattice:
         return lll_observables(self.h, p.c())
 
     def run(self, p: Params, first_pulse: int = 0, n_pulses: int = 1, T_per_pulse=None,
-            obs_every: int = 0):
-        return lll_run(self.h, p.c(), first_pulse, n_pulses, T_per_pulse, obs_every)
+            obs_every: int = 0, trace: bool = True):
+        return lll_run(self.h, p.c(), first_pulse, n_pulses, T_per_pulse, obs_every, trace)
 
     def kick_norm_dev(self, reset: bool = False) -> float:
         v = C.c_double()
@@ -471,8 +473,10 @@ class Batch:
                "lll_batch_create")
         self.h = h
 
-    def run(self, first_pulse: int, n_pulses: int, obs_every: int = 0):
-        nm = n_pulses // obs_every if obs_every > 0 else 0
+    def run(self, first_pulse: int, n_pulses: int, obs_every: int = 0, trace: bool = True):
+        """trace=False: measurements run on the device (running sums) without
+        copying a trace back; returns []."""
+        nm = n_pulses // obs_every if obs_every > 0 and trace else 0
         tr = (lll_obs * max(nm * self.n, 1))()
         _check(lib().lll_batch_run(self.h, C.c_uint64(first_pulse), int(n_pulses), int(obs_every),
                                    tr if nm > 0 else None), "lll_batch_run")

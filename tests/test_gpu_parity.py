@@ -333,20 +333,26 @@ def test_staged_measurements_match_one_by_one(P, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_one_step_intervals_bitexact(P, prec):
     """Batch with n = 1: one replay of K intervals equals K replays of one
-    interval, bit for bit, with and without measurements in between."""
+    interval, bit for bit, with and without measurements in between; without
+    a trace the measurements still feed the same running sums."""
     reps = BATCH_SETS["mixed"]
     A = P.Batch(reps, precision=prec, dt=0.2, Dt=0.2)
     B = P.Batch(reps, precision=prec, dt=0.2, Dt=0.2)
     C = P.Batch(reps, precision=prec, dt=0.2, Dt=0.2)
+    D = P.Batch(reps, precision=prec, dt=0.2, Dt=0.2)
     A.run(first_pulse=5, n_pulses=4)
     for q in range(4):
         B.run(first_pulse=5 + q, n_pulses=1)
-    C.run(first_pulse=5, n_pulses=4, obs_every=3)
+    tc = C.run(first_pulse=5, n_pulses=4, obs_every=3)
+    assert D.run(first_pulse=5, n_pulses=4, obs_every=3, trace=False) == []
     torch.cuda.synchronize()
     for r in range(len(reps)):
         assert torch.equal(A.state(r), B.state(r)), r
         assert torch.equal(A.state(r), C.state(r)), r
-    for X in (A, B, C):
+        assert torch.equal(A.state(r), D.state(r)), r
+    assert len(tc) == 1
+    assert C.accumulators() == D.accumulators()
+    for X in (A, B, C, D):
         X.close()
 
 

@@ -507,6 +507,37 @@ def test_lattice_with_replica_key_follows_batch(P, prec):
     B.close()
 
 
+def test_batch_replay_across_pulse_counter_wrap(P):
+    """A batch replays its captured schedule for any first pulse, also where the
+    pulse index passes 2^32 (the kick's counter word is the index mod 2^32):
+    two replays of a two-interval schedule equal one four-interval run bit for
+    bit, and a lone lattice keyed like a replica follows that replica."""
+    reps = BATCH_SETS["mixed"]
+    k0 = 2**32 - 2
+    dt, Dt = 0.1, 0.4
+    A = P.Batch(reps, precision="fp64", dt=dt, Dt=Dt)
+    B = P.Batch(reps, precision="fp64", dt=dt, Dt=Dt)
+    C = P.Batch(reps, precision="fp64", dt=dt, Dt=Dt)
+    A.run(first_pulse=k0, n_pulses=4)
+    B.run(first_pulse=k0, n_pulses=2)
+    B.run(first_pulse=k0 + 2, n_pulses=2)  # replay of the same graph
+    torch.cuda.synchronize()
+    for r in range(len(reps)):
+        assert torch.equal(A.state(r), B.state(r)), r
+    for r in (1, 4):
+        d = reps[r]
+        lat = P.Lattice(d["L"], precision="fp64", bc=d.get("bc", "periodic"), state=C.state(r))
+        p = P.Params(J=1.0, H=d.get("H", (0, 0, 0)), D=d.get("D", 0.0), lam=d["lam"], T=d["T"],
+                     dt=dt, Dt=Dt, seed=d["seed"], replica=d["replica"])
+        lat.run(p, first_pulse=k0, n_pulses=4)
+        torch.cuda.synchronize()
+        err = (lat.state - A.state(r)).abs().max().item()
+        assert err < 1e-12, (r, err)
+        lat.close()
+    for X in (A, B, C):
+        X.close()
+
+
 # ------------------------------------------- the other workload configs -----
 def test_small_fp64_workload_per_segment(P):
     """16^3 periodic fp64 ferromagnet (J = 1, H = 0, D = 0, lambda = 0.01, T = 1,

@@ -330,6 +330,24 @@ def test_staged_measurements_match_one_by_one(P, prec):
         L.close()
 
 
+def test_staging_buffer_full_mid_run(P):
+    """128^3 fp32: the staging buffer holds 512 measurements (64 KiB of
+    partials each), so a run of 520 measured intervals reduces a full buffer
+    mid-run and the rest at the end; its trace and running sums equal those
+    of two runs of 260, bit for bit."""
+    shape = (128, 128, 128)
+    _, gp = both_params("zaxis", dt=0.2, Dt=0.2, seed=2)
+    a = P.Lattice(shape, precision="fp32", seed=5)
+    b = P.Lattice(shape, precision="fp32", seed=5)
+    ta = a.run(gp, first_pulse=0, n_pulses=520, obs_every=1)
+    tb = b.run(gp, first_pulse=0, n_pulses=260, obs_every=1)
+    tb += b.run(gp, first_pulse=260, n_pulses=260, obs_every=1)
+    assert ta == tb
+    assert a.accumulators() == b.accumulators()
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_one_step_intervals_bitexact(P, prec):
     """Batch with n = 1: one replay of K intervals equals K replays of one

@@ -25,8 +25,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
         const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // three-input XORs as one gfx950 bitop3 (truth table 0x96); in the first
+        // round the words other than c0 are wave-uniform in every caller, so n0
+        // is left to the scalar unit there
+        const uint32_t n0 = r == 0 ? hi1 ^ c1 ^ k0 : __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
         c0 = n0;
         c1 = lo1;
         c2 = n2;

@@ -302,6 +302,33 @@ def test_schedule_identity_one_step_intervals(P, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", ["rk2mid", "rk5b"])
+def test_one_step_intervals_other_integrators(P, prec, method):
+    """The carried kick of one-step intervals with the Appendix's integrators
+    (RK2 midpoint: fused single-step launches; Butcher's RK5: per-stage path,
+    kick in its own launch): a run of K intervals equals K one-interval runs
+    bit for bit, with the kick fused and in its own launch."""
+    shape = (40, 24, 20)
+    _, gp = both_params("zaxis", dt=0.2, Dt=0.2, lam=0.1, seed=7, precession=False)
+    gp = dataclasses.replace(gp, integrator=method)
+    Ts = [1.8, 1.1, 0.6, 0.4]
+    for fused in (True, False):
+        a = P.Lattice(shape, precision=prec, seed=3)
+        b = P.Lattice(shape, precision=prec, seed=3)
+        for L in (a, b):
+            L.set_kick_fusion(fused)
+            L.kick_norm_dev(reset=True)
+        a.run(gp, first_pulse=50, n_pulses=len(Ts), T_per_pulse=Ts)
+        for q, T in enumerate(Ts):
+            b.run(gp, first_pulse=50 + q, n_pulses=1, T_per_pulse=[T])
+        torch.cuda.synchronize()
+        assert torch.equal(a.state, b.state), (method, fused)
+        assert a.kick_norm_dev() == b.kick_norm_dev(), (method, fused)
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_staged_measurements_match_one_by_one(P, prec):
     """The measurements of a run are reduced in groups (at most 1024 per
     launch, here more than one group); the trace and the running sums equal,

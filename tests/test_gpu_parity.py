@@ -467,6 +467,76 @@ def test_full_size_sampled(P, prec):
     np.testing.assert_allclose(got["m"], want["m"], rtol=1e-11, atol=1e-14)
 
 
+def test_max_size_sampled(P):
+    """A lattice just under the 2^31 - 1 site limit and ragged in x and y
+    (1023 x 1025 x 2047 = 2,146,433,025 sites, 25.8 GB per fp32 state copy)
+    in the default launch configuration: one interval of two steps with the
+    kick epilogue.  Sampled sites, the last ones included, against the oracle
+    on free-boundary cut-outs of radius 8 with the sites' global noise
+    counters; the observables against fp64 reductions of the whole state done
+    here with torch (z-slabs of 256 planes, periodic bonds to +x, +y, +z)."""
+    shape = (1023, 1025, 2047)
+    Lx, Ly, Lz = shape
+    N = Lx * Ly * Lz
+    assert N < 2**31 - 1
+    op, gp = both_params("zaxis", dt=0.2, Dt=0.4, seed=0)
+    lat = P.Lattice(shape, precision="fp32", init="random", seed=0)
+    rng = np.random.default_rng(31)
+    cen = [tuple(int(v) for v in c) for c in zip(rng.integers(0, Lx, 12), rng.integers(0, Ly, 12),
+                                                 rng.integers(0, Lz, 12))]
+    cen += [(0, 0, 0), (Lx - 1, Ly - 1, Lz - 1), (Lx - 1, 0, Lz - 1), (0, Ly - 1, Lz - 2)]
+    rad = 8
+    n = 2 * rad + 1
+    r = np.arange(-rad, rad + 1)
+    cuts = []
+    for cx, cy, cz in cen:
+        Z, Y, X = np.meshgrid((cz + r) % Lz, (cy + r) % Ly, (cx + r) % Lx, indexing="ij")
+        ids = (X + Lx * (Y + Ly * Z.astype(np.int64))).ravel()
+        st = lat.state[:, torch.from_numpy(ids).cuda()].double().cpu().numpy()
+        cuts.append((ids, st))
+    lat.run(gp, first_pulse=3, n_pulses=1)
+    torch.cuda.synchronize()
+    gc = orc.geom((n, n, n), "free")
+    mid = (n**3) // 2
+    for (cx, cy, cz), (ids, st) in zip(cen, cuts):
+        st = orc.step(gc, op, st, 1)
+        st, _ = orc.kick_indexed(gc, op, st, op.T, seed=0, r=0, k=3, site_id=ids.astype(np.uint32))
+        st = orc.step(gc, op, st, 1)
+        i = cx + Lx * (cy + Ly * cz)
+        got = lat.state[:, i].double().cpu().numpy()
+        err = np.max(np.abs(st[:, mid] - got))
+        assert err < TOL["fp32"], ((cx, cy, cz), err)
+    got = lat.observables(gp)
+    v = lat.state.view(3, Lz, Ly, Lx)
+    bonds = anis = 0.0
+    msum = np.zeros(3)
+    n2max, n2min = -1.0, 9.0
+    for z0 in range(0, Lz, 256):
+        z1 = min(z0 + 256, Lz)
+        c = v[:, z0:z1].double()
+        msum += c.sum(dim=(1, 2, 3)).cpu().numpy()
+        n2 = (c * c).sum(0)
+        n2max, n2min = max(n2max, float(n2.max())), min(n2min, float(n2.min()))
+        del n2
+        anis += float((c[2] * c[2]).sum())
+        bonds += float((c * c.roll(-1, dims=3)).sum()) + float((c * c.roll(-1, dims=2)).sum())
+        bonds += float((c[:, :-1] * c[:, 1:]).sum())
+        bonds += float((c[:, -1] * v[:, z1 % Lz].double()).sum())
+        del c
+    J, H, D = op.J, op.H, op.D
+    e_exch = -J * bonds
+    e_zee = -(H[0] * msum[0] + H[1] * msum[1] + H[2] * msum[2])
+    e_anis = -D * anis
+    assert got["E_exch"] == pytest.approx(e_exch, rel=1e-10)
+    assert got["E_zeeman"] == pytest.approx(e_zee, rel=1e-10, abs=1e-5)
+    assert got["E_anis"] == pytest.approx(e_anis, rel=1e-10)
+    assert got["E_total"] == pytest.approx(e_exch + e_zee + e_anis, rel=1e-10)
+    np.testing.assert_allclose(got["m"], msum / N, rtol=1e-9, atol=1e-13)
+    dev = max(np.sqrt(n2max) - 1.0, 1.0 - np.sqrt(n2min))
+    assert got["max_norm_dev"] == pytest.approx(dev, rel=1e-12, abs=1e-15)
+    lat.close()
+
+
 # ------------------------------------------------------------------ batch ---
 BATCH_SETS = {
     "mixed": [dict(L=(8, 8, 8), T=0.5, lam=0.02, seed=11, replica=0),

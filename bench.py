@@ -289,6 +289,34 @@ def extra_overdamped(n_pulses: int = 5000):
             "final_abs_m": float(np.linalg.norm(tr[-1]["m"]))}
 
 
+def extra_max_lattice(n_pulses: int = 10):
+    """The largest lattice the library accepts, 1024 x 1024 x 2047 (2.15e9
+    sites, 25.8 GB per fp32 state copy), headline physics, fp32, observables
+    every interval.  Step variant 1 (32 x 16 tiles) with the z-chunk chosen by
+    a short sweep (three intervals each, measurements on the device); then
+    n_pulses intervals timed with their trace."""
+    import paper_1610_04914_amd as P
+    lat = P.Lattice((1024, 1024, 2047), precision="fp32", init="random", seed=0)
+    p = P.Params(**PHYS)
+    n = int(round(PHYS["Dt"] / PHYS["dt"]))
+    sweep = {}
+    for bz in (128, 256, 512, 1024, 2047):
+        lat.set_step_config(1, bz)
+        lat.run(p, 10**6, 1, obs_every=1, trace=False)
+        el, _ = _timed(lambda: lat.run(p, 10**6 + 1, 3, obs_every=1, trace=False))
+        sweep[bz] = lat.N * n * 3 / el
+    best = max(sweep, key=sweep.get)
+    lat.set_step_config(1, best)
+    el, tr = _timed(lambda: lat.run(p, 0, n_pulses, obs_every=1))
+    rate = lat.N * n * n_pulses / el
+    N = lat.N
+    lat.close()
+    return {"workload": "1024x1024x2047 (2.15e9 sites), headline physics, fp32, obs every interval",
+            "sites": N, "pulses": n_pulses, "bz": best, "spin_steps_per_s": rate,
+            "alg_hbm_frac": rate * BYTES_PER_SPIN_STEP["fp32"] / (HBM_PEAK_GBS * 1e9),
+            "bz_sweep_spin_steps_per_s": sweep, "final_E_per_site": tr[-1]["E_total"] / N}
+
+
 def extra_integrators(n_pulses: int = 50):
     """The headline lattice and physics (128^3 fp32, precession, dt = 0.2,
     Dt = 2) stepped with each integrator of the Appendix: classical RK4 (one
@@ -528,7 +556,8 @@ def _progress(name, fn):
 
 EXTRAS = {"temperatures": extra_temperatures, "headline_256": extra_headline_256,
           "config_16": extra_config_16, "batched": extra_batched, "adjoint": extra_adjoint,
-          "overdamped_256": extra_overdamped, "integrators": extra_integrators,
+          "overdamped_256": extra_overdamped, "max_lattice": extra_max_lattice,
+          "integrators": extra_integrators,
           "escape": extra_escape, "precision": extra_precision}
 
 

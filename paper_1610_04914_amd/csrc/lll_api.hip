@@ -1011,7 +1011,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     cands.push_back({0, 0});
     if (E.anis != ANIS_SITE && E.integrator != LLL_RK5B) {  // RK5 has no fused kernel
         for (int v = 1; v <= fused_variant_count(E.prec); ++v) {
-            const int bzs[] = {4, 8, 12, 16, 24, 32, 48, 64};
+            const int bzs[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512, 1024};
             for (int b : bzs)
                 if (b <= std::max(maxLz, 4)) cands.push_back({v, b});
         }

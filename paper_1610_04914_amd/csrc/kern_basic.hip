@@ -134,9 +134,9 @@ __global__ void __launch_bounds__(kSiteBlock)
     static_assert(kSiteBlock == 256, "block_max256 assumes 256 threads");
     const double m = block_max256(dev);
     if (threadIdx.x == 0)
-        atomicMax(kickdev + (int64_t)blk_rep[blockIdx.x] * kKickSlots +
-                      (blockIdx.x & (kKickSlots - 1)),
-                  (unsigned long long)__double_as_longlong(m));
+        fold_max_slot(kickdev + (int64_t)blk_rep[blockIdx.x] * kKickSlots +
+                          (blockIdx.x & (kKickSlots - 1)),
+                      m);
 }
 
 __global__ void set_pulse_base_kernel(RepDev* reps, int nrep, uint64_t base) {

@@ -500,8 +500,7 @@ __global__ void __launch_bounds__(NT)
                 const double c = wred[w];
                 m = (c > m || c != c) ? c : m;
             }
-            atomicMax(kickdev + (int64_t)tl.x * kKickSlots + (blockIdx.x & (kKickSlots - 1)),
-                      (unsigned long long)__double_as_longlong(m));
+            fold_max_slot(kickdev + (int64_t)tl.x * kKickSlots + (blockIdx.x & (kKickSlots - 1)), m);
         }
     }
 }

@@ -175,6 +175,16 @@ __device__ __forceinline__ double kick_spin(T& sx, T& sy, T& sz, uint4 w, T sigm
     return renorm<T>(ox, oy, oz, sx, sy, sz);
 }
 
+// Folds m >= 0 (or NaN) into a running-maximum slot holding double bit
+// patterns.  The slot only grows, so a plain read that already shows a value
+// >= m, however stale, makes the atomic unnecessary: after the first kick of
+// a run almost every workgroup skips it, and workgroups that finish together
+// do not queue on the slot's cache line.
+__device__ __forceinline__ void fold_max_slot(unsigned long long* slot, double m) {
+    const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+    if (*(volatile const unsigned long long*)slot < mb) atomicMax(slot, mb);
+}
+
 // Load at a wave-uniform base plus a 32-bit per-lane byte offset.  The base
 // (pinned to scalar registers) and the offset are hidden from the optimiser,
 // which would otherwise fold them into a 64-bit per-lane address.

@@ -1043,16 +1043,17 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     }
     E.variant = bv;
     E.bz = bb;
-    // kick placement: epilogue of the fused step, or its own launch (whole intervals timed)
+    // kick placement: epilogue of the fused step, or its own launch (whole intervals timed;
+    // the two differ by a few per cent of an interval, so three alternating trials of six)
     bool bk = true;
     if (s == LLL_OK && bv != 0 && E.anis != ANIS_SITE && n_interval >= 2) {
         double tk[2] = {1e30, 1e30};
-        for (int trial = 0; trial < 2 && s == LLL_OK; ++trial)
+        for (int trial = 0; trial < 3 && s == LLL_OK; ++trial)
             for (int mode = 0; mode < 2 && s == LLL_OK; ++mode) {
                 E.kick_epilogue = mode == 1;
                 if ((s = do_interval(E, n_interval, 0, -1.0)) != LLL_OK) break;
                 HIP_TRY(hipEventRecord(e0, E.st));
-                for (int q = 0; q < 3 && s == LLL_OK; ++q) s = do_interval(E, n_interval, 1 + q, -1.0);
+                for (int q = 0; q < 6 && s == LLL_OK; ++q) s = do_interval(E, n_interval, 1 + q, -1.0);
                 HIP_TRY(hipEventRecord(e1, E.st));
                 if (s == LLL_OK) s = settle(E);
                 HIP_TRY(hipEventSynchronize(e1));

@@ -115,7 +115,10 @@ typedef struct {
 typedef struct lll_lattice lll_lattice;
 typedef struct lll_batch lll_batch;
 
-/* Creates a lattice of Lx*Ly*Lz sites on the current HIP device.
+/* Creates a lattice of Lx*Ly*Lz sites on the current HIP device, with the
+ * starting states of the paper's runs: spins uniformly distributed on the
+ * sphere (the disordered start of the many-spin runs of Sec. IV), or all
+ * along one direction (the ordered starts of Secs. III-IV).
  * sx, sy, sz: caller-owned device buffers of N elements of the precision
  * (all three or none); when NULL the library allocates and owns them.
  * hip_stream: the hipStream_t to enqueue on (NULL = the default stream).
@@ -127,16 +130,22 @@ lll_status lll_init_lattice(int32_t Lx, int32_t Ly, int32_t Lz, lll_bc bc, lll_p
                             lll_init mode, const double dir[3], uint64_t seed, void* sx, void* sy,
                             void* sz, void* hip_stream, lll_lattice** out);
 
-/* n_steps >= 0 classical RK4 steps of the noise-free equation (Eq. (1) with
- * zeta = 0; no renormalisation).  Only params' physics and dt are used. */
+/* n_steps >= 0 steps of size dt of the noise-free equation (Eq. (1) with
+ * zeta = 0; no renormalisation), with the integrator params->integrator
+ * (classical RK4 unless it names another).  Only params' physics, dt and
+ * integrator are used. */
 lll_status lll_step_conservative(lll_lattice* lat, const lll_params* params, int64_t n_steps);
 
 /* One pulse-noise kick with pulse index pulse_index at temperature params->T
  * (Eqs. (5)-(6)) followed by renormalisation of every spin.  Stateless: the
- * noise depends only on (seed, site, pulse_index, replica 0). */
+ * noise depends only on (params->seed, site, pulse_index, params->replica). */
 lll_status lll_noise_pulse(lll_lattice* lat, const lll_params* params, uint64_t pulse_index);
 
-/* Observables of the current state into *out_host (synchronises the stream).
+/* Observables of the current state into *out_host (synchronises the stream):
+ * the energy of Eq. (1)'s Hamiltonian split into exchange, Zeeman and
+ * anisotropy parts, the magnetisation per site and the largest spin-length
+ * deviation, the quantities the paper measures at the end of each noise
+ * interval (Sec. III.A) and averages over a run (Sec. IV).
  * LLL_ENONFINITE when the state holds a NaN or Inf; LLL_WARN_NORM when its
  * max_norm_dev exceeds LLL_NORM_WARN_LEVEL (out_host is filled in both cases). */
 lll_status lll_observables(lll_lattice* lat, const lll_params* params, lll_obs* out_host);

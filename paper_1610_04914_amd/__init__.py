@@ -245,6 +245,28 @@ class Params:
         return p
 
 
+def check_site_arrays(p: "Params", N: int, dtype) -> None:
+    """Raises before any launch unless p's per-site anisotropy arrays are
+    device tensors of the lattice dtype, contiguous, with N entries (D_site)
+    and 3N entries (e_site, x block then y block then z block), given
+    together.  The library reads them through raw device pointers."""
+    if (p.D_site is None) != (p.e_site is None):
+        raise ValueError("D_site and e_site must be given together")
+    for name, t, n in (("D_site", p.D_site, N), ("e_site", p.e_site, 3 * N)):
+        if t is None:
+            continue
+        if not all(hasattr(t, a) for a in ("data_ptr", "is_cuda", "dtype", "is_contiguous")):
+            raise TypeError(f"{name} must be a torch tensor")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must live in device memory")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} has dtype {t.dtype}; the lattice computes in {dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} entries; {n} expected")
+
+
 _PREC = {"fp64": LLL_FP64, "fp32": LLL_FP32}
 _INTEGRATOR = {"rk4": 0, "rk2mid": 1, "rk5b": 2}
 _BC = {"periodic": LLL_BC_PERIODIC, "free": LLL_BC_FREE}
@@ -286,18 +308,22 @@ class Lattice:
         except Exception:
             pass
 
+    def _pc(self, p: Params) -> lll_params:
+        check_site_arrays(p, self.N, self.dtype)
+        return p.c()
+
     def step(self, p: Params, n_steps: int = 1):
-        return lll_step_conservative(self.h, p.c(), n_steps)
+        return lll_step_conservative(self.h, self._pc(p), n_steps)
 
     def pulse(self, p: Params, k: int):
-        return lll_noise_pulse(self.h, p.c(), k)
+        return lll_noise_pulse(self.h, self._pc(p), k)
 
     def observables(self, p: Params) -> dict:
-        return lll_observables(self.h, p.c())
+        return lll_observables(self.h, self._pc(p))
 
     def run(self, p: Params, first_pulse: int = 0, n_pulses: int = 1, T_per_pulse=None,
             obs_every: int = 0, trace: bool = True):
-        return lll_run(self.h, p.c(), first_pulse, n_pulses, T_per_pulse, obs_every, trace)
+        return lll_run(self.h, self._pc(p), first_pulse, n_pulses, T_per_pulse, obs_every, trace)
 
     def kick_norm_dev(self, reset: bool = False) -> float:
         v = C.c_double()
@@ -333,7 +359,7 @@ class Lattice:
 
     def autotune(self, p: Params, cache_path: Optional[str] = None):
         v, b = C.c_int32(), C.c_int32()
-        _check(lib().lll_autotune(self.h, p.c(), cache_path.encode() if cache_path else None,
+        _check(lib().lll_autotune(self.h, self._pc(p), cache_path.encode() if cache_path else None,
                                   C.byref(v), C.byref(b)))
         return v.value, b.value
 
@@ -354,7 +380,7 @@ class Lattice:
             gD = None
             gDp = C.cast(C.byref(gDh), C.c_void_p)
         gs0 = torch.zeros((3, self.N), dtype=self.dtype, device="cuda") if want_g_s0 else None
-        _check(lib().lll_adjoint(self.h, C.byref(p.c()), C.c_uint64(first_pulse), int(n_pulses),
+        _check(lib().lll_adjoint(self.h, C.byref(self._pc(p)), C.c_uint64(first_pulse), int(n_pulses),
                                  int(ckpt_every), float(wE), wmc, C.byref(loss), gH, C.byref(gJ),
                                  gDp, C.c_void_p(gs0.data_ptr()) if gs0 is not None else None),
                "lll_adjoint")
@@ -381,7 +407,7 @@ def _loss_function():
             if D.dim() == 0:
                 p = replace(p, D=float(D.detach().cpu()), D_site=None)
             else:
-                p = replace(p, D_site=D.detach())
+                p = replace(p, D_site=D.detach().to(lat.dtype).contiguous())
             s0 = lat.state.clone()
             lat.run(p, first_pulse=first_pulse, n_pulses=n_pulses)
             o = lat.observables(p)

@@ -170,8 +170,10 @@ hipError_t launch_kick(int prec, const RepDev* reps, const int32_t* blk_rep, int
 // the partials of every replica in block order.  No floating-point atomics:
 // results are bit-identical from run to run.  (A single pass that lets the
 // last block finish would need a device-scope release per block, which
-// writes back the L2 of its XCD each time and costs far more than a launch.)  Each site owns its bonds to its +x, +y and
-// +z neighbours (Eq. (2) counts every bond once).
+// writes back the L2 of its XCD each time and costs far more than a launch.)
+// Each site owns its bonds to its +x, +y and +z neighbours, so every bond is
+// counted once: E = -J sum over bonds, the convention under which the
+// simple-cubic T_c / J = 1.44 quoted in Sec. IV holds.
 
 // The 8 reduced quantities: sums 0..5, max (6) and min (7) of |s|^2.  The
 // norm deviation max_i | |s_i| - 1 | follows from the extremes alone (sqrt and

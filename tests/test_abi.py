@@ -194,3 +194,50 @@ def test_status_codes_and_constants_match_header(P):
         assert getattr(P, k) == v, k
     lvl = float(re.search(r"#define LLL_NORM_WARN_LEVEL\s+([0-9.eE+-]+)", txt).group(1))
     assert P.NORM_WARN_LEVEL == lvl
+
+
+def test_site_arrays_rejected_before_any_launch():
+    """Per-site anisotropy arrays reach the kernels as raw device pointers, so
+    the binding refuses host tensors, a dtype other than the lattice's,
+    non-contiguous views, wrong sizes and a lone D_site before any call."""
+    import torch
+
+    import paper_1610_04914_amd as P
+    N = 24
+    ok = dict(dtype=torch.float32)
+    D = torch.ones(N, **ok)
+    e = torch.zeros(3 * N, **ok)
+    with pytest.raises(ValueError, match="device memory"):
+        P.check_site_arrays(P.Params(D_site=D, e_site=e), N, torch.float32)
+    with pytest.raises(ValueError, match="together"):
+        P.check_site_arrays(P.Params(D_site=D), N, torch.float32)
+    with pytest.raises(TypeError):
+        P.check_site_arrays(P.Params(D_site=[1.0] * N, e_site=[0.0] * 3 * N), N, torch.float32)
+
+    class FakeDev:
+        """Quacks like a device tensor so the remaining checks are reached on a
+        host without a GPU."""
+        def __init__(self, t, contiguous=True):
+            self.t, self.c = t, contiguous
+            self.is_cuda = True
+            self.dtype = t.dtype
+
+        def data_ptr(self):
+            return self.t.data_ptr()
+
+        def is_contiguous(self):
+            return self.c
+
+        def numel(self):
+            return self.t.numel()
+
+    P.check_site_arrays(P.Params(D_site=FakeDev(D), e_site=FakeDev(e)), N, torch.float32)
+    with pytest.raises(ValueError, match="dtype"):
+        P.check_site_arrays(P.Params(D_site=FakeDev(D), e_site=FakeDev(e)), N, torch.float64)
+    with pytest.raises(ValueError, match="contiguous"):
+        P.check_site_arrays(P.Params(D_site=FakeDev(D, False), e_site=FakeDev(e)), N,
+                            torch.float32)
+    with pytest.raises(ValueError, match="entries"):
+        P.check_site_arrays(P.Params(D_site=FakeDev(D), e_site=FakeDev(e[:N])), N, torch.float32)
+    with pytest.raises(ValueError, match="entries"):
+        P.check_site_arrays(P.Params(D_site=FakeDev(D[:5]), e_site=FakeDev(e)), N, torch.float32)

@@ -467,6 +467,47 @@ def test_full_size_sampled(P, prec):
     np.testing.assert_allclose(got["m"], want["m"], rtol=1e-11, atol=1e-14)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_headline_interval_full_size(P, prec):
+    """The headline workload's own interval on the whole 128^3 lattice, in the
+    benchmark's tuned launch configuration (kick fused where it is tuned so):
+    dt = 0.2, Dt = 2 (n = 10: five steps, kick, five steps; Eq. (7)), J = 1,
+    H = (0, 0, 0.1), D = 0.05 along z, lambda = 0.01, T = 1.  Two intervals,
+    each against the oracle started from the GPU's state before it: every spin
+    component, the measured observables and the interval's largest kick
+    deviation."""
+    import bench
+    shape = (128, 128, 128)
+    N = int(np.prod(shape))
+    ph = dict(bench.PHYS)
+    gp = P.Params(**ph)
+    op = orc.Params(J=ph["J"], H=ph["H"], D=ph["D"], e=ph["e"], lam=ph["lam"], T=ph["T"],
+                    dt=ph["dt"], Dt=ph["Dt"], precession=True)
+    assert orc.steps_per_interval(op) == 10
+    lat = P.Lattice(shape, precision=prec, init="random", seed=0)
+    bench.configure_lattice(lat, prec, shape)
+    g = orc.geom(shape)
+    prev = np_state(lat)
+    lat.kick_norm_dev(reset=True)
+    for q in range(2):
+        with pytest.warns(P.ApplicabilityWarning):  # h_max dt = 1.24 > 0.25 (the workload's own)
+            tr = lat.run(gp, first_pulse=q, n_pulses=1, obs_every=1)
+        cur = np_state(lat)
+        want, otr, odev = orc.run(g, op, prev, seed=0, first_pulse=q, n_pulses=1, obs_every=1)
+        err = float(np.max(np.abs(cur - want)))
+        assert err < TOL[prec], (q, err)
+        gdev = lat.kick_norm_dev(reset=True)
+        # | |s'| - 1 | moves by at most sqrt(3) times the largest component error
+        assert abs(gdev - odev) <= 2 * TOL[prec], (q, gdev, odev)
+        o = orc.observables(g, op, cur)
+        for k in ("E_total", "E_exch", "E_zeeman", "E_anis"):
+            assert tr[0][k] == pytest.approx(o[k], rel=1e-12, abs=1e-13 * N), (q, k)
+        np.testing.assert_allclose(tr[0]["m"], o["m"], rtol=1e-12, atol=1e-15)
+        assert tr[0]["max_norm_dev"] == pytest.approx(o["max_norm_dev"], rel=1e-12, abs=1e-16)
+        prev = cur
+    lat.close()
+
+
 def test_max_size_sampled(P):
     """A lattice just under the 2^31 - 1 site limit and ragged in x and y
     (1023 x 1025 x 2047 = 2,146,433,025 sites, 25.8 GB per fp32 state copy)

@@ -294,6 +294,33 @@ typedef struct {
 lll_status lll_escape_times(const lll_escape_params* p, int64_t n_runs, int64_t max_pulses,
                             double* times_dev, void* hip_stream);
 
+/* ---------------------------------------------------------- no-alloc --- */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * observables of lll_observables for a state the caller holds, without a
+ * handle and without allocating.  Lx, Ly, Lz, bc, prec describe the lattice
+ * as for lll_init_lattice; params supplies J, H, D, e, D_site and e_site
+ * (the rest is ignored); sx, sy, sz are the caller's device arrays of N
+ * elements of the precision (read only).  out_dev: caller-owned device array
+ * of 8 doubles receiving {E_total, E_exch, E_zeeman, E_anis, m_x, m_y, m_z,
+ * max_norm_dev} (the lll_obs order), bit for bit what lll_observables reports
+ * for the same state.  Work is enqueued on hip_stream (NULL = default
+ * stream); the call does not synchronise, so it does not check the result
+ * for NaN or Inf (the caller reads out_dev).  The call allocates nothing:
+ * the kernels use a fixed 139,520-byte device array of the library (the
+ * replica descriptor, its block table and at most 2048 blocks of partials;
+ * every lattice size maps onto that many blocks), one copy per device, held
+ * until the process ends, set up on the first call on each device.  Every
+ * call on a device shares that device's array, so calls that overlap on one
+ * device (different streams, or different host threads) race; calls on one
+ * stream run one after another.  Errors (nothing enqueued): LLL_EINVAL for
+ * NULL pointers, sizes < 1 or beyond 2^31 - 1 sites, invalid parameters;
+ * LLL_EDEVICE when the device array cannot be located or a launch fails. */
+lll_status lll_observables_noalloc(int32_t Lx, int32_t Ly, int32_t Lz, lll_bc bc,
+                                   lll_precision prec, const lll_params* params, const void* sx,
+                                   const void* sy, const void* sz, double* out_dev,
+                                   void* hip_stream);
+
 /* ---------------------------------------------------------------- misc --- */
 /* Philox4x32-10 words for counters (i0 + j, c1, c2, c3), j < n, key = seed,
  * into the device array out_dev[4*n] (enqueued on hip_stream). */

@@ -128,6 +128,8 @@ def lib():
     L.lll_batch_destroy.restype = None
     L.lll_philox4x32_10.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32, C.c_uint32,
                                     C.c_uint32, _P, _P]
+    L.lll_observables_noalloc.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                          pp, _P, _P, _P, _P, _P]
     L.lll_last_error.restype = C.c_char_p
     L.lll_version.restype = C.c_char_p
     _lib = L
@@ -191,6 +193,14 @@ def lll_run(h, params: lll_params, first_pulse: int, n_pulses: int, T_per_pulse=
                        int(obs_every), tr if nm > 0 else None)
     _check(st, "lll_run")
     return [tr[i].as_dict() for i in range(nm)]
+
+
+def lll_observables_noalloc(Lx, Ly, Lz, bc, prec, params: lll_params, sx, sy, sz, out_dev,
+                            stream):
+    """Observables of a caller-held state into the device array out_dev[8]
+    without allocating (no synchronisation; see include/lll.h)."""
+    return _check(lib().lll_observables_noalloc(Lx, Ly, Lz, bc, prec, C.byref(params), sx, sy, sz,
+                                                out_dev, stream), "lll_observables_noalloc")
 
 
 def lll_destroy(h):

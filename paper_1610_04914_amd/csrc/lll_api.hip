@@ -682,6 +682,44 @@ static int64_t checked_sites(int32_t Lx, int32_t Ly, int32_t Lz) {
     return n > 0x7FFFFFFFLL ? -1 : n;
 }
 
+// Parameter checks and the descriptor of a lone lattice for the
+// allocation-free observables (lll_noalloc.hip).
+lll_status noalloc_error(lll_status s, const char* msg, int code) {
+    return code ? set_err(s, "%s (%d)", msg, code) : set_err(s, "%s", msg);
+}
+
+lll_status noalloc_describe(int32_t Lx, int32_t Ly, int32_t Lz, lll_bc bc, const lll_params* p,
+                            RepDev* R, int* anis) {
+    if (!p) return set_err(LLL_EINVAL, "params is NULL");
+    if (Lx < 1 || Ly < 1 || Lz < 1) return set_err(LLL_EINVAL, "lattice sizes must be >= 1");
+    if (checked_sites(Lx, Ly, Lz) < 0) return set_err(LLL_EINVAL, "at most 2^31-1 sites");
+    if (bc != LLL_BC_PERIODIC && bc != LLL_BC_FREE) return set_err(LLL_EINVAL, "bad boundary");
+    Phys ph{};
+    ph.J = p->J;
+    for (int c = 0; c < 3; ++c) {
+        ph.H[c] = p->H[c];
+        ph.e[c] = p->e[c];
+    }
+    ph.D = p->D;
+    ph.lambda = p->lambda;
+    ph.T = p->T;
+    ph.D_site = p->D_site;
+    ph.e_site = p->e_site;
+    lll_status s = check_phys(ph);
+    if (s != LLL_OK) return s;
+    if (p->D_site && !p->e_site) return set_err(LLL_EINVAL, "D_site needs e_site");
+    memset(R, 0, sizeof *R);
+    R->Lx = Lx;
+    R->Ly = Ly;
+    R->Lz = Lz;
+    R->bc = bc;
+    const double dt = (p->dt > 0 && is_fin(p->dt)) ? p->dt : 1.0;
+    const double Dt = (p->Dt > 0 && is_fin(p->Dt)) ? p->Dt : dt;
+    fill_physics(*R, ph, dt, Dt, p->precession ? 1 : 0, p->seed, p->replica);
+    *anis = anis_mode_of(ph);
+    return LLL_OK;
+}
+
 extern "C" lll_status lll_init_lattice(int32_t Lx, int32_t Ly, int32_t Lz, lll_bc bc,
                                        lll_precision prec, lll_init mode, const double dir[3],
                                        uint64_t seed, void* sx, void* sy, void* sz,

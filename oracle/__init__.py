@@ -133,7 +133,7 @@ def lib():
                               dp, C.POINTER(Obs)]
         L.orc_run.restype = C.c_double
         L.orc_adjoint.argtypes = [G, P, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, dp, dp,
-                                  C.c_double, dp, dp, dp, dp, dp, dp]
+                                  C.c_double, dp, dp, dp, dp, dp, dp, dp]
         L.orc_adjoint.restype = C.c_int
         L.orc_escape_time.argtypes = [C.c_double] * 6 + [C.c_int32, C.c_int32, C.c_uint64,
                                                           C.c_uint32, C.c_uint32, C.c_int64]
@@ -299,8 +299,9 @@ def run(g: Geom, p: Params, s, seed: int, r: int = 0, first_pulse: int = 0, n_pu
 
 
 def adjoint(g: Geom, p: Params, s0, seed: int, r: int = 0, first_pulse: int = 0,
-            n_pulses: int = 1, T_per_pulse=None, wE: float = 1.0, wm=(0.0, 0.0, 0.0)):
-    """Loss L = wE*E(s_T) + wm.m(s_T) and its gradients (dict)."""
+            n_pulses: int = 1, T_per_pulse=None, wE: float = 1.0, wm=(0.0, 0.0, 0.0), cot=None):
+    """Loss L = <cot, s_T> + wE*E(s_T) + wm.m(s_T) and its gradients (dict);
+    cot: optional (3, N) cotangent of the final state."""
     N = nsites(g)
     s0 = _state(s0, N)
     pc = p.c()
@@ -313,9 +314,11 @@ def adjoint(g: Geom, p: Params, s0, seed: int, r: int = 0, first_pulse: int = 0,
     Tp = None
     if T_per_pulse is not None:
         Tp = np.ascontiguousarray(T_per_pulse, dtype=np.float64)
+    ct = _state(cot, N) if cot is not None else None
     rc = lib().orc_adjoint(C.byref(g), C.byref(pc), C.c_uint64(seed), r, C.c_uint64(first_pulse),
                            int(n_pulses), _dp(Tp) if Tp is not None else None, _dp(s0), float(wE),
-                           _dp(wm_a), _dp(loss), _dp(gs0), _dp(gH), _dp(gJ), _dp(gD))
+                           _dp(wm_a), _dp(ct) if ct is not None else None, _dp(loss), _dp(gs0),
+                           _dp(gH), _dp(gJ), _dp(gD))
     if rc != 0:
         raise ValueError(f"orc_adjoint failed: {rc}")
     return {"loss": float(loss[0]), "g_s0": gs0, "g_H": gH, "g_J": float(gJ[0]),

@@ -519,7 +519,9 @@ double orc_run(const orc_geom* g, const orc_params* p, uint64_t seed, uint32_t r
 
 /* ------------------------------------------------------------------------ */
 /* Discrete adjoint (reverse mode) of orc_run for                            */
-/*   L = wE * E(s_T) + wm . m(s_T),   m = sum_i s_i / N,                     */
+/*   L = <c, s_T> + wE * E(s_T) + wm . m(s_T),   m = sum_i s_i / N,          */
+/* where c is an optional cotangent of the final state (the gradient, with   */
+/* respect to s_T, of whatever loss the caller computes from s_T itself),    */
 /* with respect to the initial state s_0 and the parameters H (3), J and D   */
 /* (per-site D_i when D_site is given, else the uniform D).  The kicks are    */
 /* fixed by the seed and do not depend on the parameters.                    */
@@ -604,12 +606,13 @@ static void rhs_vjp(const orc_geom* g, const orc_params* p, const double* y, con
     free(q);
 }
 
-/* Loss and its gradients.  g_s0 [3N] (may be NULL), g_H[3], g_J[1], g_D [N]
- * when D_site is given else [1].  Returns ORC_OK or an error. */
+/* Loss and its gradients.  cot: [3N] cotangent c of s_T, or NULL for c = 0.
+ * g_s0 [3N] (may be NULL), g_H[3], g_J[1], g_D [N] when D_site is given else
+ * [1].  Returns ORC_OK or an error. */
 int orc_adjoint(const orc_geom* g, const orc_params* p, uint64_t seed, uint32_t r,
                 uint64_t first_pulse, int64_t n_pulses, const double* T_per_pulse,
-                const double* s0, double wE, const double wm[3], double* loss, double* g_s0,
-                double g_H[3], double* g_J, double* g_D)
+                const double* s0, double wE, const double wm[3], const double* cot,
+                double* loss, double* g_s0, double g_H[3], double* g_J, double* g_D)
 {
     int64_t n = orc_steps_per_interval(p);
     if (n < 1) return ORC_EINVAL;
@@ -643,11 +646,15 @@ int orc_adjoint(const orc_geom* g, const orc_params* p, uint64_t seed, uint32_t 
     orc_obs o;
     orc_observables(g, p, sT, &o);
     *loss = wE * o.E_total + wm[0] * o.m[0] + wm[1] * o.m[1] + wm[2] * o.m[2];
+    if (cot)
+        for (int64_t a = 0; a < M; ++a) *loss += cot[a] * sT[a];
     double* sbar = (double*)calloc((size_t)M, sizeof(double));
     double* h = (double*)malloc(sizeof(double) * M);
     orc_heff(g, p, sT, h);
     for (int c = 0; c < 3; ++c)
         for (int64_t i = 0; i < N; ++i) sbar[c * N + i] = -wE * h[c * N + i] + wm[c] / (double)N;
+    if (cot)
+        for (int64_t a = 0; a < M; ++a) sbar[a] += cot[a];
     g_H[0] = g_H[1] = g_H[2] = 0.0;
     *g_J = 0.0;
     int64_t nD = p->D_site ? N : 1;

@@ -67,8 +67,9 @@ int main(void)
                 p.precession = site;  /* both equations */
                 (void)orc_run(&g, &p, 5, 2, 0, 4, Tp, 1, t, o);
                 double wm[3] = {0.0, 0.0, 1.0}, loss, gH[3], gJ, gDu;
-                int st = orc_adjoint(&g, &p, 5, 2, 0, 2, NULL, s, 1.0, wm, &loss, gs, gH, &gJ,
-                                     site ? gD : &gDu);
+                /* with and without a final-state cotangent (h serves as one) */
+                int st = orc_adjoint(&g, &p, 5, 2, 0, 2, NULL, s, 1.0, wm, site ? h : NULL, &loss,
+                                     gs, gH, &gJ, site ? gD : &gDu);
                 bad |= st != ORC_OK;
                 bad |= !finite_all(t, 3 * N) || !finite_all(gs, 3 * N) || !finite_all(gH, 3);
                 bad |= !finite_all(e3, 3) || !isfinite(loss) || !isfinite(gJ);

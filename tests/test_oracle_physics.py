@@ -441,3 +441,58 @@ def test_adjoint_uniform_D(orc):
     eps = 1e-6
     fd = (L(0.1 + eps) - L(0.1 - eps)) / (2 * eps)
     assert abs(fd - res["g_D"]) < 1e-6 * max(1, abs(fd))
+
+
+@pytest.mark.parametrize("precession", [True, False])
+def test_adjoint_with_final_state_cotangent(orc, precession):
+    """A loss that the caller computes from s_T itself enters the adjoint as
+    its cotangent c = dL/ds_T.  For L = <c, s_T> + m_z(s_T) with a fixed
+    random c, the gradients w.r.t. s_0, H, J and D_i agree with central finite
+    differences of the forward run, and c alone (wE = 0, wm = 0) is linear:
+    the gradients of c1 + c2 are the sums of those of c1 and c2."""
+    shape = (3, 2, 3)
+    N = 18
+    g = orc.geom(shape, "free")
+    D_site, e_site = inputs.site_anisotropy(N, 31)
+    s0 = inputs.unit_spins(N, 32)
+    c = inputs.rng(33).standard_normal((3, N))
+    base = dict(J=0.9, H=(0.1, 0.0, -0.3), lam=0.04, T=0.6, dt=0.1, Dt=0.3, precession=precession)
+    kw = dict(seed=7, r=1, first_pulse=3, n_pulses=2)
+    p = orc.Params(D_site=D_site, e_site=e_site, **base)
+    res = orc.adjoint(g, p, s0, wE=0.0, wm=(0.0, 0.0, 1.0), cot=c, **kw)
+
+    def L(**over):
+        b = dict(base)
+        for k in ("H", "J"):
+            if k in over:
+                b[k] = over[k]
+        pp = orc.Params(D_site=over.get("D", D_site), e_site=e_site, **b)
+        sT, _, _ = orc.run(g, pp, over.get("s", s0), **kw)
+        return float(np.sum(c * sT)) + orc.observables(g, pp, sT)["m"][2]
+
+    assert res["loss"] == pytest.approx(L(), rel=1e-13)
+    eps = 1e-6
+    for comp in range(3):
+        Hp = list(base["H"]); Hp[comp] += eps
+        Hm = list(base["H"]); Hm[comp] -= eps
+        fd = (L(H=tuple(Hp)) - L(H=tuple(Hm))) / (2 * eps)
+        assert abs(fd - res["g_H"][comp]) < 1e-6 * max(1, abs(fd))
+    fd = (L(J=0.9 + eps) - L(J=0.9 - eps)) / (2 * eps)
+    assert abs(fd - res["g_J"]) < 1e-6 * max(1, abs(fd))
+    for i in (0, 9, 17):
+        dp = D_site.copy(); dp[i] += eps
+        dm = D_site.copy(); dm[i] -= eps
+        fd = (L(D=dp) - L(D=dm)) / (2 * eps)
+        assert abs(fd - res["g_D"][i]) < 1e-6 * max(1, abs(fd))
+    for seed in (34, 35):
+        v = inputs.unit_spins(N, seed)
+        fd = (L(s=s0 + eps * v) - L(s=s0 - eps * v)) / (2 * eps)
+        assert abs(fd - np.sum(res["g_s0"] * v)) < 1e-6 * max(1, abs(fd))
+    # linearity in the cotangent
+    c2 = inputs.rng(36).standard_normal((3, N))
+    r1 = orc.adjoint(g, p, s0, wE=0.0, cot=c, **kw)
+    r2 = orc.adjoint(g, p, s0, wE=0.0, cot=c2, **kw)
+    r12 = orc.adjoint(g, p, s0, wE=0.0, cot=c + c2, **kw)
+    np.testing.assert_allclose(r12["g_s0"], r1["g_s0"] + r2["g_s0"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(r12["g_D"], r1["g_D"] + r2["g_D"], rtol=1e-10, atol=1e-12)
+    assert r12["g_J"] == pytest.approx(r1["g_J"] + r2["g_J"], rel=1e-10, abs=1e-12)

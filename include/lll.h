@@ -209,14 +209,49 @@ lll_status lll_step_variant_info(lll_precision prec, int32_t variant, int32_t* o
 lll_status lll_autotune(lll_lattice* lat, const lll_params* params, const char* cache_path,
                         int32_t* chosen_variant, int32_t* chosen_bz);
 
-/* Discrete adjoint (reverse mode) of lll_run from the current state (the
- * state is left unchanged) for L = wE * E(s_T) + wm . m(s_T).  The forward
- * pass stores a checkpoint every ckpt_every RK4 steps; the backward pass
- * recomputes each checkpoint block.  Kicks are fixed by the seed.
- * Outputs: *loss; g_H[3], *g_J (host); g_D: host double[1] = dL/dD when
- * params->D_site is NULL, else a device fp64 array [N] of dL/dD_i;
- * g_s0 (optional): device array [3*N] of the lattice precision = dL/ds_0.
- * Synchronises. */
+/* Discrete adjoint (reverse mode) of lll_run.  The paper has no adjoint;
+ * this differentiates its schedule (Eq. (7): n1 RK4 steps, the kick of
+ * Eqs. (5)-(6), n2 steps, per interval) with the kicks held fixed by the seed,
+ * for a loss L(s_T) of the final state plus the energy terms below.
+ *
+ * lll_adjoint_forward: runs n_pulses intervals from the current state exactly
+ * as lll_run does (same kernels, same bits, no measurements; the kicks fold
+ * into the lattice's kick-deviation maximum) and records a tape: the state
+ * before every ckpt_every-th operation (one RK4 step or one kick) and the
+ * final state s_T, which is also left in the lattice.  The tape keeps a copy
+ * of params; params->D_site / e_site must stay valid until the tape is
+ * destroyed.  Only LLL_RK4.  On success *tape receives the handle.
+ *
+ * lll_adjoint_backward: gradients of
+ *     L = <cot, s_T> + wE * E(s_T) + wm . m(s_T)
+ * with respect to the initial state and the parameters.  cot (optional,
+ * NULL = 0) is a device array [3*N] of the lattice precision (x block, y
+ * block, z block): the cotangent dL/ds_T of whatever loss the caller computes
+ * from s_T itself.  Each call recomputes every checkpoint block, so a tape
+ * can be reversed any number of times.  Outputs: *loss (may be NULL) =
+ * wE E(s_T) + wm . m(s_T) (the caller's own term is not included); g_H[3],
+ * *g_J (host); g_D: host double[1] = dL/dD when the tape's D_site is NULL,
+ * else a device fp64 array [N] of dL/dD_i; g_s0 (optional): device array
+ * [3*N] of the lattice precision = dL/ds_0.  Synchronises the lattice's
+ * stream.  The lattice's state and kick maximum are not touched.
+ * LLL_EINVAL when the tape's lattice has been destroyed.
+ *
+ * lll_tape_destroy: frees the tape (its checkpoint buffer is handed back to
+ * the lattice and reused by its next forward).  Tapes may be destroyed
+ * before or after their lattice.
+ *
+ * lll_adjoint: forward, backward with cot = NULL, and the initial state
+ * restored, in one call (the lattice's state and kick maximum are left as
+ * they were).
+ *
+ * Work buffers of the backward pass (4 ckpt_every + 11 states) stay with the
+ * lattice and are reused. */
+typedef struct lll_tape lll_tape;
+lll_status lll_adjoint_forward(lll_lattice* lat, const lll_params* params, uint64_t first_pulse,
+                               int64_t n_pulses, int32_t ckpt_every, lll_tape** tape);
+lll_status lll_adjoint_backward(lll_tape* tape, const void* cot, double wE, const double wm[3],
+                                double* loss, double* g_H, double* g_J, void* g_D, void* g_s0);
+void lll_tape_destroy(lll_tape* tape);
 lll_status lll_adjoint(lll_lattice* lat, const lll_params* params, uint64_t first_pulse,
                        int64_t n_pulses, int32_t ckpt_every, double wE, const double wm[3],
                        double* loss, double* g_H, double* g_J, void* g_D, void* g_s0);

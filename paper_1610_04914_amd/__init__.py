@@ -115,6 +115,12 @@ def lib():
     L.lll_adjoint.argtypes = [_P, pp, C.c_uint64, C.c_int64, C.c_int32, C.c_double,
                               C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(C.c_double), _P, _P]
+    L.lll_adjoint_forward.argtypes = [_P, pp, C.c_uint64, C.c_int64, C.c_int32, C.POINTER(_P)]
+    L.lll_adjoint_backward.argtypes = [_P, _P, C.c_double, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), _P, _P]
+    L.lll_tape_destroy.argtypes = [_P]
+    L.lll_tape_destroy.restype = None
     L.lll_destroy.argtypes = [_P]
     L.lll_destroy.restype = None
     L.lll_batch_create.argtypes = [C.c_int32, C.POINTER(lll_replica_desc), C.c_int32, C.c_double,
@@ -397,67 +403,174 @@ class Lattice:
         return {"loss": loss.value, "g_H": list(gH), "g_J": gJ.value,
                 "g_D": gD if gD is not None else gDh.value, "g_s0": gs0}
 
+    def adjoint_forward(self, p: Params, first_pulse: int, n_pulses: int,
+                        ckpt_every: int = 10) -> "Tape":
+        """Runs n_pulses intervals like run() (the state advances to s_T) and
+        records the tape of lll_adjoint_forward for a later backward()."""
+        pc = self._pc(p)
+        h = _P()
+        _check(lib().lll_adjoint_forward(self.h, C.byref(pc), C.c_uint64(first_pulse),
+                                         int(n_pulses), int(ckpt_every), C.byref(h)),
+               "lll_adjoint_forward")
+        return Tape(self, h, p)
 
-def _loss_function():
+
+class Tape:
+    """Tape of one forward pass (lll_adjoint_forward); backward() may be
+    called any number of times.  Keeps the Params it was recorded with (and
+    so the per-site tensors the library reads)."""
+
+    def __init__(self, lat: Lattice, h, p: Params):
+        self.lat = lat
+        self.h = h
+        self.p = p
+
+    def backward(self, cot=None, wE: float = 0.0, wm=(0.0, 0.0, 0.0), want_g_s0: bool = True):
+        """Gradients of L = <cot, s_T> + wE E(s_T) + wm.m(s_T): cot is an
+        optional (3, N) device tensor of the lattice dtype.  Returns a dict
+        with loss (the energy terms only), g_H, g_J, g_D (per site when the
+        tape has D_site) and g_s0 (a (3, N) tensor, when asked for)."""
+        torch = _torch()
+        lat = self.lat
+        cp = None
+        if cot is not None:
+            if (not cot.is_cuda or cot.dtype != lat.dtype or tuple(cot.shape) != (3, lat.N)
+                    or not cot.is_contiguous()):
+                raise ValueError("cot must be a contiguous (3, N) device tensor of the lattice dtype")
+            cp = C.c_void_p(cot.data_ptr())
+        loss = C.c_double()
+        gH = (C.c_double * 3)()
+        gJ = C.c_double()
+        wmc = (C.c_double * 3)(*[float(v) for v in wm])
+        if self.p.D_site is not None:
+            gD = torch.zeros(lat.N, dtype=torch.float64, device="cuda")
+            gDp = C.c_void_p(gD.data_ptr())
+        else:
+            gDh = C.c_double()
+            gD = None
+            gDp = C.cast(C.byref(gDh), C.c_void_p)
+        gs0 = torch.zeros((3, lat.N), dtype=lat.dtype, device="cuda") if want_g_s0 else None
+        _check(lib().lll_adjoint_backward(self.h, cp, float(wE), wmc, C.byref(loss), gH,
+                                          C.byref(gJ), gDp,
+                                          C.c_void_p(gs0.data_ptr()) if gs0 is not None else None),
+               "lll_adjoint_backward")
+        return {"loss": loss.value, "g_H": list(gH), "g_J": gJ.value,
+                "g_D": gD if gD is not None else gDh.value, "g_s0": gs0}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lll_tape_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _params_with(base: Params, H, J, D, dtype) -> Params:
+    from dataclasses import replace
+    p = replace(base, H=tuple(float(v) for v in H.detach().cpu().tolist()),
+                J=float(J.detach().cpu()))
+    if D.dim() == 0:
+        return replace(p, D=float(D.detach().cpu()), D_site=None)
+    return replace(p, D_site=D.detach().to(dtype).contiguous())
+
+
+def _param_grads(r, H, J, D, scale=None):
+    torch = _torch()
+    gH = torch.tensor(r["g_H"], dtype=H.dtype, device=H.device)
+    gJ = torch.tensor(r["g_J"], dtype=J.dtype, device=J.device)
+    if D.dim() == 0:
+        gD = torch.tensor(r["g_D"], dtype=D.dtype, device=D.device)
+    else:
+        gD = r["g_D"].to(dtype=D.dtype, device=D.device)
+    if scale is not None:
+        gH, gJ, gD = gH * scale, gJ * scale, gD * scale
+    return gH, gJ, gD
+
+
+def _autograd_functions():
     torch = _torch()
 
-    class LLLLoss(torch.autograd.Function):
-        """L = wE * E(s_T) + wm . m(s_T) after n_pulses intervals of the schedule
-        from the lattice's current state (which the forward advances to s_T).
-        Differentiable in H (3-vector), J (scalar) and D (scalar uniform D, or
-        an (N,) device tensor of per-site D_i of the lattice dtype).  The
-        backward runs the library's adjoint from the saved initial state with a
-        checkpoint every ckpt_every RK4 steps."""
+    class LLLRun(torch.autograd.Function):
+        """s_T = n_pulses intervals of the schedule from s_0 on lattice `lat`,
+        differentiable in s_0 ((3, N), the lattice dtype), H (3-vector), J
+        (scalar) and D (scalar uniform D, or an (N,) tensor of per-site D_i
+        with base.e_site).  The forward records a tape (checkpoints every
+        ckpt_every operations); the backward hands the incoming gradient of
+        s_T to the library's reverse pass as its cotangent."""
 
         @staticmethod
-        def forward(ctx, H, J, D, lat, base, first_pulse, n_pulses, ckpt_every, wE, wm):
-            from dataclasses import replace
-            p = replace(base, H=tuple(float(v) for v in H.detach().cpu().tolist()),
-                        J=float(J.detach().cpu()))
-            if D.dim() == 0:
-                p = replace(p, D=float(D.detach().cpu()), D_site=None)
-            else:
-                p = replace(p, D_site=D.detach().to(lat.dtype).contiguous())
-            s0 = lat.state.clone()
-            lat.run(p, first_pulse=first_pulse, n_pulses=n_pulses)
+        def forward(ctx, s0, H, J, D, lat, base, first_pulse, n_pulses, ckpt_every):
+            p = _params_with(base, H, J, D, lat.dtype)
+            lat.state.copy_(s0.detach())
+            ctx.tape = lat.adjoint_forward(p, first_pulse, n_pulses, ckpt_every)
+            ctx.save_for_backward(H, J, D)
+            return lat.state.clone()
+
+        @staticmethod
+        def backward(ctx, g_sT):
+            H, J, D = ctx.saved_tensors
+            tape = ctx.tape
+            r = tape.backward(cot=g_sT.to(tape.lat.dtype).contiguous(), want_g_s0=True)
+            gH, gJ, gD = _param_grads(r, H, J, D)
+            return (r["g_s0"], gH, gJ, gD, None, None, None, None, None)
+
+    class LLLLoss(torch.autograd.Function):
+        """L = wE * E(s_T) + wm . m(s_T) after n_pulses intervals from s_0, the
+        lattice's state before the call (the forward advances it to s_T).
+        Differentiable in s_0, H, J and D as LLLRun.  The forward records the
+        tape; the backward only recomputes and reverses."""
+
+        @staticmethod
+        def forward(ctx, s0, H, J, D, lat, base, first_pulse, n_pulses, ckpt_every, wE, wm):
+            p = _params_with(base, H, J, D, lat.dtype)
+            lat.state.copy_(s0.detach())
+            ctx.tape = lat.adjoint_forward(p, first_pulse, n_pulses, ckpt_every)
             o = lat.observables(p)
             val = wE * o["E_total"] + sum(w * m for w, m in zip(wm, o["m"]))
-            ctx.lat_meta = (lat.shape, lat.bc, lat.precision)
-            ctx.args = (p, first_pulse, n_pulses, ckpt_every, wE, tuple(wm))
-            ctx.D_shape = D.shape
-            ctx.save_for_backward(s0, H, J, D)
+            ctx.w = (float(wE), tuple(float(v) for v in wm))
+            ctx.save_for_backward(H, J, D)
             return torch.tensor(val, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gout):
-            s0, H, J, D = ctx.saved_tensors
-            shape, bc, prec = ctx.lat_meta
-            p, first_pulse, n_pulses, ckpt_every, wE, wm = ctx.args
-            tmp = Lattice(shape, bc=bc, precision=prec, state=s0.clone())
-            r = tmp.adjoint(p, first_pulse, n_pulses, ckpt_every=ckpt_every, wE=wE, wm=wm)
-            tmp.close()
+            H, J, D = ctx.saved_tensors
+            wE, wm = ctx.w
+            r = ctx.tape.backward(wE=wE, wm=wm, want_g_s0=True)
             g = float(gout)
-            gH = torch.tensor(r["g_H"], dtype=H.dtype, device=H.device) * g
-            gJ = torch.tensor(r["g_J"], dtype=J.dtype, device=J.device) * g
-            if D.dim() == 0:
-                gD = torch.tensor(r["g_D"], dtype=D.dtype, device=D.device) * g
-            else:
-                gD = r["g_D"].to(dtype=D.dtype, device=D.device) * g
-            return gH, gJ, gD, None, None, None, None, None, None, None
+            gH, gJ, gD = _param_grads(r, H, J, D, g)
+            return (r["g_s0"] * g, gH, gJ, gD, None, None, None, None, None, None, None)
 
-    return LLLLoss
+    return LLLRun, LLLLoss
 
 
-_LLLLoss = None
+_FUNCS = None
+
+
+def _funcs():
+    global _FUNCS
+    if _FUNCS is None:
+        _FUNCS = _autograd_functions()
+    return _FUNCS
+
+
+def lll_run_diff(s0, H, J, D, lat: "Lattice", base: Params, first_pulse: int, n_pulses: int,
+                 ckpt_every: int = 10):
+    """Differentiable final state of a pulse-noise run (see LLLRun): any torch
+    loss of the returned s_T backpropagates to s0, H, J and D."""
+    return _funcs()[0].apply(s0, H, J, D, lat, base, first_pulse, n_pulses, ckpt_every)
 
 
 def lll_loss(H, J, D, lat: "Lattice", base: Params, first_pulse: int, n_pulses: int,
-             ckpt_every: int = 10, wE: float = 1.0, wm=(0.0, 0.0, 1.0)):
-    """Differentiable loss of a pulse-noise run (see LLLLoss)."""
-    global _LLLLoss
-    if _LLLLoss is None:
-        _LLLLoss = _loss_function()
-    return _LLLLoss.apply(H, J, D, lat, base, first_pulse, n_pulses, ckpt_every, wE, wm)
+             ckpt_every: int = 10, wE: float = 1.0, wm=(0.0, 0.0, 1.0), s0=None):
+    """Differentiable loss wE E(s_T) + wm.m(s_T) of a pulse-noise run from s0
+    (default: the lattice's current state; see LLLLoss)."""
+    if s0 is None:
+        s0 = lat.state.clone()
+    return _funcs()[1].apply(s0, H, J, D, lat, base, first_pulse, n_pulses, ckpt_every, wE, wm)
 
 
 def step_variant_info(precision: str, variant: int):

@@ -97,13 +97,14 @@ __device__ __forceinline__ void block_sum5(double v[5], double* part) {
     if (threadIdx.x < 5) part[(int64_t)blockIdx.x * 5 + threadIdx.x] += red[threadIdx.x][0];
 }
 
-// Cotangent of the loss L = wE E(s) + wm . m(s) at the final state:
-// sbar_i = -wE h_i + wm / N, with the direct parameter terms
-// dE/dH = -sum s_i, dE/dJ = -sum_bonds s_i.s_j, dE/dD_i = -(s_i.e_i)^2.
+// Cotangent of the loss L = <c, s> + wE E(s) + wm . m(s) at the final state:
+// sbar_i = c_i - wE h_i + wm / N (c = 0 when cot.x is null), with the direct
+// parameter terms dE/dH = -sum s_i, dE/dJ = -sum_bonds s_i.s_j,
+// dE/dD_i = -(s_i.e_i)^2.
 template <typename T, int ANIS>
 __global__ void __launch_bounds__(kAdjBlock)
-    adj_loss_kernel(const RepDev* reps, const int32_t* blk_rep, State s, State sbar, double wE,
-                    double wm0, double wm1, double wm2, double* gD, double* part) {
+    adj_loss_kernel(const RepDev* reps, const int32_t* blk_rep, State s, State cot, State sbar,
+                    double wE, double wm0, double wm1, double wm2, double* gD, double* part) {
     SiteA c;
     double v[5] = {0, 0, 0, 0, 0};
     if (adj_site(reps, blk_rep, c)) {
@@ -121,9 +122,15 @@ __global__ void __launch_bounds__(kAdjBlock)
         const double h1 = R.J * n1 + R.H[1] + 2.0 * D * se * e1;
         const double h2 = R.J * n2 + R.H[2] + 2.0 * D * se * e2;
         const double N = (double)R.Lx * R.Ly * R.Lz;
-        static_cast<T*>(sbar.x)[c.gi] = (T)(-wE * h0 + wm0 / N);
-        static_cast<T*>(sbar.y)[c.gi] = (T)(-wE * h1 + wm1 / N);
-        static_cast<T*>(sbar.z)[c.gi] = (T)(-wE * h2 + wm2 / N);
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+        if (cot.x) {
+            c0 = (double)static_cast<const T*>(cot.x)[c.gi];
+            c1 = (double)static_cast<const T*>(cot.y)[c.gi];
+            c2 = (double)static_cast<const T*>(cot.z)[c.gi];
+        }
+        static_cast<T*>(sbar.x)[c.gi] = (T)(c0 + (-wE * h0 + wm0 / N));
+        static_cast<T*>(sbar.y)[c.gi] = (T)(c1 + (-wE * h1 + wm1 / N));
+        static_cast<T*>(sbar.z)[c.gi] = (T)(c2 + (-wE * h2 + wm2 / N));
         // bonds along +x, +y, +z of this site
         const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
         const bool pbc = R.bc == 0;
@@ -377,21 +384,21 @@ __global__ void __launch_bounds__(kAdjBlock)
 // ------------------------------------------------------------ launchers ----
 template <typename T>
 static hipError_t loss_t(int anis, const RepDev* reps, const int32_t* blk, int nblk, State s,
-                         State sbar, double wE, const double wm[3], double* gD, double* part,
-                         hipStream_t st) {
+                         State cot, State sbar, double wE, const double wm[3], double* gD,
+                         double* part, hipStream_t st) {
     switch (anis) {
-        case ANIS_NONE: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, s, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
-        case ANIS_SITE: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, s, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
-        default: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, s, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
+        case ANIS_NONE: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, s, cot, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
+        case ANIS_SITE: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, s, cot, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
+        default: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, s, cot, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_adj_loss(int prec, int anis, const RepDev* reps, const int32_t* blk, int nblk,
-                           State s, State sbar, double wE, const double wm[3], double* gD,
-                           double* part, hipStream_t st) {
-    return prec == 0 ? loss_t<double>(anis, reps, blk, nblk, s, sbar, wE, wm, gD, part, st)
-                     : loss_t<float>(anis, reps, blk, nblk, s, sbar, wE, wm, gD, part, st);
+                           State s, State cot, State sbar, double wE, const double wm[3],
+                           double* gD, double* part, hipStream_t st) {
+    return prec == 0 ? loss_t<double>(anis, reps, blk, nblk, s, cot, sbar, wE, wm, gD, part, st)
+                     : loss_t<float>(anis, reps, blk, nblk, s, cot, sbar, wE, wm, gD, part, st);
 }
 
 hipError_t launch_adj_finish(const double* part, int nblk, double* acc, hipStream_t st) {

@@ -614,6 +614,8 @@ lll_status norm_warning(double dev) {
 }  // namespace
 
 // ------------------------------------------------------------- lattice ----
+struct lll_tape;
+
 struct lll_lattice {
     Engine E;
     int32_t Lx, Ly, Lz, bc;
@@ -623,6 +625,18 @@ struct lll_lattice {
     int precession = 1;
     uint64_t seed = 0;
     uint32_t replica = 0;
+    // adjoint: live tapes, a checkpoint buffer handed back by a destroyed
+    // tape, and the backward pass's work buffers (grow-only, reused)
+    std::vector<lll_tape*> tapes;
+    void* ck_pool = nullptr;
+    size_t ck_pool_bytes = 0;
+    void* adj_bb = nullptr;
+    size_t adj_bb_bytes = 0;
+    void* adj_sc = nullptr;
+    size_t adj_sc_bytes = 0;
+    void* adj_small = nullptr;
+    size_t adj_small_bytes = 0;
+    ~lll_lattice();
 };
 
 static lll_status lattice_params(lll_lattice* L, const lll_params* p, bool need_schedule) {
@@ -1143,11 +1157,17 @@ extern "C" lll_status lll_autotune(lll_lattice* L, const lll_params* p, const ch
 }
 
 // ------------------------------------------------------------- adjoint ----
-// Reverse mode of the schedule: the forward pass stores the state before
-// every ckpt_every-th operation (an operation is one RK4 step or one kick);
-// the backward pass walks the checkpoint blocks in reverse, recomputes each
-// block while keeping the stage inputs of every step, and runs the reverse
-// stages and kick reverses.
+// Reverse mode of the schedule, split into a forward call that records a
+// tape and a backward call that takes the cotangent of the final state.  The
+// forward pass advances the lattice like lll_run and stores the state before
+// every ckpt_every-th operation (an operation is one RK4 step or one kick)
+// and the final state; the backward pass walks the checkpoint blocks in
+// reverse, recomputes each block while keeping the stage inputs of every
+// step, and runs the reverse stages and kick reverses.  Work buffers of the
+// backward pass live in the lattice's engine and are reused by later calls;
+// a destroyed tape hands its checkpoint buffer back to the lattice, so a
+// forward/backward cycle of the same length allocates nothing after the
+// first.
 namespace {
 struct TmpAlloc {
     std::vector<void*> ptrs;
@@ -1166,99 +1186,187 @@ State state_at(void* base, size_t comp_bytes, int64_t idx) {
     char* b = (char*)base + (size_t)idx * 3 * comp_bytes;
     return State{b, b + comp_bytes, b + 2 * comp_bytes};
 }
+
+// Grow-only device buffer.
+lll_status ensure_buf(void** p, size_t* have, size_t bytes) {
+    if (*p && *have >= bytes) return LLL_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return set_err(LLL_ENOMEM, "hipMalloc of %zu bytes failed (adjoint buffers)", bytes);
+    }
+    *have = bytes;
+    return LLL_OK;
+}
 }  // namespace
 
-extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t first_pulse,
-                                  int64_t n_pulses, int32_t ckpt_every, double wE,
-                                  const double wm[3], double* loss, double* g_H, double* g_J,
-                                  void* g_D, void* g_s0) {
-    if (!L || !loss || !g_H || !g_J || !g_D || !wm) return set_err(LLL_EINVAL, "NULL argument");
-    if (n_pulses < 0 || ckpt_every < 1) return set_err(LLL_EINVAL, "bad n_pulses or ckpt_every");
-    if (p && p->integrator != LLL_RK4)
-        return set_err(LLL_EUNSUPPORTED, "the adjoint is implemented for LLL_RK4 only");
-    lll_status s = lattice_params(L, p, true);
-    if (s != LLL_OK) return s;
+struct lll_tape {
+    lll_lattice* lat = nullptr;
+    lll_params p{};
+    std::vector<int8_t> op;        // 0 = RK4 step, 1 = kick
+    std::vector<uint64_t> opk;     // pulse index of each operation
+    int64_t K = 1, nblocks = 0;
+    void* ck = nullptr;            // [nblocks + 1][3][N]: checkpoints, then s_T
+    size_t ck_bytes = 0;
+};
+
+lll_lattice::~lll_lattice() {
+    // tapes may outlive their lattice: their backward calls then fail cleanly,
+    // and destroying them still frees their checkpoints
+    for (lll_tape* T : tapes) T->lat = nullptr;
+    for (void* p : {ck_pool, adj_bb, adj_sc, adj_small})
+        if (p) (void)hipFree(p);
+}
+
+// Adjoint work buffers of an engine: block buffer (4K + 1 states), ten
+// scratch states, parameter partials, their sum, the loss observables and
+// the kick maxima of recomputed kicks (kept apart from the lattice's own).
+static lll_status ensure_adj_work(lll_lattice* L, int64_t K) {
     Engine& E = L->E;
-    if ((s = settle(E)) != LLL_OK) return s;
+    const size_t cb = (size_t)E.nsites * E.esz;
+    lll_status s;
+    if ((s = ensure_buf(&L->adj_bb, &L->adj_bb_bytes, 3 * cb * (size_t)(4 * K + 1))) != LLL_OK)
+        return s;
+    if ((s = ensure_buf(&L->adj_sc, &L->adj_sc_bytes, 3 * cb * 10)) != LLL_OK) return s;
+    const size_t small = sizeof(double) * (5 * (size_t)E.nblk + 5 + 8) +
+                         sizeof(unsigned long long) * kKickSlots;
+    return ensure_buf(&L->adj_small, &L->adj_small_bytes, small);
+}
+
+static void tape_release_ck(lll_tape* T) {
+    if (!T->ck) return;
+    lll_lattice* L = T->lat;
+    if (L && (!L->ck_pool || L->ck_pool_bytes < T->ck_bytes)) {
+        if (L->ck_pool) (void)hipFree(L->ck_pool);
+        L->ck_pool = T->ck;
+        L->ck_pool_bytes = T->ck_bytes;
+    } else {
+        (void)hipFree(T->ck);
+    }
+    T->ck = nullptr;
+    T->ck_bytes = 0;
+}
+
+// Forward pass with checkpoints; kicks fold their deviation into kd.
+static lll_status tape_forward(lll_lattice* L, lll_tape* T, uint64_t first_pulse,
+                               int64_t n_pulses, unsigned long long* kd) {
+    Engine& E = L->E;
     int64_t n;
-    if ((s = steps_per_interval(p->dt, p->Dt, &n)) != LLL_OK) return s;
+    lll_status s = steps_per_interval(T->p.dt, T->p.Dt, &n);
+    if (s != LLL_OK) return s;
     const int64_t n1 = n / 2, n2 = n - n1;
-    std::vector<int> op;          // 0 = RK4 step, 1 = kick
-    std::vector<uint64_t> opk;
+    T->op.clear();
+    T->opk.clear();
     for (int64_t q = 0; q < n_pulses; ++q) {
         const uint64_t k = first_pulse + (uint64_t)q;
-        for (int64_t a = 0; a < n1; ++a) { op.push_back(0); opk.push_back(k); }
-        op.push_back(1); opk.push_back(k);
-        for (int64_t a = 0; a < n2; ++a) { op.push_back(0); opk.push_back(k); }
+        for (int64_t a = 0; a < n1; ++a) { T->op.push_back(0); T->opk.push_back(k); }
+        T->op.push_back(1); T->opk.push_back(k);
+        for (int64_t a = 0; a < n2; ++a) { T->op.push_back(0); T->opk.push_back(k); }
     }
-    const int64_t nops = (int64_t)op.size();
-    const int64_t K = ckpt_every;
-    const int64_t nblocks = (nops + K - 1) / K;
+    const int64_t nops = (int64_t)T->op.size();
+    T->nblocks = (nops + T->K - 1) / T->K;
     const size_t cb = (size_t)E.nsites * E.esz;
-    TmpAlloc T;
-    void* ck = T.get(3 * cb * (size_t)std::max<int64_t>(nblocks, 1));
-    void* bb = T.get(3 * cb * (size_t)(4 * K + 1));
-    void* sc = T.get(3 * cb * 10);
-    double* part = (double*)T.get(sizeof(double) * 5 * E.nblk);
-    double* acc5 = (double*)T.get(sizeof(double) * 5);
-    if (!ck || !bb || !sc || !part || !acc5) return set_err(LLL_ENOMEM, "adjoint buffers");
-    State cur = state_at(sc, cb, 0), nxt = state_at(sc, cb, 1), accb = state_at(sc, cb, 2);
-    State sbar = state_at(sc, cb, 3), xbar = state_at(sc, cb, 4), kb = state_at(sc, cb, 5);
-    const State q2[2] = {state_at(sc, cb, 6), state_at(sc, cb, 8)};
-    const State loc2[2] = {state_at(sc, cb, 7), state_at(sc, cb, 9)};
+    const size_t need = 3 * cb * (size_t)(T->nblocks + 1);
+    if (L->ck_pool && L->ck_pool_bytes >= need) {
+        T->ck = L->ck_pool;
+        T->ck_bytes = L->ck_pool_bytes;
+        L->ck_pool = nullptr;
+        L->ck_pool_bytes = 0;
+    } else {
+        if (hipMalloc(&T->ck, need) != hipSuccess) {
+            T->ck = nullptr;
+            return set_err(LLL_ENOMEM, "hipMalloc of %zu bytes failed (adjoint checkpoints)", need);
+        }
+        T->ck_bytes = need;
+    }
+    if ((s = settle(E)) != LLL_OK) return s;
+    E.carried = false;
+    const int pr = E.prec;
+    for (int64_t j = 0; j < nops;) {
+        if (j % T->K == 0)
+            HIP_TRY(launch_copy(pr, state_at(T->ck, cb, j / T->K), cur_state(E), E.nsites, E.st));
+        if (T->op[j] == 1) {
+            HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), T->opk[j], -1.0, kd,
+                                E.st));
+            ++j;
+            continue;
+        }
+        // consecutive steps up to the next kick or checkpoint
+        int64_t e = j + 1;
+        while (e < nops && T->op[e] == 0 && e % T->K != 0) ++e;
+        if ((s = do_steps(E, e - j, false, 0, -1.0)) != LLL_OK) return s;
+        j = e;
+    }
+    if ((s = settle(E)) != LLL_OK) return s;
+    HIP_TRY(launch_copy(pr, state_at(T->ck, cb, T->nblocks), E.s, E.nsites, E.st));
+    return LLL_OK;
+}
+
+// Backward pass for L = <cot, s_T> + wE E(s_T) + wm . m(s_T).
+static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const double wm[3],
+                                double* loss, double* g_H, double* g_J, void* g_D, void* g_s0) {
+    lll_lattice* L = T->lat;
+    if (!L) return set_err(LLL_EINVAL, "the tape's lattice has been destroyed");
+    lll_status s = lattice_params(L, &T->p, true);
+    if (s != LLL_OK) return s;
+    Engine& E = L->E;
+    if ((s = ensure_adj_work(L, T->K)) != LLL_OK) return s;
+    const size_t cb = (size_t)E.nsites * E.esz;
+    const int64_t nops = (int64_t)T->op.size();
+    const int64_t K = T->K;
+    double* part = (double*)L->adj_small;
+    double* acc5 = part + 5 * (size_t)E.nblk;
+    double* res8 = acc5 + 5;
+    unsigned long long* kd = (unsigned long long*)(res8 + 8);
+    State cur = state_at(L->adj_sc, cb, 0), nxt = state_at(L->adj_sc, cb, 1);
+    State accb = state_at(L->adj_sc, cb, 2);
+    State sbar = state_at(L->adj_sc, cb, 3), xbar = state_at(L->adj_sc, cb, 4);
+    State kb = state_at(L->adj_sc, cb, 5);
+    const State q2[2] = {state_at(L->adj_sc, cb, 6), state_at(L->adj_sc, cb, 8)};
+    const State loc2[2] = {state_at(L->adj_sc, cb, 7), state_at(L->adj_sc, cb, 9)};
+    (void)cur;
+    (void)nxt;
     // block buffer: slot j holds x, y2, y3, y4 of operation j of the block
-    auto slot = [&](int64_t j, int c) { return state_at(bb, cb, 4 * j + c); };
-    const bool site = p->D_site != nullptr;
+    auto slot = [&](int64_t j, int c) { return state_at(L->adj_bb, cb, 4 * j + c); };
+    const bool site = T->p.D_site != nullptr;
     double* gD = site ? (double*)g_D : nullptr;
-    HIP_TRY(hipMemsetAsync(acc5, 0, sizeof(double) * 5, E.st));
-    HIP_TRY(hipMemsetAsync(part, 0, sizeof(double) * 5 * E.nblk, E.st));
+    HIP_TRY(hipMemsetAsync(L->adj_small, 0, sizeof(double) * (5 * (size_t)E.nblk + 5), E.st));
     if (site) HIP_TRY(hipMemsetAsync(gD, 0, sizeof(double) * E.nsites, E.st));
     const int pr = E.prec, pc = E.precession, an = E.anis;
-    // forward with checkpoints
-    HIP_TRY(launch_copy(pr, cur, E.s, E.nsites, E.st));
-    for (int64_t j = 0; j < nops; ++j) {
-        if (j % K == 0) HIP_TRY(launch_copy(pr, state_at(ck, cb, j / K), cur, E.nsites, E.st));
-        if (op[j] == 0) {
-            HIP_TRY(launch_rk4_stages(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, cur, slot(0, 1),
-                                      slot(0, 2), slot(0, 3), accb, nxt, E.st));
-            std::swap(cur, nxt);
-        } else {
-            HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, cur, opk[j], -1.0, E.d_kickdev,
-                                E.st));
-        }
-    }
-    // loss and its cotangent
-    HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, cur, E.d_partials, E.d_result,
-                       E.d_accum, 0, E.st));
-    HIP_TRY(launch_adj_loss(pr, an, E.dreps, E.d_blk_rep, E.nblk, cur, sbar, wE, wm, gD, part,
+    const State sT = state_at(T->ck, cb, T->nblocks);
+    const State cs = cot ? State{const_cast<void*>(cot), (char*)cot + cb, (char*)cot + 2 * cb}
+                         : State{};
+    HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, sT, E.d_partials, res8, nullptr,
+                       0, E.st));
+    HIP_TRY(launch_adj_loss(pr, an, E.dreps, E.d_blk_rep, E.nblk, sT, cs, sbar, wE, wm, gD, part,
                             E.st));
-    // backward
-    const double dt = p->dt;
-    for (int64_t b = nblocks - 1; b >= 0; --b) {
+    const double dt = T->p.dt;
+    for (int64_t b = T->nblocks - 1; b >= 0; --b) {
         const int64_t j0 = b * K, j1 = std::min(j0 + K, nops);
-        HIP_TRY(launch_copy(pr, slot(0, 0), state_at(ck, cb, b), E.nsites, E.st));
+        HIP_TRY(launch_copy(pr, slot(0, 0), state_at(T->ck, cb, b), E.nsites, E.st));
         for (int64_t j = j0; j < j1; ++j) {
             const int64_t sl = j - j0;
             State nx = slot(sl + 1, 0);
-            if (op[j] == 0) {
+            if (T->op[j] == 0) {
                 HIP_TRY(launch_rk4_stages(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, slot(sl, 0),
                                           slot(sl, 1), slot(sl, 2), slot(sl, 3), accb, nx, E.st));
             } else {
                 HIP_TRY(launch_copy(pr, nx, slot(sl, 0), E.nsites, E.st));
-                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, opk[j], -1.0, E.d_kickdev,
-                                    E.st));
+                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, T->opk[j], -1.0, kd, E.st));
             }
         }
         for (int64_t j = j1 - 1; j >= j0; --j) {
             const int64_t sl = j - j0;
-            if (op[j] == 0) {
+            if (T->op[j] == 0) {
                 const State y[4] = {slot(sl, 0), slot(sl, 1), slot(sl, 2), slot(sl, 3)};
                 HIP_TRY(launch_adj_step(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, y, dt, sbar, xbar,
                                         kb, q2, loc2, gD, part, E.st));
                 std::swap(sbar, xbar);
             } else {
-                HIP_TRY(launch_adj_kick(pr, E.dreps, E.d_blk_rep, E.nblk, slot(sl, 0), sbar, opk[j],
-                                        -1.0, E.st));
+                HIP_TRY(launch_adj_kick(pr, E.dreps, E.d_blk_rep, E.nblk, slot(sl, 0), sbar,
+                                        T->opk[j], -1.0, E.st));
             }
         }
     }
@@ -1269,9 +1377,9 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
     }
     double h5[5], r[8];
     HIP_TRY(hipMemcpyAsync(h5, acc5, sizeof h5, hipMemcpyDeviceToHost, E.st));
-    HIP_TRY(hipMemcpyAsync(r, E.d_result, sizeof r, hipMemcpyDeviceToHost, E.st));
+    HIP_TRY(hipMemcpyAsync(r, res8, sizeof r, hipMemcpyDeviceToHost, E.st));
     HIP_TRY(hipStreamSynchronize(E.st));
-    *loss = wE * r[0] + wm[0] * r[4] + wm[1] * r[5] + wm[2] * r[6];
+    if (loss) *loss = wE * r[0] + wm[0] * r[4] + wm[1] * r[5] + wm[2] * r[6];
     g_H[0] = h5[0];
     g_H[1] = h5[1];
     g_H[2] = h5[2];
@@ -1279,6 +1387,84 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
     if (!site) *(double*)g_D = h5[4];
     if (!obs_finite(r)) return set_err(LLL_ENONFINITE, "forward state became NaN or Inf");
     return LLL_OK;
+}
+
+static lll_status tape_check_args(lll_lattice* L, const lll_params* p, int64_t n_pulses,
+                                  int32_t ckpt_every) {
+    if (!L || !p) return set_err(LLL_EINVAL, "NULL argument");
+    if (n_pulses < 0 || ckpt_every < 1) return set_err(LLL_EINVAL, "bad n_pulses or ckpt_every");
+    if (p->integrator != LLL_RK4)
+        return set_err(LLL_EUNSUPPORTED, "the adjoint is implemented for LLL_RK4 only");
+    return lattice_params(L, p, true);
+}
+
+extern "C" lll_status lll_adjoint_forward(lll_lattice* L, const lll_params* p, uint64_t first_pulse,
+                                          int64_t n_pulses, int32_t ckpt_every, lll_tape** out) {
+    if (!out) return set_err(LLL_EINVAL, "out is NULL");
+    *out = nullptr;
+    lll_status s = tape_check_args(L, p, n_pulses, ckpt_every);
+    if (s != LLL_OK) return s;
+    lll_tape* T = new lll_tape();
+    T->lat = L;
+    T->p = *p;
+    T->K = ckpt_every;
+    if ((s = tape_forward(L, T, first_pulse, n_pulses, L->E.d_kickdev)) != LLL_OK) {
+        tape_release_ck(T);
+        delete T;
+        return s;
+    }
+    L->tapes.push_back(T);
+    *out = T;
+    return LLL_OK;
+}
+
+extern "C" lll_status lll_adjoint_backward(lll_tape* T, const void* cot, double wE,
+                                           const double wm[3], double* loss, double* g_H,
+                                           double* g_J, void* g_D, void* g_s0) {
+    if (!T || !wm || !g_H || !g_J || !g_D) return set_err(LLL_EINVAL, "NULL argument");
+    return tape_backward(T, cot, wE, wm, loss, g_H, g_J, g_D, g_s0);
+}
+
+extern "C" void lll_tape_destroy(lll_tape* T) {
+    if (!T) return;
+    lll_lattice* L = T->lat;
+    if (L) {
+        if (L->E.st) (void)hipStreamSynchronize(L->E.st);
+        else (void)hipDeviceSynchronize();
+        auto& v = L->tapes;
+        v.erase(std::remove(v.begin(), v.end(), T), v.end());
+    }
+    tape_release_ck(T);
+    delete T;
+}
+
+extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t first_pulse,
+                                  int64_t n_pulses, int32_t ckpt_every, double wE,
+                                  const double wm[3], double* loss, double* g_H, double* g_J,
+                                  void* g_D, void* g_s0) {
+    if (!loss || !g_H || !g_J || !g_D || !wm) return set_err(LLL_EINVAL, "NULL argument");
+    lll_status s = tape_check_args(L, p, n_pulses, ckpt_every);
+    if (s != LLL_OK) return s;
+    if ((s = ensure_adj_work(L, ckpt_every)) != LLL_OK) return s;
+    lll_tape T;
+    T.lat = L;
+    T.p = *p;
+    T.K = ckpt_every;
+    // the forward's kicks go to the scratch maxima: the state is restored
+    unsigned long long* kd =
+        (unsigned long long*)((double*)L->adj_small + 5 * (size_t)L->E.nblk + 5 + 8);
+    s = tape_forward(L, &T, first_pulse, n_pulses, kd);
+    if (s == LLL_OK) s = tape_backward(&T, nullptr, wE, wm, loss, g_H, g_J, g_D, g_s0);
+    Engine& E = L->E;
+    if (T.ck) {
+        const hipError_t e = launch_copy(E.prec, E.s, state_at(T.ck, (size_t)E.nsites * E.esz, 0),
+                                         E.nsites, E.st);
+        E.cur = 0;
+        (void)hipStreamSynchronize(E.st);
+        if (s == LLL_OK && e != hipSuccess) s = set_err(LLL_EDEVICE, "state restore failed");
+    }
+    tape_release_ck(&T);
+    return s;
 }
 
 // --------------------------------------------------------------- batch -----

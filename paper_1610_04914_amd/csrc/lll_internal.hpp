@@ -142,9 +142,10 @@ hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* r
 // part: [nblk][5] fp64 running partials {Hbar x3, Jbar, Dbar} (zeroed by the
 // caller, added to by every pass, reduced in block order into acc[5] by
 // launch_adj_finish); gD: per-site fp64 Dbar_i (per-site anisotropy) or unused.
+// cot: cotangent of s added to the loss's own (null pointers: none).
 hipError_t launch_adj_loss(int prec, int anis, const RepDev* reps, const int32_t* blk, int nblk,
-                           State s, State sbar, double wE, const double wm[3], double* gD,
-                           double* part, hipStream_t st);
+                           State s, State cot, State sbar, double wE, const double wm[3],
+                           double* gD, double* part, hipStream_t st);
 // q[2], loc[2]: two scratch pairs used alternately.
 hipError_t launch_adj_step(int prec, int precession, int anis, const RepDev* reps,
                            const int32_t* blk, int nblk, const State y[4], double dt, State sbar,

@@ -119,15 +119,110 @@ def test_autograd_function(P):
     J = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
     Dt_ = _dev(D, "fp64").requires_grad_(True)
     lat = P.Lattice(shape, precision="fp64", state=_dev(s0, "fp64"))
-    loss = P.lll_loss(H, J, Dt_, lat, base, first_pulse=0, n_pulses=2, ckpt_every=3)
+    s0t = _dev(s0, "fp64").requires_grad_(True)
+    loss = P.lll_loss(H, J, Dt_, lat, base, first_pulse=0, n_pulses=2, ckpt_every=3, s0=s0t)
     loss.backward()
     want = orc.adjoint(orc.geom(shape), orc.Params(J=1.0, H=(0, 0, 0.2), lam=0.01, T=0.5, dt=0.1,
                                                    Dt=0.4, D_site=D, e_site=e),
                        s0, seed=2, n_pulses=2, wE=1.0, wm=(0, 0, 1))
-    assert float(loss) == pytest.approx(want["loss"], rel=1e-12)
+    assert float(loss.detach()) == pytest.approx(want["loss"], rel=1e-12)
+    assert _rel(s0t.grad.cpu().numpy(), want["g_s0"]) < 1e-10
     assert _rel(H.grad.numpy(), want["g_H"]) < 1e-10
     assert _rel(float(J.grad), want["g_J"]) < 1e-10
     assert _rel(Dt_.grad.cpu().numpy(), want["g_D"]) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("site", [True, False])
+def test_autograd_torch_loss_of_final_state(P, prec, site):
+    """A torch loss of s_T (linear plus quadratic in s_T) backpropagated through
+    lll_run_diff: the gradients w.r.t. s_0, H, J and D equal the oracle's FP64
+    adjoint whose cotangent is that loss's gradient at the oracle's own s_T."""
+    shape = (7, 4, 5)
+    N = int(np.prod(shape))
+    bc = "free" if site else "periodic"
+    s0n = _rounded(inputs.near_ordered_spins(N, 51), prec)
+    Dn, en = inputs.site_anisotropy(N, 52)
+    Dn, en = _rounded(Dn, prec), _rounded(en, prec)
+    W = inputs.rng(53).standard_normal((3, N))
+    kw = dict(J=1.05, H=(0.02, -0.05, 0.15), lam=0.03, T=0.6, dt=0.1, Dt=0.4)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    H = torch.tensor(kw["H"], dtype=torch.float64, requires_grad=True)
+    J = torch.tensor(kw["J"], dtype=torch.float64, requires_grad=True)
+    if site:
+        D = _dev(Dn, prec).requires_grad_(True)
+        base = P.Params(lam=kw["lam"], T=kw["T"], dt=kw["dt"], Dt=kw["Dt"], seed=8,
+                        e_site=_dev(en, prec))
+        op = orc.Params(D_site=Dn, e_site=en, **kw)
+    else:
+        D = torch.tensor(0.07, dtype=torch.float64, requires_grad=True)
+        base = P.Params(lam=kw["lam"], T=kw["T"], dt=kw["dt"], Dt=kw["Dt"], seed=8, e=(0.0, 1.0, 1.0))
+        op = orc.Params(D=0.07, e=(0.0, 1.0, 1.0), **kw)
+    s0 = _dev(s0n, prec).requires_grad_(True)
+    lat = P.Lattice(shape, bc=bc, precision=prec, state=_dev(s0n, prec))
+    Wt = _dev(W, prec)
+    sT = P.lll_run_diff(s0, H, J, D, lat, base, first_pulse=2, n_pulses=3, ckpt_every=4)
+    loss = (Wt * sT).sum() + 0.5 * (sT[2] ** 2).sum()
+    loss.backward()
+    g = orc.geom(shape, bc)
+    sTo, _, _ = orc.run(g, op, s0n, seed=8, first_pulse=2, n_pulses=3)
+    cot = W.copy()
+    cot[2] += sTo[2]
+    want = orc.adjoint(g, op, s0n, seed=8, first_pulse=2, n_pulses=3, wE=0.0, cot=cot)
+    tol = GTOL[prec]
+    torch.cuda.synchronize()
+    want_loss = float(np.sum(W * sTo) + 0.5 * np.sum(sTo[2] ** 2))
+    assert float(loss.detach()) == pytest.approx(want_loss, rel=1e-12 if prec == "fp64" else 1e-5)
+    assert _rel(s0.grad.double().cpu().numpy(), want["g_s0"]) < tol
+    assert _rel(H.grad.numpy(), want["g_H"]) < tol
+    assert _rel(float(J.grad), want["g_J"]) < tol
+    gD = D.grad.double().cpu().numpy() if site else float(D.grad)
+    assert _rel(gD, want["g_D"]) < tol
+    lat.close()
+
+
+def test_tape_reuse_and_lifetime(P):
+    """One tape reversed twice gives the same gradients bit for bit; the
+    backward leaves the lattice's state and kick maximum alone; the forward
+    equals lll_run bit for bit and folds its kicks into the maximum; a tape
+    whose lattice is gone reports an error instead of touching freed memory;
+    a second forward of the same length reuses the checkpoint buffer."""
+    shape = (9, 6, 5)
+    N = 270
+    s0 = inputs.near_ordered_spins(N, 61)
+    p = P.Params(J=1.0, H=(0, 0, 0.1), D=0.05, lam=0.02, T=0.8, dt=0.1, Dt=0.4, seed=3)
+    ref = P.Lattice(shape, precision="fp64", state=_dev(s0, "fp64"))
+    ref.kick_norm_dev(reset=True)
+    ref.run(p, first_pulse=5, n_pulses=2)
+    lat = P.Lattice(shape, precision="fp64", state=_dev(s0, "fp64"))
+    lat.kick_norm_dev(reset=True)
+    tape = lat.adjoint_forward(p, 5, 2, ckpt_every=3)
+    torch.cuda.synchronize()
+    assert torch.equal(lat.state, ref.state)
+    kmax = lat.kick_norm_dev()
+    assert kmax == ref.kick_norm_dev() and kmax > 0
+    sT = lat.state.clone()
+    cot = _dev(inputs.rng(62).standard_normal((3, N)), "fp64")
+    r1 = tape.backward(cot=cot, wE=1.0, wm=(0, 0, 1))
+    r2 = tape.backward(cot=cot, wE=1.0, wm=(0, 0, 1))
+    assert r1["g_H"] == r2["g_H"] and r1["g_J"] == r2["g_J"] and r1["g_D"] == r2["g_D"]
+    assert torch.equal(r1["g_s0"], r2["g_s0"])
+    assert torch.equal(lat.state, sT)
+    assert lat.kick_norm_dev() == kmax
+    # the one-call adjoint from s0 agrees with the tape without a cotangent
+    lat2 = P.Lattice(shape, precision="fp64", state=_dev(s0, "fp64"))
+    one = lat2.adjoint(p, 5, 2, ckpt_every=3, wE=1.0, wm=(0, 0, 1), want_g_s0=True)
+    r3 = tape.backward(wE=1.0, wm=(0, 0, 1))
+    assert one["g_H"] == r3["g_H"] and one["g_J"] == r3["g_J"] and one["loss"] == r3["loss"]
+    assert torch.equal(one["g_s0"], r3["g_s0"])
+    tape.close()
+    tape2 = lat.adjoint_forward(p, 7, 2, ckpt_every=3)
+    lat.close()
+    with pytest.raises(P.LLLError):
+        tape2.backward(wE=1.0)
+    tape2.close()
+    ref.close()
+    lat2.close()
 
 
 @pytest.fixture(scope="module")

@@ -47,6 +47,7 @@ ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "spin-steps/s (RK4, 128^3 sc, fp32) + % HBM roofline; batched & adjoint ratios"
 TUNE_CACHE = os.path.join(ROOT, "paper_1610_04914_amd", "tune_cache.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rk4_fused_128c_fp32_traffic.md")
+TRAFFIC_FILE_256 = os.path.join(ROOT, "profiles", "rk4_fused_256c_fp32_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1610_04914_amd", "csrc", f)
                   for f in ("kern_fused.hpp", "lll_device.hpp")]
 
@@ -69,37 +70,53 @@ def configure_lattice(lat, prec: str, shape, p=None) -> tuple:
     return lat.autotune(p, cache_path=TUNE_CACHE)
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused step from the committed rocprofv3
-    counter summary, or None when it is missing or was taken on other kernel
-    sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path: str = None):
+    """Bytes per launch of the fused step between L2 and the memory fabric
+    (calibrated FETCH_SIZE + WRITE_SIZE) from a committed rocprofv3 counter
+    summary, or None when it is missing or was taken on other kernel sources.
+    At 128^3 the reads include what the 256 MB Infinity Cache serves; at 256^3
+    (two 201 MB state copies) they are close to HBM traffic."""
+    path = path or TRAFFIC_FILE
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     mh = re.search(r"kernel_sources_hash:\s*(\w+)", txt)
-    mb = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    mb = re.search(r"l2_fabric_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     if not mh or not mb or mh.group(1) != kernel_hash():
         return None
     return float(mb.group(1))
 
 
-def cpu_baseline(steps: int = 4):
-    """The FP64 oracle (single-threaded C) on a bounded sample of the same
-    workload: `steps` RK4 steps of the 128^3 lattice."""
+def cpu_baseline(steps: int = 10, steps_all_cores: int = 40):
+    """The FP64 oracle on a bounded sample of the same workload (RK4 steps of
+    the 128^3 lattice): its OpenMP build on every core this process may use
+    (the reported value), and the single-threaded build the tests use."""
     import numpy as np
     import oracle as orc
     g = orc.geom(SHAPE)
     p = orc.Params(J=PHYS["J"], H=PHYS["H"], D=PHYS["D"], e=PHYS["e"], lam=PHYS["lam"], T=PHYS["T"],
                    dt=PHYS["dt"], Dt=PHYS["Dt"], precession=True)
     s = orc.init_random_sphere(g, 0)
+    N = int(np.prod(SHAPE))
+    host = host_info()
+    # the OpenMP runtime reads this when it starts; a value already set is kept
+    os.environ.setdefault("OMP_NUM_THREADS", str(host["affinity_cores"] or 1))
+    cores = orc.threads(all_cores=True)
     orc.step(g, p, s, 1)  # warm-up (page in)
     t0 = time.perf_counter()
     orc.step(g, p, s, steps)
-    el = time.perf_counter() - t0
-    N = int(np.prod(SHAPE))
-    return {"value": N * steps / el, "unit": "spin-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} RK4 steps of the 128^3 fp64 lattice ({el:.1f} s, one host thread)",
-            "host": host_info()}
+    el1 = time.perf_counter() - t0
+    orc.step(g, p, s, 1, all_cores=True)
+    t0 = time.perf_counter()
+    orc.step(g, p, s, steps_all_cores, all_cores=True)
+    eln = time.perf_counter() - t0
+    return {"value": N * steps_all_cores / eln, "unit": "spin-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps_all_cores} RK4 steps of the 128^3 fp64 lattice ({eln:.1f} s, "
+                      f"OpenMP build on {cores} host threads)",
+            "single_thread": {"value": N * steps / el1, "cores": 1,
+                              "sample": f"{steps} RK4 steps ({el1:.1f} s, one host thread)"},
+            "host": host}
 
 
 def host_info() -> dict:
@@ -129,7 +146,7 @@ def _timed(fn):
     return time.perf_counter() - t0, r
 
 
-def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn: int = 1000):
+def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 5000, burn: int = 1000):
     """Uneven-replica workload: 32 each of 24^3, 48^3, 64^3, T uniform in
     [0.3, 2], lambda log-uniform in [0.005, 0.05], J = 1, H = 0, dt = 0.1,
     Dt = 1.0, random-sphere starts, per-replica noise keys.
@@ -196,33 +213,42 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
         return e / N[:, None], mag
 
     def mean_sem(x):
-        """Mean after burn-in and its standard error from the integrated
-        autocorrelation time (automatic window: the first M >= 5 tau(M))."""
+        """Mean after burn-in and its standard error by blocking (Flyvbjerg and
+        Petersen, J. Chem. Phys. 91, 461 (1989)): the series is averaged in
+        blocks of 1, 2, 4, ... samples, the naive error of the block means is
+        taken at each level, and the largest over the levels that keep at
+        least 16 blocks is used (the plateau, or its conservative side when
+        the correlation time is not much shorter than the run)."""
         x = x[:, burn:]
-        n = x.shape[1]
         means, sems = x.mean(1), np.zeros(x.shape[0])
+        conv = np.zeros(x.shape[0], dtype=bool)
         for r in range(x.shape[0]):
-            d = x[r] - means[r]
-            f = np.fft.rfft(d, 2 * n)
-            acf = np.fft.irfft(f * np.conj(f))[:n]
-            if acf[0] <= 0:
-                continue
-            rho = acf / acf[0]
-            tau = 0.5
-            for M in range(1, n):
-                tau += rho[M]
-                if M >= 5 * tau:
-                    break
-            sems[r] = np.sqrt(acf[0] / n * 2 * max(tau, 0.5) / n)
-        return means, sems
+            b = x[r].copy()
+            errs = []
+            while b.size >= 16:
+                errs.append((float(np.std(b, ddof=1) / np.sqrt(b.size)), b.size))
+                m = b.size // 2
+                b = 0.5 * (b[:2 * m:2] + b[1:2 * m:2])
+            sems[r] = max(e for e, _ in errs)
+            # plateau: the last two levels agree within the statistical error
+            # of the last one, e / sqrt(2 (n_blocks - 1))
+            (e1, _), (e2, n2) = errs[-2], errs[-1]
+            conv[r] = abs(e2 - e1) <= e2 / np.sqrt(2 * (n2 - 1)) or sems[r] == 0.0
+        return means, sems, conv
 
     e32, m32 = series("fp32")
     e64, m64 = series("fp64")
-    zs = {}
+    zs, cv = {}, {}
     for name, a, b in (("E_per_site", e32, e64), ("abs_m", m32, m64)):
-        ma, sa = mean_sem(a)
-        mb, sb = mean_sem(b)
+        ma, sa, ca = mean_sem(a)
+        mb, sb, cb = mean_sem(b)
         zs[name] = (ma - mb) / np.sqrt(sa**2 + sb**2 + 1e-300)
+        cv[name] = ca & cb
+    # For independent normal z, P(|z| < 2) = 0.9545: 96 replicas give 91.6
+    # within 2 sigma with a binomial standard deviation of 2.0.
+    nrep = len(reps)
+    expect2 = 0.9545 * nrep
+    sd2 = math.sqrt(nrep * 0.9545 * 0.0455)
     rate_b = sites * 10 * n_pulses / el_b
     rate_s = sites * 10 * n_seq / el_s
     return {"workload": "96 replicas (32 x 24^3, 48^3, 64^3), fp32 batch vs fp64 single-lattice path",
@@ -232,12 +258,23 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 2000, burn
             "sequential_fp64_spin_steps_per_s": rate_s,
             "speedup": rate_b / rate_s,
             "pulses_timed": {"batch": n_pulses, "sequential": n_seq},
-            "accuracy": {"pulses": n_acc, "burn_in": burn, "replicas": len(reps),
+            "accuracy": {"pulses": n_acc, "burn_in": burn, "replicas": nrep,
+                         "error_bars": "blocking analysis, largest block error with >= 16 blocks",
+                         "expected_within_2sigma": [expect2, sd2],
                          **{k: {"within_2sigma": int(np.sum(np.abs(z) < 2.0)),
                                 "within_3sigma": int(np.sum(np.abs(z) < 3.0)),
                                 "mean_signed_z": float(z.mean()),
-                                "max_abs_z": float(np.abs(z).max())}
-                            for k, z in zs.items()}}}
+                                "max_abs_z": float(np.abs(z).max()),
+                                "blocking_converged": int(cv[k].sum()),
+                                "converged_within_2sigma": int(np.sum(np.abs(z[cv[k]]) < 2.0)),
+                                "converged_expected_within_2sigma": [
+                                    0.9545 * int(cv[k].sum()),
+                                    math.sqrt(int(cv[k].sum()) * 0.9545 * 0.0455)]}
+                            for k, z in zs.items()},
+                         "per_replica_T_lambda_zE_zm_converged": [
+                             [float(r["T"]), float(r["lam"]), float(zs["E_per_site"][i]),
+                              float(zs["abs_m"][i]), int(cv["E_per_site"][i]),
+                              int(cv["abs_m"][i])] for i, r in enumerate(reps)]}}
 
 
 def extra_adjoint():
@@ -480,10 +517,38 @@ def extra_headline_256(n_pulses: int = 100):
     lat.close()
     torch.cuda.synchronize()
     gbs = BYTES_PER_SPIN_STEP["fp32"] * N / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    alg = BYTES_PER_SPIN_STEP["fp32"] * N
+    meas = measured_traffic(TRAFFIC_FILE_256)
     return {"workload": "256^3, headline physics, fp32, obs every interval",
             "spin_steps_per_s": N * n * n_pulses / el, "step_variant": variant, "bz": bz,
             "fused_launch_us": ms * 1e3, "launches_timed": nt,
-            "alg_hbm_gbs": gbs, "alg_hbm_frac": gbs / HBM_PEAK_GBS}
+            "alg_hbm_gbs": gbs, "alg_hbm_frac": gbs / HBM_PEAK_GBS,
+            "alg_bytes_per_launch": alg, "l2_fabric_bytes_per_launch": meas,
+            "measured_over_algorithmic": meas / alg if meas else None}
+
+
+def extra_headline_fp64(n_pulses: int = 300):
+    """The headline workload in fp64 (128^3, the same physics and schedule,
+    observables every interval): rate, and the fused step's mean duration
+    from dispatch events with its algorithmic bandwidth (48 B per spin-step)."""
+    import torch
+    import paper_1610_04914_amd as P
+    p = P.Params(**PHYS)
+    lat = P.Lattice(SHAPE, precision="fp64", init="random", seed=0)
+    variant, bz = configure_lattice(lat, "fp64", SHAPE)
+    n = int(round(PHYS["Dt"] / PHYS["dt"]))
+    lat.run(p, first_pulse=0, n_pulses=50, obs_every=1)
+    lat.kernel_timing_start()
+    el, _ = _timed(lambda: lat.run(p, first_pulse=50, n_pulses=n_pulses, obs_every=1))
+    ms, nt = lat.kernel_timing_stop()
+    N = lat.N
+    lat.close()
+    torch.cuda.synchronize()
+    gbs = BYTES_PER_SPIN_STEP["fp64"] * N / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"workload": "128^3, headline physics, fp64, obs every interval",
+            "spin_steps_per_s": N * n * n_pulses / el, "intervals": n_pulses,
+            "step_variant": variant, "bz": bz, "fused_launch_us": ms * 1e3,
+            "launches_timed": nt, "alg_hbm_gbs": gbs, "alg_hbm_frac": gbs / HBM_PEAK_GBS}
 
 
 def extra_config_16():
@@ -555,6 +620,7 @@ def _progress(name, fn):
 
 
 EXTRAS = {"temperatures": extra_temperatures, "headline_256": extra_headline_256,
+          "headline_fp64": extra_headline_fp64,
           "config_16": extra_config_16, "batched": extra_batched, "adjoint": extra_adjoint,
           "overdamped_256": extra_overdamped, "max_lattice": extra_max_lattice,
           "integrators": extra_integrators,
@@ -571,6 +637,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps-all-cores", type=int, default=40)
     ap.add_argument("--no-extras", dest="extras", action="store_false",
                     help="skip the batched, adjoint and 256^3 overdamped workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -668,6 +735,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / ALU_PEAK_TFLOPS,
                      "traffic": traffic,
+                     "traffic_kind": "L2<->fabric bytes per launch (FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated); at 128^3 reads served by the Infinity "
+                                     "Cache are included (256^3 figure in extras.headline_256)",
                      "kernel": "rk4_fused_kernel",
                      "alg_flops_per_launch": alg_flops,
                      "alg_bytes_per_launch": alg_bytes,
@@ -680,7 +750,7 @@ def main():
         out["extras"] = {"headline_variants": extra_headline_variants(lat, p),
                          **{name: _progress(name, fn) for name, fn in EXTRAS.items()}}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps, args.cpu_steps_all_cores)
     print(json.dumps(out))
 
 

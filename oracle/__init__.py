@@ -22,15 +22,20 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lll_oracle.c")
 _LIB = os.path.join(_HERE, "liblll_oracle.so")
+# the same source built with OpenMP: used only to time the oracle on all host
+# cores (its site loops are independent, so it computes identical results)
+_LIB_OMP = os.path.join(_HERE, "liblll_oracle_omp.so")
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11"]
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no GPU code involved)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (no GPU code involved), single-threaded and,
+    for the all-cores timing, with OpenMP."""
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            tmp = out + ".tmp"
+            subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, out)
     return _LIB
 
 
@@ -96,6 +101,7 @@ class Params:
 
 
 _lib = None
+_lib_omp = None
 
 
 def lib():
@@ -103,43 +109,58 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=True)
-        L = C.CDLL(_LIB)
-        dp = C.POINTER(C.c_double)
-        u32p = C.POINTER(C.c_uint32)
-        G = C.POINTER(Geom)
-        P = C.POINTER(_Params)
-        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        L.orc_philox_stream.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32,
-                                        C.c_uint32, C.c_uint32, u32p]
-        L.orc_u01.argtypes = [C.c_uint32]
-        L.orc_u01.restype = C.c_double
-        L.orc_gauss3.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp]
-        L.orc_init_random_sphere.argtypes = [G, C.c_uint64, C.c_uint32, dp]
-        L.orc_init_direction.argtypes = [G, dp, dp]
-        for nm in ("orc_heff", "orc_rhs"):
-            getattr(L, nm).argtypes = [G, P, dp, dp]
-        L.orc_energy_parts.argtypes = [G, P, dp, dp]
-        for nm in ("orc_step_rk4", "orc_step_heun", "orc_step_rk2mid", "orc_step_rk5b"):
-            getattr(L, nm).argtypes = [G, P, dp, C.c_int64]
-        L.orc_rotate.argtypes = [dp, dp, dp]
-        L.orc_kick.argtypes = [G, P, C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, dp]
-        L.orc_kick.restype = C.c_double
-        L.orc_kick_indexed.argtypes = [G, P, C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, u32p, dp]
-        L.orc_kick_indexed.restype = C.c_double
-        L.orc_observables.argtypes = [G, P, dp, C.POINTER(Obs)]
-        L.orc_steps_per_interval.argtypes = [P]
-        L.orc_steps_per_interval.restype = C.c_int64
-        L.orc_run.argtypes = [G, P, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, dp, C.c_int32,
-                              dp, C.POINTER(Obs)]
-        L.orc_run.restype = C.c_double
-        L.orc_adjoint.argtypes = [G, P, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, dp, dp,
-                                  C.c_double, dp, dp, dp, dp, dp, dp, dp]
-        L.orc_adjoint.restype = C.c_int
-        L.orc_escape_time.argtypes = [C.c_double] * 6 + [C.c_int32, C.c_int32, C.c_uint64,
-                                                          C.c_uint32, C.c_uint32, C.c_int64]
-        L.orc_escape_time.restype = C.c_double
-        _lib = L
+        _lib = _bind(C.CDLL(_LIB))
     return _lib
+
+
+def lib_omp():
+    """The OpenMP build (all-cores timing only; OMP_NUM_THREADS sets its threads)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP):
+            build(force=True)
+        _lib_omp = _bind(C.CDLL(_LIB_OMP))
+    return _lib_omp
+
+
+def _bind(L):
+    """Sets the argument and result types of the oracle's C functions."""
+    L.orc_threads.restype = C.c_int
+    dp = C.POINTER(C.c_double)
+    u32p = C.POINTER(C.c_uint32)
+    G = C.POINTER(Geom)
+    P = C.POINTER(_Params)
+    L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    L.orc_philox_stream.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_uint32,
+                                    C.c_uint32, C.c_uint32, u32p]
+    L.orc_u01.argtypes = [C.c_uint32]
+    L.orc_u01.restype = C.c_double
+    L.orc_gauss3.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp]
+    L.orc_init_random_sphere.argtypes = [G, C.c_uint64, C.c_uint32, dp]
+    L.orc_init_direction.argtypes = [G, dp, dp]
+    for nm in ("orc_heff", "orc_rhs"):
+        getattr(L, nm).argtypes = [G, P, dp, dp]
+    L.orc_energy_parts.argtypes = [G, P, dp, dp]
+    for nm in ("orc_step_rk4", "orc_step_heun", "orc_step_rk2mid", "orc_step_rk5b"):
+        getattr(L, nm).argtypes = [G, P, dp, C.c_int64]
+    L.orc_rotate.argtypes = [dp, dp, dp]
+    L.orc_kick.argtypes = [G, P, C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, dp]
+    L.orc_kick.restype = C.c_double
+    L.orc_kick_indexed.argtypes = [G, P, C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, u32p, dp]
+    L.orc_kick_indexed.restype = C.c_double
+    L.orc_observables.argtypes = [G, P, dp, C.POINTER(Obs)]
+    L.orc_steps_per_interval.argtypes = [P]
+    L.orc_steps_per_interval.restype = C.c_int64
+    L.orc_run.argtypes = [G, P, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, dp, C.c_int32,
+                          dp, C.POINTER(Obs)]
+    L.orc_run.restype = C.c_double
+    L.orc_adjoint.argtypes = [G, P, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, dp, dp,
+                              C.c_double, dp, dp, dp, dp, dp, dp, dp]
+    L.orc_adjoint.restype = C.c_int
+    L.orc_escape_time.argtypes = [C.c_double] * 6 + [C.c_int32, C.c_int32, C.c_uint64,
+                                                      C.c_uint32, C.c_uint32, C.c_int64]
+    L.orc_escape_time.restype = C.c_double
+    return L
 
 
 def _dp(a: np.ndarray):
@@ -227,13 +248,21 @@ def energy_parts(g: Geom, p: Params, s) -> np.ndarray:
     return out
 
 
-def step(g: Geom, p: Params, s, n_steps: int = 1, method: str = "rk4") -> np.ndarray:
+def threads(all_cores: bool = True) -> int:
+    """Threads the oracle's parallel loops use (the OpenMP build's, or 1)."""
+    return int((lib_omp() if all_cores else lib()).orc_threads())
+
+
+def step(g: Geom, p: Params, s, n_steps: int = 1, method: str = "rk4",
+         all_cores: bool = False) -> np.ndarray:
+    """n_steps steps of the integrator; all_cores runs the OpenMP build (the
+    same results, used to time the oracle on every host core)."""
     N = nsites(g)
     s = _state(s, N)
     pc = p.c()
     fn = {"rk4": "orc_step_rk4", "heun": "orc_step_heun", "rk2mid": "orc_step_rk2mid",
           "rk5b": "orc_step_rk5b"}[method]
-    getattr(lib(), fn)(C.byref(g), C.byref(pc), _dp(s), int(n_steps))
+    getattr(lib_omp() if all_cores else lib(), fn)(C.byref(g), C.byref(pc), _dp(s), int(n_steps))
     return s
 
 

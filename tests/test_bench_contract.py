@@ -17,8 +17,21 @@ def test_traffic_is_null_when_kernel_changed(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
     f = tmp_path / "t.md"
-    f.write_text("kernel_sources_hash: deadbeef0000\nhbm_bytes_per_launch: 1.0e8\n")
+    f.write_text("kernel_sources_hash: deadbeef0000\nl2_fabric_bytes_per_launch: 1.0e8\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.measured_traffic() is None
-    f.write_text(f"kernel_sources_hash: {bench.kernel_hash()}\nhbm_bytes_per_launch: 1.0e8\n")
+    f.write_text(f"kernel_sources_hash: {bench.kernel_hash()}\nl2_fabric_bytes_per_launch: 1.0e8\n")
     assert bench.measured_traffic() == 1.0e8
+
+
+def test_oracle_all_cores_build_is_identical():
+    """The OpenMP build that times the oracle on all host cores computes the
+    same states as the single-threaded build the tests use."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import oracle as orc
+    g = orc.geom((12, 10, 9), "free")
+    p = orc.Params(J=1.0, H=(0.0, 0.1, 0.2), D=0.1, e=(1.0, 0.0, 1.0), lam=0.05, T=1.0,
+                   dt=0.1, Dt=0.4)
+    s = orc.init_random_sphere(g, 3)
+    assert np.array_equal(orc.step(g, p, s, 3), orc.step(g, p, s, 3, all_cores=True))

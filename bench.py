@@ -358,9 +358,10 @@ def extra_integrators(n_pulses: int = 50):
     """The headline lattice and physics (128^3 fp32, precession, dt = 0.2,
     Dt = 2) stepped with each integrator of the Appendix: classical RK4 (one
     fused launch per step), RK2 midpoint (two steps per fused launch) and
-    Butcher's RK5 (one launch per stage).  Spin-steps/s over n_pulses
-    intervals with observables, and the mean kernel time of the fused step
-    launches of an even run of steps (RK4: one step, RK2: two steps)."""
+    Butcher's RK5 (two fused launches per step: stages 1-4, stages 5-6).
+    Spin-steps/s over n_pulses intervals with observables, the mean kernel
+    time of the fused step launches of an even run of steps (RK4: one step,
+    RK2: two steps), and each method's time per step relative to RK4's."""
     import torch
     import paper_1610_04914_amd as P
     out = {}
@@ -383,6 +384,9 @@ def extra_integrators(n_pulses: int = 50):
         out[method] = rec
         lat.close()
     torch.cuda.synchronize()
+    for method in ("rk2mid", "rk5b"):
+        out[method]["step_time_vs_rk4"] = (out["rk4"]["spin_steps_per_s"] /
+                                           out[method]["spin_steps_per_s"])
     return out
 
 

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblll.so")
 SOURCES = ["kern_fused_f32.hip", "kern_fused_f64.hip", "kern_fused_rk2_f32.hip",
            "kern_fused_rk2_f64.hip", "lll_api.hip", "kern_basic.hip", "kern_adjoint.hip",
-           "kern_escape.hip", "lll_noalloc.hip"]
+           "kern_escape.hip", "lll_noalloc.hip", "kern_fused_rk5_f32.hip",
+           "kern_fused_rk5_f64.hip"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",

@@ -121,15 +121,34 @@ __device__ __forceinline__ void stage_at(const T* L0, const T* L1, const T* L2, 
     stage_k<T, PREC, ANIS>(c[0], c[1], c[2], nx, ny, nz, C, Di, ex, ey, ez, kx, ky, kz);
 }
 
+// Coefficients of Butcher's six-stage fifth-order method (Appendix): stage
+// inputs Y_{i+1} = x + sum_j a_ij k_j, result x' = x + sum_i b_i k_i.
+template <typename T>
+struct Rk5B {
+    static constexpr T a10 = T(1) / T(4), a20 = T(1) / T(8), a21 = T(1) / T(8);
+    static constexpr T a31 = T(-1) / T(2), a32 = T(1);
+    static constexpr T a40 = T(3) / T(16), a43 = T(9) / T(16);
+    static constexpr T a50 = T(-3) / T(7), a51 = T(2) / T(7), a52 = T(12) / T(7),
+                       a53 = T(-12) / T(7), a54 = T(8) / T(7);
+    static constexpr T b0 = T(7) / T(90), b2 = T(32) / T(90), b3 = T(12) / T(90),
+                       b4 = T(32) / T(90), b5 = T(7) / T(90);
+};
+
 // SCHEME 0: one classical RK4 step.  SCHEME 1: two RK2-midpoint steps, whose
 // four stage evaluations have the same dependency depth (y2 = x + k1/2,
 // x1 = x + k2, y4 = x1 + k3/2, x2 = x1 + k4).  SCHEME 2: one RK2-midpoint step
-// (stages 1 and 2 only; x1 is the output).
+// (stages 1 and 2 only; x1 is the output).  SCHEME 3: the first four stages
+// of Butcher's RK5 (the second launch, rk5_tail_kernel, does stages 5 and 6):
+// Y2 = x + a10 k1, Y3 = P3 + a21 k2 with P3 = x + a20 k1, Y4 = P4 + a32 k3
+// with P4 = x + a31 k2; per point the partial sums P5 = x + a40 k1,
+// Q6 = x + a50 k1 + a51 k2 + a52 k3 (+ a53 k4) and R = x + b0 k1 + b2 k3
+// (+ b3 k4) ride along, and the last stage writes Y5 = P5 + a43 k4 to out,
+// Q6 to out2 and R to out3 (b1 = 0).
 template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, bool KICK, int SCHEME>
 __global__ void __launch_bounds__(NT)
     rk4_fused_kernel(const RepDev* __restrict__ reps, const int4* __restrict__ tiles, State in,
                      State out, int bz_arg, uint64_t kpulse, double sigma_override,
-                     unsigned long long* kickdev) {
+                     unsigned long long* kickdev, State out2, State out3) {
     // Region Rs = the tile grown by 4-s sites in x and y (R0: loaded points).
     constexpr int R0 = (BX + 8) * (BY + 8);
     constexpr int R1 = (BX + 6) * (BY + 6);
@@ -232,6 +251,10 @@ __global__ void __launch_bounds__(NT)
 
     // Register FIFOs indexed by plane mod 4: x, stage inputs y2..y4, RK4 accumulator.
     T X[NI][4][3], Y2[NI][4][3], Y3[NI][4][3], Y4[NI][4][3], A[NI][4][3], XN[NI][3];
+    // SCHEME 3: the partial sums (P3, P4 by plane parity; P5, Q6, R by plane mod 4)
+    constexpr int N5 = SCHEME == 3 ? NI : 1;
+    T P3[N5][2][3], P4[N5][2][3], P5[N5][4][3], Q6[N5][4][3], RR[N5][4][3];
+    using BT = Rk5B<T>;
 #pragma unroll
     for (int j = 0; j < NI; ++j)
 #pragma unroll
@@ -339,9 +362,26 @@ __global__ void __launch_bounds__(NT)
                         site_aniso(j, P - 1, Di, ex, ey, ez);
                         stage_at<T, PREC, ANIS, W0>(sA1[sl][0], sA1[sl][1], sA1[sl][2], r1[j], X[j][u1],
                                                     X[j][u2], X[j][u], C, Di, ex, ey, ez, kx, ky, kz);
-                        Y2[j][u1][0] = kx * c2 + X[j][u1][0];
-                        Y2[j][u1][1] = ky * c2 + X[j][u1][1];
-                        Y2[j][u1][2] = kz * c2 + X[j][u1][2];
+                        if constexpr (SCHEME == 3) {
+                            const T kk[3] = {kx, ky, kz};
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                Y2[j][u1][c] = kk[c] * BT::a10 + X[j][u1][c];
+                                P3[j][u1 & 1][c] = kk[c] * BT::a20 + X[j][u1][c];
+                            }
+                            if (pfirst[j] < R4) {  // the partial sums serve the core only
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) {
+                                    P5[j][u1][c] = kk[c] * BT::a40 + X[j][u1][c];
+                                    Q6[j][u1][c] = kk[c] * BT::a50 + X[j][u1][c];
+                                    RR[j][u1][c] = kk[c] * BT::b0 + X[j][u1][c];
+                                }
+                            }
+                        } else {
+                            Y2[j][u1][0] = kx * c2 + X[j][u1][0];
+                            Y2[j][u1][1] = ky * c2 + X[j][u1][1];
+                            Y2[j][u1][2] = kz * c2 + X[j][u1][2];
+                        }
                         if (SCHEME == 0 && j * NT < R4) {
                             A[j][u1][0] = kx * c6 + X[j][u1][0];
                             A[j][u1][1] = ky * c6 + X[j][u1][1];
@@ -375,6 +415,17 @@ __global__ void __launch_bounds__(NT)
                                 A[j][u2][1] = ky * c3 + A[j][u2][1];
                                 A[j][u2][2] = kz * c3 + A[j][u2][2];
                             }
+                        } else if constexpr (SCHEME == 3) {
+                            const T kk[3] = {kx, ky, kz};
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                Y3[j][u2][c] = kk[c] * BT::a21 + P3[j][u2 & 1][c];
+                                P4[j][u2 & 1][c] = kk[c] * BT::a31 + X[j][u2][c];
+                            }
+                            if (pfirst[j] < R4) {
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) Q6[j][u2][c] = kk[c] * BT::a51 + Q6[j][u2][c];
+                            }
                         } else {  // x1 = x + k2
                             Y3[j][u2][0] = kx + X[j][u2][0];
                             Y3[j][u2][1] = ky + X[j][u2][1];
@@ -407,6 +458,17 @@ __global__ void __launch_bounds__(NT)
                                 A[j][u3][0] = kx * c3 + A[j][u3][0];
                                 A[j][u3][1] = ky * c3 + A[j][u3][1];
                                 A[j][u3][2] = kz * c3 + A[j][u3][2];
+                            }
+                        } else if constexpr (SCHEME == 3) {  // a32 = 1
+                            const T kk[3] = {kx, ky, kz};
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) Y4[j][u3][c] = kk[c] + P4[j][u3 & 1][c];
+                            if (pfirst[j] < R4) {
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) {
+                                    Q6[j][u3][c] = kk[c] * BT::a52 + Q6[j][u3][c];
+                                    RR[j][u3][c] = kk[c] * BT::b2 + RR[j][u3][c];
+                                }
                             }
                         } else {  // y4 = x1 + k3/2
                             Y4[j][u3][0] = kx * c2 + Y3[j][u3][0];
@@ -445,6 +507,16 @@ __global__ void __launch_bounds__(NT)
                                 rx = kx * c6 + A[j][u][0];
                                 ry = ky * c6 + A[j][u][1];
                                 rz = kz * c6 + A[j][u][2];
+                            } else if constexpr (SCHEME == 3) {  // Y5; Q6 and R finished
+                                rx = kx * BT::a43 + P5[j][u][0];
+                                ry = ky * BT::a43 + P5[j][u][1];
+                                rz = kz * BT::a43 + P5[j][u][2];
+                                Q6[j][u][0] = kx * BT::a53 + Q6[j][u][0];
+                                Q6[j][u][1] = ky * BT::a53 + Q6[j][u][1];
+                                Q6[j][u][2] = kz * BT::a53 + Q6[j][u][2];
+                                RR[j][u][0] = kx * BT::b3 + RR[j][u][0];
+                                RR[j][u][1] = ky * BT::b3 + RR[j][u][1];
+                                RR[j][u][2] = kz * BT::b3 + RR[j][u][2];
                             } else {  // x2 = x1 + k4
                                 rx = kx + Y3[j][u][0];
                                 ry = ky + Y3[j][u][1];
@@ -462,6 +534,14 @@ __global__ void __launch_bounds__(NT)
                             ox[g] = rx;
                             oy[g] = ry;
                             oz[g] = rz;
+                            if constexpr (SCHEME == 3) {
+                                static_cast<T*>(out2.x)[R.off + g] = Q6[j][u][0];
+                                static_cast<T*>(out2.y)[R.off + g] = Q6[j][u][1];
+                                static_cast<T*>(out2.z)[R.off + g] = Q6[j][u][2];
+                                static_cast<T*>(out3.x)[R.off + g] = RR[j][u][0];
+                                static_cast<T*>(out3.y)[R.off + g] = RR[j][u][1];
+                                static_cast<T*>(out3.z)[R.off + g] = RR[j][u][2];
+                            }
                         }
                     }
                 }
@@ -509,16 +589,17 @@ template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, int SCHEME>
 inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, State in, State out,
                            int bz, int kick, uint64_t k, double so, unsigned long long* kd,
                            const LaunchEvents* ev, hipStream_t st) {
+    const State none{};
     if (kick)
         hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, true, SCHEME>), dim3(ntiles),
-                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd);
+                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd, none, none);
     else if (ev)  // start/stop events taken from the dispatch itself
         hipExtLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false, SCHEME>),
                               dim3(ntiles), dim3(NT), 0, st, ev->start, ev->stop, 0, reps, tiles, in,
-                              out, bz, k, so, kd);
+                              out, bz, k, so, kd, none, none);
     else
         hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false, SCHEME>), dim3(ntiles),
-                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd);
+                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd, none, none);
     return hipGetLastError();
 }
 

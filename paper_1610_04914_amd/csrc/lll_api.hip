@@ -418,6 +418,27 @@ const LaunchEvents* kt_take(Engine& E) {
 lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sigma_override) {
     if (n <= 0) return LLL_OK;
     const bool fused_ok = E.variant != 0 && E.anis != ANIS_SITE;
+    if (E.integrator == LLL_RK5B && fused_ok) {
+        // two launches per step (stages 1-4, stages 5-6) through three scratch
+        // states; the kick rides on the last step's second launch
+        lll_status s = alloc_state(E, E.alt);
+        for (int j = 0; j < 3 && s == LLL_OK; ++j) s = alloc_state(E, E.Kt[j]);
+        if (s != LLL_OK) return s;
+        if ((s = ensure_tiles(E)) != LLL_OK) return s;
+        for (int64_t q = 0; q < n; ++q) {
+            const bool kk = kick_last && q + 1 == n && E.kick_epilogue;
+            State in = cur_state(E);
+            State out = E.cur ? E.s : E.alt;
+            HIP_TRY(launch_step_rk5_fused(E.prec, E.precession, E.anis, E.variant, eff_bz(E),
+                                          E.dreps, E.d_tiles, E.ntiles, in, out, E.Kt, kk ? 1 : 0, k,
+                                          sigma_override, E.d_kickdev, E.st));
+            E.cur ^= 1;
+        }
+        if (kick_last && !E.kick_epilogue)
+            HIP_TRY(launch_kick(E.prec, E.dreps, E.d_blk_rep, E.nblk, cur_state(E), k,
+                                sigma_override, E.d_kickdev, E.st));
+        return LLL_OK;
+    }
     if (E.integrator == LLL_RK5B || (E.integrator == LLL_RK2MID && !fused_ok)) {
         const Tableau tb = tableau_of(E.integrator);
         KSet ks;
@@ -1061,7 +1082,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     HIP_TRY(hipEventCreate(&e1));
     std::vector<std::pair<int, int>> cands;
     cands.push_back({0, 0});
-    if (E.anis != ANIS_SITE && E.integrator != LLL_RK5B) {  // RK5 has no fused kernel
+    if (E.anis != ANIS_SITE) {
         for (int v = 1; v <= fused_variant_count(E.prec); ++v) {
             const int bzs[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512, 1024};
             for (int b : bzs)

@@ -133,6 +133,15 @@ hipError_t launch_step_fused(int prec, int precession, int anis, int variant, in
                              State out, int kick, uint64_t k, double sigma_override,
                              unsigned long long* kickdev, const LaunchEvents* ev, hipStream_t st);
 
+// Fused Butcher RK5 step (Appendix) in two launches: stages 1-4 from in into
+// the scratch states k[0] (Y5), k[1] (Q6), k[2] (R), then stages 5-6 into out,
+// with kick number kp as the epilogue when kick != 0 (as launch_step_fused).
+// The variant has the tile shape of the same RK4 variant.
+hipError_t launch_step_rk5_fused(int prec, int precession, int anis, int variant, int bz,
+                                 const RepDev* reps, const int4* tiles, int ntiles, State in,
+                                 State out, const State* k, int kick, uint64_t kp, double so,
+                                 unsigned long long* kd, hipStream_t st);
+
 // RK4 step keeping the stage inputs y2, y3, y4 (per-stage launches).
 hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* reps,
                              const int32_t* blk_rep, int nblk, State x, State y2, State y3,

@@ -897,6 +897,68 @@ def test_rk2_fused_all_variants(P, prec, kind, precession):
                 lat.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind,precession", [("zaxis", True), ("axis", False), ("none", True)])
+def test_rk5_fused_all_variants(P, prec, kind, precession):
+    """Fused Butcher RK5 (two launches per step: stages 1-4, then 5-6) in every
+    tile shape and z-chunk, on periodic, free, flat, odd and single-site
+    lattices, against the oracle's stepper; and one interval of the schedule
+    (2 steps with the kick as the epilogue or as its own launch, then 3 steps)
+    against the oracle's steps and kick."""
+    op, _ = both_params(kind, dt=0.1, Dt=0.5, precession=precession)
+    gp = P.Params(seed=37, dt=0.1, Dt=0.5, precession=precession, integrator="rk5b", **PHYS[kind])
+    for shape, bc, bz in STEP_SHAPES:
+        N = int(np.prod(shape))
+        s0 = rounded(inputs.unit_spins(N, 300 + N), prec)
+        g = orc.geom(shape, bc)
+        want = orc.step(g, op, s0, 3, method="rk5b")
+        for v in variants(P, prec):
+            lat = make_lattice(P, shape, bc, prec, s0)
+            lat.set_step_config(v, bz)
+            lat.step(gp, 3)
+            err = np.max(np.abs(np_state(lat) - want))
+            assert err < TOL[prec], (shape, bc, v, bz, err)
+            lat.close()
+        want = orc.step(g, op, s0, 2, method="rk5b")
+        want, _ = orc.kick(g, op, want, op.T, seed=37, r=0, k=5)
+        want = orc.step(g, op, want, 3, method="rk5b")
+        for v in variants(P, prec):
+            for fused in (True, False):
+                lat = make_lattice(P, shape, bc, prec, s0)
+                lat.set_step_config(v, bz)
+                lat.set_kick_fusion(fused)
+                lat.kick_norm_dev(reset=True)
+                lat.run(gp, first_pulse=5, n_pulses=1)
+                err = np.max(np.abs(np_state(lat) - want))
+                assert err < TOL[prec], (shape, bc, v, bz, fused, err)
+                lat.close()
+
+
+def test_rk5_fused_headline_interval(P):
+    """The headline lattice (128^3, fp32, dt = 0.2, Dt = 2) with Butcher RK5 in
+    its tuned fused configuration: one interval against the oracle started
+    from the GPU's state, element by element."""
+    import bench
+    shape = (128, 128, 128)
+    ph = dict(bench.PHYS)
+    gp = P.Params(integrator="rk5b", **ph)
+    op = orc.Params(J=ph["J"], H=ph["H"], D=ph["D"], e=ph["e"], lam=ph["lam"], T=ph["T"],
+                    dt=ph["dt"], Dt=ph["Dt"], precession=True)
+    lat = P.Lattice(shape, precision="fp32", init="random", seed=0)
+    v, _ = lat.autotune(gp, cache_path=bench.TUNE_CACHE)
+    assert v != 0, "the fused RK5 step is not selected"
+    prev = np_state(lat)
+    with pytest.warns(P.ApplicabilityWarning):
+        lat.run(gp, first_pulse=3, n_pulses=1)
+    g = orc.geom(shape)
+    want = orc.step(g, op, prev, 5, method="rk5b")
+    want, _ = orc.kick(g, op, want, op.T, seed=0, r=0, k=3)
+    want = orc.step(g, op, want, 5, method="rk5b")
+    err = float(np.max(np.abs(np_state(lat) - want)))
+    assert err < TOL["fp32"], err
+    lat.close()
+
+
 # --------------------------------------------------------------- autotuner ---
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_autotune_restores_state_and_reuses_its_cache(P, prec, tmp_path):

@@ -294,6 +294,7 @@ def extra_adjoint():
         p = P.Params(J=1.0, H=(0, 0, 0.2), lam=0.01, T=0.5, dt=0.1, Dt=10.0, D_site=Dt_, e_site=et,
                      seed=0)
         lat = P.Lattice((32, 32, 32), precision=prec, init="direction", direction=(0, 0, 1))
+        variant, bz = lat.autotune(p, cache_path=TUNE_CACHE)
         s0 = lat.state.clone()
         lat.run(p, 0, 3)
         lat.state.copy_(s0)
@@ -301,7 +302,8 @@ def extra_adjoint():
         lat.state.copy_(s0)
         lat.adjoint(p, 0, 3, ckpt_every=10, wE=1.0, wm=(0, 0, 1))
         el_a, _ = _timed(lambda: lat.adjoint(p, 0, 3, ckpt_every=10, wE=1.0, wm=(0, 0, 1)))
-        out[prec] = {"forward_s": el_f, "adjoint_s": el_a, "ratio": el_a / el_f}
+        out[prec] = {"forward_s": el_f, "adjoint_s": el_a, "ratio": el_a / el_f,
+                     "step_variant": variant, "bz": bz}
         lat.close()
     return out
 

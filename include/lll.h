@@ -78,8 +78,8 @@ typedef enum {
  * x' = x + K2 (fused: two steps per launch).  LLL_RK5B: Butcher's six-stage
  * fifth-order method (the paper's main solver; fused: two launches per step,
  * stages 1-4 and stages 5-6).  With the unfused step configuration
- * (variant 0) or per-site anisotropy, RK2MID and RK5B run one launch per
- * stage.  Neither is available to the adjoint or the batch. */
+ * (variant 0), RK2MID and RK5B run one launch per stage.  Neither is
+ * available to the adjoint or the batch. */
 typedef enum { LLL_RK4 = 0, LLL_RK2MID = 1, LLL_RK5B = 2 } lll_integrator;
 
 /* Physical and numerical parameters, copied on every call.  Thresholds of the

@@ -143,12 +143,16 @@ struct Rk5B {
 // with P4 = x + a31 k2; per point the partial sums P5 = x + a40 k1,
 // Q6 = x + a50 k1 + a51 k2 + a52 k3 (+ a53 k4) and R = x + b0 k1 + b2 k3
 // (+ b3 k4) ride along, and the last stage writes Y5 = P5 + a43 k4 to out,
-// Q6 to out2 and R to out3 (b1 = 0).
+// Q6 to out2 and R to out3 (b1 = 0).  SCHEME 4: one classical RK4 step, as
+// SCHEME 0 and with the same bits, that also writes its stage inputs y2, y3
+// and y4 of the output tile to out2, out3 and out4 (the discrete adjoint's
+// recompute of a checkpoint block needs them).
 template <typename T, int BX, int BY, int NT, bool PREC, int ANIS, bool KICK, int SCHEME>
 __global__ void __launch_bounds__(NT)
     rk4_fused_kernel(const RepDev* __restrict__ reps, const int4* __restrict__ tiles, State in,
                      State out, int bz_arg, uint64_t kpulse, double sigma_override,
-                     unsigned long long* kickdev, State out2, State out3) {
+                     unsigned long long* kickdev, State out2, State out3, State out4) {
+    constexpr bool RK4S = SCHEME == 0 || SCHEME == 4;  // classical RK4 arithmetic
     // Region Rs = the tile grown by 4-s sites in x and y (R0: loaded points).
     constexpr int R0 = (BX + 8) * (BY + 8);
     constexpr int R1 = (BX + 6) * (BY + 6);
@@ -305,6 +309,17 @@ __global__ void __launch_bounds__(NT)
         }
     };
 
+    // SCHEME 4: a stage input of output-tile point j on plane q, stored when the
+    // plane belongs to this tile's z-chunk
+    auto store_core = [&](int j, int q, const State& dst, const T* v) {
+        if (j * NT < R4 && pidx[j] < R4 && outok[j] && q >= z0 && q < zend) {
+            const int64_t g = R.off + (int64_t)col[j] + plane * q;
+            static_cast<T*>(dst.x)[g] = v[0];
+            static_cast<T*>(dst.y)[g] = v[1];
+            static_cast<T*>(dst.z)[g] = v[2];
+        }
+    };
+
     const T c6 = T(1) / T(6), c3 = T(1) / T(3), c2 = T(0.5);
     double kmax = 0.0;
     T sg = T(0);
@@ -382,7 +397,7 @@ __global__ void __launch_bounds__(NT)
                             Y2[j][u1][1] = ky * c2 + X[j][u1][1];
                             Y2[j][u1][2] = kz * c2 + X[j][u1][2];
                         }
-                        if (SCHEME == 0 && j * NT < R4) {
+                        if (RK4S && j * NT < R4) {
                             A[j][u1][0] = kx * c6 + X[j][u1][0];
                             A[j][u1][1] = ky * c6 + X[j][u1][1];
                             A[j][u1][2] = kz * c6 + X[j][u1][2];
@@ -392,6 +407,7 @@ __global__ void __launch_bounds__(NT)
                             sA2[sl][1][o2[j]] = Y2[j][u1][1];
                             sA2[sl][2][o2[j]] = Y2[j][u1][2];
                         }
+                        if constexpr (SCHEME == 4) store_core(j, P - 1, out2, Y2[j][u1]);
                     }
                 }
             }
@@ -406,7 +422,7 @@ __global__ void __launch_bounds__(NT)
                         site_aniso(j, P - 2, Di, ex, ey, ez);
                         stage_at<T, PREC, ANIS, W1>(sA2[sl][0], sA2[sl][1], sA2[sl][2], r2[j], Y2[j][u2],
                                                     Y2[j][u3], Y2[j][u1], C, Di, ex, ey, ez, kx, ky, kz);
-                        if constexpr (SCHEME == 0) {
+                        if constexpr (RK4S) {
                             Y3[j][u2][0] = kx * c2 + X[j][u2][0];
                             Y3[j][u2][1] = ky * c2 + X[j][u2][1];
                             Y3[j][u2][2] = kz * c2 + X[j][u2][2];
@@ -436,6 +452,7 @@ __global__ void __launch_bounds__(NT)
                             sA3[sl][1][o3[j]] = Y3[j][u2][1];
                             sA3[sl][2][o3[j]] = Y3[j][u2][2];
                         }
+                        if constexpr (SCHEME == 4) store_core(j, P - 2, out3, Y3[j][u2]);
                     }
                 }
             }
@@ -450,7 +467,7 @@ __global__ void __launch_bounds__(NT)
                         site_aniso(j, P - 3, Di, ex, ey, ez);
                         stage_at<T, PREC, ANIS, W2>(sA3[sl][0], sA3[sl][1], sA3[sl][2], r3[j], Y3[j][u3],
                                                     Y3[j][u], Y3[j][u2], C, Di, ex, ey, ez, kx, ky, kz);
-                        if constexpr (SCHEME == 0) {
+                        if constexpr (RK4S) {
                             Y4[j][u3][0] = kx + X[j][u3][0];
                             Y4[j][u3][1] = ky + X[j][u3][1];
                             Y4[j][u3][2] = kz + X[j][u3][2];
@@ -480,6 +497,7 @@ __global__ void __launch_bounds__(NT)
                             sA4[sl][1][o4[j]] = Y4[j][u3][1];
                             sA4[sl][2][o4[j]] = Y4[j][u3][2];
                         }
+                        if constexpr (SCHEME == 4) store_core(j, P - 3, out4, Y4[j][u3]);
                     }
                 }
             }
@@ -503,7 +521,7 @@ __global__ void __launch_bounds__(NT)
                             stage_at<T, PREC, ANIS, W3>(sA4[sl][0], sA4[sl][1], sA4[sl][2], r4[j],
                                                         Y4[j][u], Y4[j][u1], Y4[j][u3], C, Di, ex,
                                                         ey, ez, kx, ky, kz);
-                            if constexpr (SCHEME == 0) {
+                            if constexpr (RK4S) {
                                 rx = kx * c6 + A[j][u][0];
                                 ry = ky * c6 + A[j][u][1];
                                 rz = kz * c6 + A[j][u][2];
@@ -592,14 +610,14 @@ inline hipError_t launch_v(const RepDev* reps, const int4* tiles, int ntiles, St
     const State none{};
     if (kick)
         hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, true, SCHEME>), dim3(ntiles),
-                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd, none, none);
+                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd, none, none, none);
     else if (ev)  // start/stop events taken from the dispatch itself
         hipExtLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false, SCHEME>),
                               dim3(ntiles), dim3(NT), 0, st, ev->start, ev->stop, 0, reps, tiles, in,
-                              out, bz, k, so, kd, none, none);
+                              out, bz, k, so, kd, none, none, none);
     else
         hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PREC, ANIS, false, SCHEME>), dim3(ntiles),
-                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd, none, none);
+                           dim3(NT), 0, st, reps, tiles, in, out, bz, k, so, kd, none, none, none);
     return hipGetLastError();
 }
 
@@ -611,7 +629,8 @@ inline hipError_t launch_a(int anis, const RepDev* reps, const int4* tiles, int 
         case ANIS_NONE: return launch_v<T, BX, BY, NT, PREC, ANIS_NONE, SCHEME>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
         case ANIS_Z: return launch_v<T, BX, BY, NT, PREC, ANIS_Z, SCHEME>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
         case ANIS_AXIS: return launch_v<T, BX, BY, NT, PREC, ANIS_AXIS, SCHEME>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
-        default: return hipErrorInvalidValue;  // per-site anisotropy runs on the unfused step
+        case ANIS_SITE: return launch_v<T, BX, BY, NT, PREC, ANIS_SITE, SCHEME>(reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -622,6 +641,35 @@ inline hipError_t launch_p(int precession, int anis, const RepDev* reps, const i
     if (precession)
         return launch_a<T, BX, BY, NT, true, SCHEME>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
     return launch_a<T, BX, BY, NT, false, SCHEME>(anis, reps, tiles, ntiles, in, out, bz, kick, k, so, kd, ev, st);
+}
+
+// One RK4 step (SCHEME 4) from in to out that also writes the stage inputs
+// y2, y3, y4 (no kick).
+template <typename T, int BX, int BY, int NT>
+inline hipError_t launch_stages_v(int precession, int anis, const RepDev* reps, const int4* tiles,
+                                  int ntiles, State in, State out, const State* y, int bz,
+                                  hipStream_t st) {
+#define LLL_ST_LAUNCH(PR, AN)                                                                          \
+    hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NT, PR, AN, false, 4>), dim3(ntiles), dim3(NT), 0, \
+                       st, reps, tiles, in, out, bz, (uint64_t)0, -1.0, (unsigned long long*)nullptr,  \
+                       y[0], y[1], y[2]);                                                              \
+    break;
+#define LLL_ST_ANIS(PR)                                             \
+    switch (anis) {                                                 \
+        case ANIS_NONE: LLL_ST_LAUNCH(PR, ANIS_NONE)                \
+        case ANIS_Z: LLL_ST_LAUNCH(PR, ANIS_Z)                      \
+        case ANIS_AXIS: LLL_ST_LAUNCH(PR, ANIS_AXIS)                \
+        case ANIS_SITE: LLL_ST_LAUNCH(PR, ANIS_SITE)                \
+        default: return hipErrorInvalidValue;                       \
+    }
+    if (precession) {
+        LLL_ST_ANIS(true)
+    } else {
+        LLL_ST_ANIS(false)
+    }
+#undef LLL_ST_ANIS
+#undef LLL_ST_LAUNCH
+    return hipGetLastError();
 }
 
 // Tile variants (bx, by, threads) by precision, for one scheme.  The same

@@ -37,6 +37,34 @@ bool fused_variant_info(int prec, int variant, FusedInfo* out) {
 
 hipError_t fused_f32_rk4(LLL_FUSED_ARGS) { return fused_f32<0>(precession, anis, variant, bz, reps, tiles, ntiles, in, out, kick, k, so, kd, ev, st); }
 
+hipError_t fused_f64_stages(int precession, int anis, int variant, int bz, const RepDev* reps,
+                            const int4* tiles, int ntiles, State in, State out, const State* y,
+                            hipStream_t st);
+
+static hipError_t fused_f32_stages(int precession, int anis, int variant, int bz, const RepDev* reps,
+                                   const int4* tiles, int ntiles, State in, State out,
+                                   const State* y, hipStream_t st) {
+#define LLL_ST_PASS precession, anis, reps, tiles, ntiles, in, out, y, bz, st
+    switch (variant) {
+        case 1: return launch_stages_v<float, 32, 16, 960>(LLL_ST_PASS);
+        case 2: return launch_stages_v<float, 32, 16, 512>(LLL_ST_PASS);
+        case 3: return launch_stages_v<float, 16, 16, 576>(LLL_ST_PASS);
+        case 4: return launch_stages_v<float, 32, 8, 640>(LLL_ST_PASS);
+        case 5: return launch_stages_v<float, 64, 8, 512>(LLL_ST_PASS);
+        case 6: return launch_stages_v<float, 32, 16, 1024>(LLL_ST_PASS);
+        default: return hipErrorInvalidValue;
+    }
+#undef LLL_ST_PASS
+}
+
+hipError_t launch_step_fused_stages(int prec, int precession, int anis, int variant, int bz,
+                                    const RepDev* reps, const int4* tiles, int ntiles, State in,
+                                    State out, const State* y, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    return prec == 0 ? fused_f64_stages(precession, anis, variant, bz, reps, tiles, ntiles, in, out, y, st)
+                     : fused_f32_stages(precession, anis, variant, bz, reps, tiles, ntiles, in, out, y, st);
+}
+
 hipError_t launch_step_fused(int prec, int precession, int anis, int variant, int bz, int scheme,
                              const RepDev* reps, const int4* tiles, int ntiles, State in,
                              State out, int kick, uint64_t k, double so,

@@ -326,7 +326,8 @@ inline hipError_t launch_rk5_v(const RepDev* reps, const int4* tiles, int ntiles
                                State out, const State* k, int bz, int kick, uint64_t kp, double so,
                                unsigned long long* kd, hipStream_t st) {
     hipLaunchKernelGGL((rk4_fused_kernel<T, BX, BY, NTA, PREC, ANIS, false, 3>), dim3(ntiles),
-                       dim3(NTA), 0, st, reps, tiles, in, k[0], bz, kp, so, kd, k[1], k[2]);
+                       dim3(NTA), 0, st, reps, tiles, in, k[0], bz, kp, so, kd, k[1], k[2],
+                       State{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (kick)
@@ -347,6 +348,7 @@ inline hipError_t launch_rk5_p(int precession, int anis, const RepDev* reps, con
         case ANIS_NONE: return launch_rk5_v<T, BX, BY, NTA, NTB, PR, ANIS_NONE>(reps, tiles, ntiles, in, out, k, bz, kick, kp, so, kd, st); \
         case ANIS_Z: return launch_rk5_v<T, BX, BY, NTA, NTB, PR, ANIS_Z>(reps, tiles, ntiles, in, out, k, bz, kick, kp, so, kd, st);       \
         case ANIS_AXIS: return launch_rk5_v<T, BX, BY, NTA, NTB, PR, ANIS_AXIS>(reps, tiles, ntiles, in, out, k, bz, kick, kp, so, kd, st); \
+        case ANIS_SITE: return launch_rk5_v<T, BX, BY, NTA, NTB, PR, ANIS_SITE>(reps, tiles, ntiles, in, out, k, bz, kick, kp, so, kd, st); \
         default: return hipErrorInvalidValue;                                                         \
     }
     if (precession) {

@@ -417,7 +417,7 @@ const LaunchEvents* kt_take(Engine& E) {
 
 lll_status do_steps(Engine& E, int64_t n, bool kick_last, uint64_t k, double sigma_override) {
     if (n <= 0) return LLL_OK;
-    const bool fused_ok = E.variant != 0 && E.anis != ANIS_SITE;
+    const bool fused_ok = E.variant != 0;
     if (E.integrator == LLL_RK5B && fused_ok) {
         // two launches per step (stages 1-4, stages 5-6) through three scratch
         // states; the kick rides on the last step's second launch
@@ -1082,7 +1082,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     HIP_TRY(hipEventCreate(&e1));
     std::vector<std::pair<int, int>> cands;
     cands.push_back({0, 0});
-    if (E.anis != ANIS_SITE) {
+    {
         for (int v = 1; v <= fused_variant_count(E.prec); ++v) {
             const int bzs[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512, 1024};
             for (int b : bzs)
@@ -1119,7 +1119,7 @@ lll_status engine_autotune(Engine& E, const std::string& key, int maxLz, int64_t
     // kick placement: epilogue of the fused step, or its own launch (whole intervals timed;
     // the two differ by a few per cent of an interval, so three alternating trials of six)
     bool bk = true;
-    if (s == LLL_OK && bv != 0 && E.anis != ANIS_SITE && n_interval >= 2) {
+    if (s == LLL_OK && bv != 0 && n_interval >= 2) {
         double tk[2] = {1e30, 1e30};
         for (int trial = 0; trial < 3 && s == LLL_OK; ++trial)
             for (int mode = 0; mode < 2 && s == LLL_OK; ++mode) {
@@ -1334,6 +1334,7 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
     if (s != LLL_OK) return s;
     Engine& E = L->E;
     if ((s = ensure_adj_work(L, T->K)) != LLL_OK) return s;
+    if (E.variant != 0 && (s = ensure_tiles(E)) != LLL_OK) return s;
     const size_t cb = (size_t)E.nsites * E.esz;
     const int64_t nops = (int64_t)T->op.size();
     const int64_t K = T->K;
@@ -1370,7 +1371,11 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
         for (int64_t j = j0; j < j1; ++j) {
             const int64_t sl = j - j0;
             State nx = slot(sl + 1, 0);
-            if (T->op[j] == 0) {
+            if (T->op[j] == 0 && E.variant != 0) {  // one fused launch: x', y2, y3, y4
+                const State ys[3] = {slot(sl, 1), slot(sl, 2), slot(sl, 3)};
+                HIP_TRY(launch_step_fused_stages(pr, pc, an, E.variant, eff_bz(E), E.dreps,
+                                                 E.d_tiles, E.ntiles, slot(sl, 0), nx, ys, E.st));
+            } else if (T->op[j] == 0) {
                 HIP_TRY(launch_rk4_stages(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, slot(sl, 0),
                                           slot(sl, 1), slot(sl, 2), slot(sl, 3), accb, nx, E.st));
             } else {

@@ -142,6 +142,12 @@ hipError_t launch_step_rk5_fused(int prec, int precession, int anis, int variant
                                  State out, const State* k, int kick, uint64_t kp, double so,
                                  unsigned long long* kd, hipStream_t st);
 
+// Fused RK4 step from in to out (same bits as launch_step_fused without a
+// kick) that also writes its stage inputs y2, y3, y4 into y[0..2].
+hipError_t launch_step_fused_stages(int prec, int precession, int anis, int variant, int bz,
+                                    const RepDev* reps, const int4* tiles, int ntiles, State in,
+                                    State out, const State* y, hipStream_t st);
+
 // RK4 step keeping the stage inputs y2, y3, y4 (per-stage launches).
 hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* reps,
                              const int32_t* blk_rep, int nblk, State x, State y2, State y3,

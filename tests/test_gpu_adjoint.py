@@ -80,6 +80,40 @@ def test_adjoint_vs_oracle(P, prec, case):
     assert _rel(got["g_s0"].double().cpu().numpy(), want["g_s0"]) < tol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES[:3])
+def test_adjoint_every_step_configuration(P, prec, case):
+    """The same gradients with every step configuration: the forward and the
+    recompute of each checkpoint block use the fused step (the recompute's
+    variant also writes the stage inputs the reverse pass needs) or the
+    per-stage launches."""
+    shape, bc, precession, site, dt, Dt, npl, ck = case
+    N = int(np.prod(shape))
+    s0 = _rounded(inputs.near_ordered_spins(N, 31), prec)
+    D, e = inputs.site_anisotropy(N, 32)
+    D, e = _rounded(D, prec), _rounded(e, prec)
+    kw = dict(J=1.1, H=(0.05, -0.02, 0.2), lam=0.05, T=0.5, dt=dt, Dt=Dt, precession=precession)
+    if site:
+        op = orc.Params(D_site=D, e_site=e, **kw)
+        gp = P.Params(D_site=_dev(D, prec), e_site=_dev(e, prec), seed=6, **kw)
+    else:
+        op = orc.Params(D=0.1, e=(1.0, 0.0, 1.0), **kw)
+        gp = P.Params(D=0.1, e=(1.0, 0.0, 1.0), seed=6, **kw)
+    want = orc.adjoint(orc.geom(shape, bc), op, s0, seed=6, r=0, first_pulse=4, n_pulses=npl,
+                       wE=0.7, wm=(0.0, 0.3, 1.0))
+    for v in P.step_variants(prec):
+        lat = P.Lattice(shape, bc=bc, precision=prec, state=_dev(s0, prec))
+        lat.set_step_config(v, 4 if v else 0)
+        got = lat.adjoint(gp, 4, npl, ckpt_every=ck, wE=0.7, wm=(0.0, 0.3, 1.0), want_g_s0=True)
+        tol = GTOL[prec]
+        assert _rel(got["g_H"], want["g_H"]) < tol, v
+        assert _rel(got["g_J"], want["g_J"]) < tol, v
+        gD = got["g_D"].cpu().numpy() if site else got["g_D"]
+        assert _rel(gD, want["g_D"]) < tol, v
+        assert _rel(got["g_s0"].double().cpu().numpy(), want["g_s0"]) < tol, v
+        lat.close()
+
+
 def test_adjoint_finite_differences_gpu(P):
     """dL/dH_z and dL/dJ of the fp64 GPU adjoint against central differences of
     the GPU forward run."""

@@ -139,6 +139,47 @@ def test_step_site_anisotropy(P, prec):
     assert np.max(np.abs(np_state(lat) - want)) < 4 * TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", ["rk4", "rk2mid", "rk5b"])
+def test_site_anisotropy_fused_all_variants(P, prec, method):
+    """Per-site D_i along per-site axes e_i on the fused steps (every tile shape,
+    periodic and free, an odd lattice, z-chunks that leave a ragged last
+    chunk): three steps against the oracle's stepper, and one interval with
+    the kick as the epilogue and as its own launch."""
+    dt_ = torch.float64 if prec == "fp64" else torch.float32
+    for shape, bc, bz in (((33, 17, 9), "periodic", 4), ((40, 24, 20), "free", 7),
+                          ((12, 10, 9), "periodic", 0)):
+        N = int(np.prod(shape))
+        D, e = inputs.site_anisotropy(N, 11 + N)
+        D, e = rounded(D[None, :], prec)[0], rounded(e, prec)
+        s0 = rounded(inputs.unit_spins(N, 12 + N), prec)
+        kw = dict(J=1.0, H=(0.05, 0.0, 0.2), lam=0.02, T=0.7, dt=0.1, Dt=0.5)
+        op = orc.Params(D_site=D, e_site=e, **kw)
+        gp = P.Params(D_site=torch.tensor(D, dtype=dt_, device="cuda"),
+                      e_site=torch.tensor(e.reshape(-1), dtype=dt_, device="cuda"), seed=17,
+                      integrator=method, **kw)
+        g = orc.geom(shape, bc)
+        want3 = orc.step(g, op, s0, 3, method=method)
+        wantI = orc.step(g, op, s0, 2, method=method)
+        wantI, _ = orc.kick(g, op, wantI, op.T, seed=17, r=0, k=4)
+        wantI = orc.step(g, op, wantI, 3, method=method)
+        for v in variants(P, prec):
+            lat = make_lattice(P, shape, bc, prec, s0)
+            lat.set_step_config(v, bz)
+            lat.step(gp, 3)
+            err = np.max(np.abs(np_state(lat) - want3))
+            assert err < TOL[prec], (shape, bc, v, bz, err)
+            lat.close()
+            for fused in (True, False):
+                lat = make_lattice(P, shape, bc, prec, s0)
+                lat.set_step_config(v, bz)
+                lat.set_kick_fusion(fused)
+                lat.run(gp, first_pulse=4, n_pulses=1)
+                err = np.max(np.abs(np_state(lat) - wantI))
+                assert err < TOL[prec], (shape, bc, v, bz, fused, err)
+                lat.close()
+
+
 # ------------------------------------------------------------------ kicks ---
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_kick_parity(P, prec):

@@ -247,6 +247,7 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 5000, burn
     # For independent normal z, P(|z| < 2) = 0.9545: 96 replicas give 91.6
     # within 2 sigma with a binomial standard deviation of 2.0.
     nrep = len(reps)
+    hotT = np.array([r["T"] > 1.0 for r in reps])
     expect2 = 0.9545 * nrep
     sd2 = math.sqrt(nrep * 0.9545 * 0.0455)
     rate_b = sites * 10 * n_pulses / el_b
@@ -269,12 +270,28 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 5000, burn
                                 "converged_within_2sigma": int(np.sum(np.abs(z[cv[k]]) < 2.0)),
                                 "converged_expected_within_2sigma": [
                                     0.9545 * int(cv[k].sum()),
-                                    math.sqrt(int(cv[k].sum()) * 0.9545 * 0.0455)]}
+                                    math.sqrt(int(cv[k].sum()) * 0.9545 * 0.0455)],
+                                # sign test (no error bars needed): under no fp32
+                                # bias the count of positive z is Binomial(n, 1/2)
+                                "positive_z": int(np.sum(z > 0)),
+                                "positive_z_T_above_1": int(np.sum(z[hotT] > 0)),
+                                "replicas_T_above_1": int(hotT.sum()),
+                                "sign_test_p": _binom_two_sided(int(np.sum(z > 0)), nrep),
+                                "sign_test_p_T_above_1": _binom_two_sided(
+                                    int(np.sum(z[hotT] > 0)), int(hotT.sum()))}
                             for k, z in zs.items()},
                          "per_replica_T_lambda_zE_zm_converged": [
                              [float(r["T"]), float(r["lam"]), float(zs["E_per_site"][i]),
                               float(zs["abs_m"][i]), int(cv["E_per_site"][i]),
                               int(cv["abs_m"][i])] for i, r in enumerate(reps)]}}
+
+
+def _binom_two_sided(k: int, n: int) -> float:
+    """Two-sided exact binomial p-value of k successes in n trials at p = 1/2."""
+    if n == 0:
+        return 1.0
+    pk = [math.comb(n, j) / 2.0**n for j in range(n + 1)]
+    return float(min(1.0, sum(q for q in pk if q <= pk[k] * (1 + 1e-12))))
 
 
 def extra_adjoint():

@@ -35,3 +35,18 @@ def test_oracle_all_cores_build_is_identical():
                    dt=0.1, Dt=0.4)
     s = orc.init_random_sphere(g, 3)
     assert np.array_equal(orc.step(g, p, s, 3), orc.step(g, p, s, 3, all_cores=True))
+
+
+def test_sign_test_p_values():
+    """The batched accuracy sign test: exact two-sided binomial p at 1/2,
+    checked against closed forms (all heads in n: 2 / 2^n) and symmetry."""
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    assert bench._binom_two_sided(0, 5) == 2.0 / 32
+    assert bench._binom_two_sided(5, 5) == 2.0 / 32
+    assert bench._binom_two_sided(2, 4) == 1.0
+    for n in (7, 61, 96):
+        for k in range(n + 1):
+            assert bench._binom_two_sided(k, n) == bench._binom_two_sided(n - k, n)
+    # n = 10, k = 2: P(X <= 2) + P(X >= 8) = 2 * (1 + 10 + 45) / 1024
+    assert abs(bench._binom_two_sided(2, 10) - 112 / 1024) < 1e-15

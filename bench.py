@@ -296,7 +296,9 @@ def _binom_two_sided(k: int, n: int) -> float:
 
 def extra_adjoint():
     """Adjoint workload (32^3, per-site anisotropy, 3 intervals of 100 steps):
-    (forward with checkpoints + backward with recompute) / plain forward."""
+    (forward with checkpoints + backward with recompute) / plain forward, and
+    the same with a full tape (the forward keeps every step's stage inputs,
+    4 states per step, and the backward recomputes nothing)."""
     import numpy as np
     import torch
     import paper_1610_04914_amd as P
@@ -319,7 +321,13 @@ def extra_adjoint():
         lat.state.copy_(s0)
         lat.adjoint(p, 0, 3, ckpt_every=10, wE=1.0, wm=(0, 0, 1))
         el_a, _ = _timed(lambda: lat.adjoint(p, 0, 3, ckpt_every=10, wE=1.0, wm=(0, 0, 1)))
+        lat.adjoint(p, 0, 3, ckpt_every=P.TAPE_FULL, wE=1.0, wm=(0, 0, 1))
+        el_t, _ = _timed(lambda: lat.adjoint(p, 0, 3, ckpt_every=P.TAPE_FULL, wE=1.0,
+                                             wm=(0, 0, 1)))
+        nops = 3 * (100 + 1)
         out[prec] = {"forward_s": el_f, "adjoint_s": el_a, "ratio": el_a / el_f,
+                     "full_tape_adjoint_s": el_t, "full_tape_ratio": el_t / el_f,
+                     "full_tape_bytes": 3 * N * lat.state.element_size() * (4 * nops + 1),
                      "step_variant": variant, "bz": bz}
         lat.close()
     return out

@@ -220,7 +220,13 @@ lll_status lll_autotune(lll_lattice* lat, const lll_params* params, const char* 
  * as lll_run does (same kernels, same bits, no measurements; the kicks fold
  * into the lattice's kick-deviation maximum) and records a tape: the state
  * before every ckpt_every-th operation (one RK4 step or one kick) and the
- * final state s_T, which is also left in the lattice.  The tape keeps a copy
+ * final state s_T, which is also left in the lattice.  ckpt_every =
+ * LLL_TAPE_FULL (0) records instead the stage inputs x, y2 = x + k1/2,
+ * y3 = x + k2/2, y4 = x + k3 of every step (and the state before every
+ * kick): 4 states per operation plus s_T, 3 N (4 n_ops + 1) elements of the
+ * lattice precision, so that the backward recomputes nothing (the same
+ * bits as the checkpointed tape).  Tape memory is device memory allocated
+ * by the call (LLL_ENOMEM when it does not fit).  The tape keeps a copy
  * of params; params->D_site / e_site must stay valid until the tape is
  * destroyed.  Only LLL_RK4.  On success *tape receives the handle.
  *
@@ -229,8 +235,8 @@ lll_status lll_autotune(lll_lattice* lat, const lll_params* params, const char* 
  * with respect to the initial state and the parameters.  cot (optional,
  * NULL = 0) is a device array [3*N] of the lattice precision (x block, y
  * block, z block): the cotangent dL/ds_T of whatever loss the caller computes
- * from s_T itself.  Each call recomputes every checkpoint block, so a tape
- * can be reversed any number of times.  Outputs: *loss (may be NULL) =
+ * from s_T itself.  Each call recomputes every checkpoint block (none for a
+ * full tape), so a tape can be reversed any number of times.  Outputs: *loss (may be NULL) =
  * wE E(s_T) + wm . m(s_T) (the caller's own term is not included); g_H[3],
  * *g_J (host); g_D: host double[1] = dL/dD when the tape's D_site is NULL,
  * else a device fp64 array [N] of dL/dD_i; g_s0 (optional): device array
@@ -246,8 +252,10 @@ lll_status lll_autotune(lll_lattice* lat, const lll_params* params, const char* 
  * restored, in one call (the lattice's state and kick maximum are left as
  * they were).
  *
- * Work buffers of the backward pass (4 ckpt_every + 11 states) stay with the
- * lattice and are reused. */
+ * Work buffers of the backward pass (4 ckpt_every + 11 states; 10 for a
+ * full tape) stay with the lattice and are reused.  ckpt_every < 0 is
+ * LLL_EINVAL. */
+#define LLL_TAPE_FULL 0
 typedef struct lll_tape lll_tape;
 lll_status lll_adjoint_forward(lll_lattice* lat, const lll_params* params, uint64_t first_pulse,
                                int64_t n_pulses, int32_t ckpt_every, lll_tape** tape);

@@ -406,13 +406,18 @@ class Lattice:
     def adjoint_forward(self, p: Params, first_pulse: int, n_pulses: int,
                         ckpt_every: int = 10) -> "Tape":
         """Runs n_pulses intervals like run() (the state advances to s_T) and
-        records the tape of lll_adjoint_forward for a later backward()."""
+        records the tape of lll_adjoint_forward for a later backward().
+        ckpt_every = TAPE_FULL (0) keeps every step's stage inputs, so the
+        backward recomputes nothing."""
         pc = self._pc(p)
         h = _P()
         _check(lib().lll_adjoint_forward(self.h, C.byref(pc), C.c_uint64(first_pulse),
                                          int(n_pulses), int(ckpt_every), C.byref(h)),
                "lll_adjoint_forward")
         return Tape(self, h, p)
+
+
+TAPE_FULL = 0  # ckpt_every value of a tape that keeps every step's stage inputs
 
 
 class Tape:

@@ -24,10 +24,12 @@ struct SiteA {
     int x, y, z;
 };
 
-__device__ __forceinline__ bool adj_site(const RepDev* reps, const int32_t* blk_rep, SiteA& c) {
+// The adjoint runs on one lattice, whose descriptor comes by value as a
+// kernel argument: no dependent loads of a block table and a replica record
+// before the first data load.
+__device__ __forceinline__ bool adj_site(const RepDev& R, SiteA& c) {
     const int b = blockIdx.x;
-    c.r = blk_rep[b];
-    const RepDev& R = reps[c.r];
+    c.r = 0;
     const int64_t N = (int64_t)R.Lx * R.Ly * R.Lz;
     c.i = (int64_t)(b - R.sb0) * kAdjBlock + threadIdx.x;
     c.gi = R.off + c.i;
@@ -36,26 +38,32 @@ __device__ __forceinline__ bool adj_site(const RepDev* reps, const int32_t* blk_
     return true;
 }
 
-// Sum over the (up to six) neighbours of site c of the field a.
+// Sum over the (up to six) neighbours of site c of the field a, in the order
+// -x, +x, -y, +y, -z, +z.  Branch-free: a missing neighbour (free boundary)
+// reads the site itself and adds 0.0 instead, which leaves the sum's bits as
+// they are; all eighteen loads are independent, so they are in flight
+// together rather than each waiting for the one before.
 template <typename T>
 __device__ __forceinline__ void nbr_sum(const RepDev& R, const SiteA& c, const T* ax, const T* ay,
                                         const T* az, double& sx, double& sy, double& sz) {
-    const int Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
-    const bool pbc = R.bc == 0;
+    int64_t d[6];
+    bool has[6];
+    nbr_offsets(R, c.x, c.y, c.z, d, has);
+    double vx[6], vy[6], vz[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int64_t j = c.gi + d[k];
+        vx[k] = (double)ax[j];
+        vy[k] = (double)ay[j];
+        vz[k] = (double)az[j];
+    }
     sx = sy = sz = 0.0;
-    auto add = [&](int xx, int yy, int zz) {
-        const int64_t j = R.off + xx + (int64_t)Lx * (yy + (int64_t)Ly * zz);
-        sx += (double)ax[j];
-        sy += (double)ay[j];
-        sz += (double)az[j];
-    };
-    const int x = c.x, y = c.y, z = c.z;
-    if (pbc || x > 0) add(x > 0 ? x - 1 : Lx - 1, y, z);
-    if (pbc || x + 1 < Lx) add(x + 1 < Lx ? x + 1 : 0, y, z);
-    if (pbc || y > 0) add(x, y > 0 ? y - 1 : Ly - 1, z);
-    if (pbc || y + 1 < Ly) add(x, y + 1 < Ly ? y + 1 : 0, z);
-    if (pbc || z > 0) add(x, y, z > 0 ? z - 1 : Lz - 1);
-    if (pbc || z + 1 < Lz) add(x, y, z + 1 < Lz ? z + 1 : 0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        sx += has[k] ? vx[k] : 0.0;
+        sy += has[k] ? vy[k] : 0.0;
+        sz += has[k] ? vz[k] : 0.0;
+    }
 }
 
 template <typename T, int ANIS>
@@ -84,17 +92,25 @@ __device__ __forceinline__ void aniso_of(const RepDev& R, int64_t i, double& D, 
 
 // Block sum of five fp64 partials added to part[blockIdx.x][0..4] (each block
 // owns its row, so the running sums are deterministic; they are reduced once,
-// in block order, at the end of the backward pass).
+// in block order, at the end of the backward pass).  A butterfly within each
+// wave, then the wave sums in wave order: a fixed order with one barrier.
 __device__ __forceinline__ void block_sum5(double v[5], double* part) {
-    __shared__ double red[5][kAdjBlock];
-    for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = v[q];
+    constexpr int kWaves = kAdjBlock / 64;
+    __shared__ double red[5][kWaves];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[q] += __shfl_xor(v[q], o, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) red[q][w] = v[q];
     __syncthreads();
-    for (int o = kAdjBlock / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
-        __syncthreads();
+    if (threadIdx.x < 5) {
+        double t = red[threadIdx.x][0];
+        for (int k = 1; k < kWaves; ++k) t += red[threadIdx.x][k];
+        part[(int64_t)blockIdx.x * 5 + threadIdx.x] += t;
     }
-    if (threadIdx.x < 5) part[(int64_t)blockIdx.x * 5 + threadIdx.x] += red[threadIdx.x][0];
 }
 
 // Cotangent of the loss L = <c, s> + wE E(s) + wm . m(s) at the final state:
@@ -103,12 +119,11 @@ __device__ __forceinline__ void block_sum5(double v[5], double* part) {
 // dE/dD_i = -(s_i.e_i)^2.
 template <typename T, int ANIS>
 __global__ void __launch_bounds__(kAdjBlock)
-    adj_loss_kernel(const RepDev* reps, const int32_t* blk_rep, State s, State cot, State sbar,
-                    double wE, double wm0, double wm1, double wm2, double* gD, double* part) {
+    adj_loss_kernel(const RepDev R, State s, State cot, State sbar, double wE, double wm0,
+                    double wm1, double wm2, double* gD, double* part) {
     SiteA c;
     double v[5] = {0, 0, 0, 0, 0};
-    if (adj_site(reps, blk_rep, c)) {
-        const RepDev& R = reps[c.r];
+    if (adj_site(R, c)) {
         const T* sx = static_cast<const T*>(s.x);
         const T* sy = static_cast<const T*>(s.y);
         const T* sz = static_cast<const T*>(s.z);
@@ -154,21 +169,41 @@ __global__ void __launch_bounds__(kAdjBlock)
     block_sum5(v, part);
 }
 
+// What the reverse of f at a site reads: the stage input there, the sum of
+// its neighbours, the site's anisotropy and (per-site anisotropy) its running
+// dL/dD_i.  Loaded ahead of any store of the same launch, so that these loads
+// are not held behind the stores (the compiler cannot move a load across a
+// store it might alias).
+struct AIn {
+    double s0, s1, s2, n0, n1, n2, D, e0, e1, e2, gd;
+};
+
+template <typename T, int ANIS>
+__device__ __forceinline__ AIn load_a_in(const RepDev& R, const SiteA& c, const State& y,
+                                         const double* gD) {
+    AIn a;
+    a.gd = ANIS == ANIS_SITE ? gD[c.i] : 0.0;
+    const T* yx = static_cast<const T*>(y.x);
+    const T* yy = static_cast<const T*>(y.y);
+    const T* yz = static_cast<const T*>(y.z);
+    a.s0 = yx[c.gi];
+    a.s1 = yy[c.gi];
+    a.s2 = yz[c.gi];
+    nbr_sum<T>(R, c, yx, yy, yz, a.n0, a.n1, a.n2);
+    aniso_of<T, ANIS>(R, c.i, a.D, a.e0, a.e1, a.e2);
+    return a;
+}
+
 // Reverse of f at one site: u is the cotangent of f(y) there; writes q and
 // loc and adds the site's parameter terms to v (Hbar 0..2, Jbar 3, Dbar 4;
 // per-site Dbar goes to gD).
 template <typename T, bool PREC, int ANIS>
-__device__ __forceinline__ void adj_a_site(const RepDev& R, const SiteA& c, const State& y,
+__device__ __forceinline__ void adj_a_site(const RepDev& R, const SiteA& c, const AIn& a,
                                            double u0, double u1, double u2, const State& q,
                                            const State& loc, double* gD, double v[5]) {
-    const T* yx = static_cast<const T*>(y.x);
-    const T* yy = static_cast<const T*>(y.y);
-    const T* yz = static_cast<const T*>(y.z);
-    const double s0 = yx[c.gi], s1 = yy[c.gi], s2 = yz[c.gi];
-    double n0, n1, n2;
-    nbr_sum<T>(R, c, yx, yy, yz, n0, n1, n2);
-    double D, e0, e1, e2;
-    aniso_of<T, ANIS>(R, c.i, D, e0, e1, e2);
+    const double s0 = a.s0, s1 = a.s1, s2 = a.s2;
+    const double n0 = a.n0, n1 = a.n1, n2 = a.n2;
+    const double D = a.D, e0 = a.e0, e1 = a.e1, e2 = a.e2;
     const double se = s0 * e0 + s1 * e1 + s2 * e2;
     const double h0 = R.J * n0 + R.H[0] + 2.0 * D * se * e0;
     const double h1 = R.J * n1 + R.H[1] + 2.0 * D * se * e1;
@@ -204,7 +239,7 @@ __device__ __forceinline__ void adj_a_site(const RepDev& R, const SiteA& c, cons
     v[3] += q0 * n0 + q1 * n1 + q2 * n2;
     const double dD = 2.0 * se * (q0 * e0 + q1 * e1 + q2 * e2);
     if constexpr (ANIS == ANIS_SITE)
-        gD[c.i] += dD;
+        gD[c.i] = a.gd + dD;
     else
         v[4] += dD;
 }
@@ -213,15 +248,16 @@ __device__ __forceinline__ void adj_a_site(const RepDev& R, const SiteA& c, cons
 // parameter partials.
 template <typename T, bool PREC, int ANIS>
 __global__ void __launch_bounds__(kAdjBlock)
-    adj_pass_a(const RepDev* reps, const int32_t* blk_rep, State y, State kb, double scale,
-               State q, State loc, double* gD, double* part) {
+    adj_pass_a(const RepDev R, State y, State kb, double scale, State q, State loc, double* gD,
+               double* part) {
     SiteA c;
     double v[5] = {0, 0, 0, 0, 0};
-    if (adj_site(reps, blk_rep, c)) {
+    if (adj_site(R, c)) {
         const double u0 = scale * (double)static_cast<const T*>(kb.x)[c.gi];
         const double u1 = scale * (double)static_cast<const T*>(kb.y)[c.gi];
         const double u2 = scale * (double)static_cast<const T*>(kb.z)[c.gi];
-        adj_a_site<T, PREC, ANIS>(reps[c.r], c, y, u0, u1, u2, q, loc, gD, v);
+        adj_a_site<T, PREC, ANIS>(R, c, load_a_in<T, ANIS>(R, c, y, gD), u0, u1, u2, q, loc, gD,
+                                  v);
     }
     block_sum5(v, part);
 }
@@ -230,18 +266,18 @@ __global__ void __launch_bounds__(kAdjBlock)
 // RK4 cotangents (stage 4: xbar = sbar + ybar, kb = sbar/3 + ybar; stage 3:
 // xbar += ybar, kb = sbar/3 + ybar/2; stage 2: xbar += ybar,
 // kb = sbar/6 + ybar/2; stage 1: xbar += ybar).  Returns the new kb at the
-// site as stored (stages 4..2).
+// site as stored (stages 4..2), or at stage 1 the finished xbar as stored:
+// the cotangent of the step's input, which is the output of the step before.
 template <typename T, int ANIS>
 __device__ __forceinline__ void adj_b_site(const RepDev& R, const SiteA& c, const State& q,
                                            const State& loc, const State& sbar, const State& xbar,
-                                           const State& kb, int stage, T& kb0, T& kb1, T& kb2) {
+                                           const State& kb, int stage, double D, double e0,
+                                           double e1, double e2, T& kb0, T& kb1, T& kb2) {
     const T* qx = static_cast<const T*>(q.x);
     const T* qy = static_cast<const T*>(q.y);
     const T* qz = static_cast<const T*>(q.z);
     double n0, n1, n2;
     nbr_sum<T>(R, c, qx, qy, qz, n0, n1, n2);
-    double D, e0, e1, e2;
-    aniso_of<T, ANIS>(R, c.i, D, e0, e1, e2);
     const double q0 = qx[c.gi], q1 = qy[c.gi], q2 = qz[c.gi];
     const double eq = e0 * q0 + e1 * q1 + e2 * q2;
     const int64_t g = c.gi;
@@ -259,9 +295,15 @@ __device__ __forceinline__ void adj_b_site(const RepDev& R, const SiteA& c, cons
         xb1[g] = (T)(b1 + y1);
         xb2[g] = (T)(b2 + y2);
     } else {
-        xb0[g] = (T)((double)xb0[g] + y0);
-        xb1[g] = (T)((double)xb1[g] + y1);
-        xb2[g] = (T)((double)xb2[g] + y2);
+        const T x0 = (T)((double)xb0[g] + y0);
+        const T x1 = (T)((double)xb1[g] + y1);
+        const T x2 = (T)((double)xb2[g] + y2);
+        xb0[g] = x0;
+        xb1[g] = x1;
+        xb2[g] = x2;
+        kb0 = x0;
+        kb1 = x1;
+        kb2 = x2;
     }
     if (stage == 4) {
         kb0 = (T)(b0 / 3.0 + y0);
@@ -286,29 +328,32 @@ __device__ __forceinline__ void adj_b_site(const RepDev& R, const SiteA& c, cons
 // Pass B of one stage alone (the last stage of a step's reverse).
 template <typename T, int ANIS>
 __global__ void __launch_bounds__(kAdjBlock)
-    adj_pass_b(const RepDev* reps, const int32_t* blk_rep, State q, State loc, State sbar,
-               State xbar, State kb, int stage) {
+    adj_pass_b(const RepDev R, State q, State loc, State sbar, State xbar, State kb, int stage) {
     SiteA c;
-    if (!adj_site(reps, blk_rep, c)) return;
+    if (!adj_site(R, c)) return;
     T k0, k1, k2;
-    adj_b_site<T, ANIS>(reps[c.r], c, q, loc, sbar, xbar, kb, stage, k0, k1, k2);
+    double D, e0, e1, e2;
+    aniso_of<T, ANIS>(R, c.i, D, e0, e1, e2);
+    adj_b_site<T, ANIS>(R, c, q, loc, sbar, xbar, kb, stage, D, e0, e1, e2, k0, k1, k2);
 }
 
 // Pass B of stage s followed by pass A of stage s - 1 at the same site: the
 // cotangent of k_{s-1} is pointwise in B's result, so one launch does both
-// (q, loc of stage s are read; qn, locn of stage s - 1 are written).
+// (q, loc of stage s are read; qn, locn of stage s - 1 are written).  With
+// stage = 1 the pass A is stage 4 of the step before (y its stage-4 input,
+// scale dt/6), whose k4 cotangent is the finished xbar / 6.
 template <typename T, bool PREC, int ANIS>
 __global__ void __launch_bounds__(kAdjBlock)
-    adj_pass_ba(const RepDev* reps, const int32_t* blk_rep, State q, State loc, State sbar,
-                State xbar, State kb, int stage, State y, double scale, State qn, State locn,
-                double* gD, double* part) {
+    adj_pass_ba(const RepDev R, State q, State loc, State sbar, State xbar, State kb, int stage,
+                State y, double scale, State qn, State locn, double* gD, double* part) {
     SiteA c;
     double v[5] = {0, 0, 0, 0, 0};
-    if (adj_site(reps, blk_rep, c)) {
-        const RepDev& R = reps[c.r];
+    if (adj_site(R, c)) {
         T k0, k1, k2;
-        adj_b_site<T, ANIS>(R, c, q, loc, sbar, xbar, kb, stage, k0, k1, k2);
-        adj_a_site<T, PREC, ANIS>(R, c, y, scale * (double)k0, scale * (double)k1,
+        const AIn a = load_a_in<T, ANIS>(R, c, y, gD);
+        adj_b_site<T, ANIS>(R, c, q, loc, sbar, xbar, kb, stage, a.D, a.e0, a.e1, a.e2, k0, k1,
+                            k2);
+        adj_a_site<T, PREC, ANIS>(R, c, a, scale * (double)k0, scale * (double)k1,
                                   scale * (double)k2, qn, locn, gD, v);
     }
     block_sum5(v, part);
@@ -334,11 +379,9 @@ __global__ void __launch_bounds__(256) adj_reduce5(const double* part, int nblk,
 // R^T being the rotation by -phi about the same axis.
 template <typename T>
 __global__ void __launch_bounds__(kAdjBlock)
-    adj_kick_kernel(const RepDev* reps, const int32_t* blk_rep, State spre, State sbar, uint64_t k,
-                    double sigma_override) {
+    adj_kick_kernel(const RepDev R, State spre, State sbar, uint64_t k, double sigma_override) {
     SiteA c;
-    if (!adj_site(reps, blk_rep, c)) return;
-    const RepDev& R = reps[c.r];
+    if (!adj_site(R, c)) return;
     const T sg = (T)(sigma_override >= 0.0 ? sigma_override : R.sigma);
     const uint4 w = philox_site(R.seed, (uint32_t)c.i, (uint32_t)(k + R.kbase), R.rid, 0u);
     T G[3];
@@ -383,22 +426,22 @@ __global__ void __launch_bounds__(kAdjBlock)
 
 // ------------------------------------------------------------ launchers ----
 template <typename T>
-static hipError_t loss_t(int anis, const RepDev* reps, const int32_t* blk, int nblk, State s,
+static hipError_t loss_t(int anis, const RepDev& R, int nblk, State s,
                          State cot, State sbar, double wE, const double wm[3], double* gD,
                          double* part, hipStream_t st) {
     switch (anis) {
-        case ANIS_NONE: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, s, cot, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
-        case ANIS_SITE: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, s, cot, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
-        default: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, s, cot, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
+        case ANIS_NONE: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, R, s, cot, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
+        case ANIS_SITE: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, R, s, cot, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
+        default: hipLaunchKernelGGL((adj_loss_kernel<T, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, R, s, cot, sbar, wE, wm[0], wm[1], wm[2], gD, part); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_adj_loss(int prec, int anis, const RepDev* reps, const int32_t* blk, int nblk,
+hipError_t launch_adj_loss(int prec, int anis, const RepDev& R, int nblk,
                            State s, State cot, State sbar, double wE, const double wm[3],
                            double* gD, double* part, hipStream_t st) {
-    return prec == 0 ? loss_t<double>(anis, reps, blk, nblk, s, cot, sbar, wE, wm, gD, part, st)
-                     : loss_t<float>(anis, reps, blk, nblk, s, cot, sbar, wE, wm, gD, part, st);
+    return prec == 0 ? loss_t<double>(anis, R, nblk, s, cot, sbar, wE, wm, gD, part, st)
+                     : loss_t<float>(anis, R, nblk, s, cot, sbar, wE, wm, gD, part, st);
 }
 
 hipError_t launch_adj_finish(const double* part, int nblk, double* acc, hipStream_t st) {
@@ -407,33 +450,33 @@ hipError_t launch_adj_finish(const double* part, int nblk, double* acc, hipStrea
 }
 
 template <typename T, bool PREC>
-static void pass_a_t(int anis, const RepDev* reps, const int32_t* blk, int nblk, State y, State kb,
+static void pass_a_t(int anis, const RepDev& R, int nblk, State y, State kb,
                      double scale, State q, State loc, double* gD, double* part, hipStream_t st) {
     switch (anis) {
-        case ANIS_NONE: hipLaunchKernelGGL((adj_pass_a<T, PREC, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, y, kb, scale, q, loc, gD, part); break;
-        case ANIS_SITE: hipLaunchKernelGGL((adj_pass_a<T, PREC, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, y, kb, scale, q, loc, gD, part); break;
-        default: hipLaunchKernelGGL((adj_pass_a<T, PREC, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, y, kb, scale, q, loc, gD, part); break;
+        case ANIS_NONE: hipLaunchKernelGGL((adj_pass_a<T, PREC, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, R, y, kb, scale, q, loc, gD, part); break;
+        case ANIS_SITE: hipLaunchKernelGGL((adj_pass_a<T, PREC, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, R, y, kb, scale, q, loc, gD, part); break;
+        default: hipLaunchKernelGGL((adj_pass_a<T, PREC, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, R, y, kb, scale, q, loc, gD, part); break;
     }
 }
 
 template <typename T>
-static void pass_b_t(int anis, const RepDev* reps, const int32_t* blk, int nblk, State q, State loc,
+static void pass_b_t(int anis, const RepDev& R, int nblk, State q, State loc,
                      State sbar, State xbar, State kb, int stage, hipStream_t st) {
     switch (anis) {
-        case ANIS_NONE: hipLaunchKernelGGL((adj_pass_b<T, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, q, loc, sbar, xbar, kb, stage); break;
-        case ANIS_SITE: hipLaunchKernelGGL((adj_pass_b<T, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, q, loc, sbar, xbar, kb, stage); break;
-        default: hipLaunchKernelGGL((adj_pass_b<T, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, q, loc, sbar, xbar, kb, stage); break;
+        case ANIS_NONE: hipLaunchKernelGGL((adj_pass_b<T, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, R, q, loc, sbar, xbar, kb, stage); break;
+        case ANIS_SITE: hipLaunchKernelGGL((adj_pass_b<T, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, R, q, loc, sbar, xbar, kb, stage); break;
+        default: hipLaunchKernelGGL((adj_pass_b<T, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, R, q, loc, sbar, xbar, kb, stage); break;
     }
 }
 
 template <typename T, bool PREC>
-static void pass_ba_t(int anis, const RepDev* reps, const int32_t* blk, int nblk, State q, State loc,
+static void pass_ba_t(int anis, const RepDev& R, int nblk, State q, State loc,
                       State sbar, State xbar, State kb, int stage, State y, double scale, State qn,
                       State locn, double* gD, double* part, hipStream_t st) {
     switch (anis) {
-        case ANIS_NONE: hipLaunchKernelGGL((adj_pass_ba<T, PREC, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, q, loc, sbar, xbar, kb, stage, y, scale, qn, locn, gD, part); break;
-        case ANIS_SITE: hipLaunchKernelGGL((adj_pass_ba<T, PREC, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, q, loc, sbar, xbar, kb, stage, y, scale, qn, locn, gD, part); break;
-        default: hipLaunchKernelGGL((adj_pass_ba<T, PREC, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, q, loc, sbar, xbar, kb, stage, y, scale, qn, locn, gD, part); break;
+        case ANIS_NONE: hipLaunchKernelGGL((adj_pass_ba<T, PREC, ANIS_NONE>), dim3(nblk), dim3(kAdjBlock), 0, st, R, q, loc, sbar, xbar, kb, stage, y, scale, qn, locn, gD, part); break;
+        case ANIS_SITE: hipLaunchKernelGGL((adj_pass_ba<T, PREC, ANIS_SITE>), dim3(nblk), dim3(kAdjBlock), 0, st, R, q, loc, sbar, xbar, kb, stage, y, scale, qn, locn, gD, part); break;
+        default: hipLaunchKernelGGL((adj_pass_ba<T, PREC, ANIS_AXIS>), dim3(nblk), dim3(kAdjBlock), 0, st, R, q, loc, sbar, xbar, kb, stage, y, scale, qn, locn, gD, part); break;
     }
 }
 
@@ -442,19 +485,21 @@ static void pass_ba_t(int anis, const RepDev* reps, const int32_t* blk, int nblk
 // Launches: A of stage 4, then B of stage s fused with A of stage s - 1 for
 // s = 4, 3, 2, then B of stage 1; q/loc alternate between two buffers.
 // Parameter partials accumulate in part (reduced by launch_adj_finish).
-hipError_t launch_adj_step(int prec, int precession, int anis, const RepDev* reps,
-                           const int32_t* blk, int nblk, const State y[4], double dt, State sbar,
+hipError_t launch_adj_step(int prec, int precession, int anis, const RepDev& R, int nblk, const State y[4], double dt, State sbar,
                            State xbar, State kb, const State q[2], const State loc[2], double* gD,
-                           double* part, hipStream_t st) {
-    if (prec == 0) {
-        if (precession) pass_a_t<double, true>(anis, reps, blk, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
-        else pass_a_t<double, false>(anis, reps, blk, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
-    } else {
-        if (precession) pass_a_t<float, true>(anis, reps, blk, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
-        else pass_a_t<float, false>(anis, reps, blk, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
+                           double* part, bool a4, hipStream_t st) {
+    hipError_t e;
+    if (a4) {
+        if (prec == 0) {
+            if (precession) pass_a_t<double, true>(anis, R, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
+            else pass_a_t<double, false>(anis, R, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
+        } else {
+            if (precession) pass_a_t<float, true>(anis, R, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
+            else pass_a_t<float, false>(anis, R, nblk, y[3], sbar, dt / 6.0, q[0], loc[0], gD, part, st);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     int cur = 0;
     for (int s = 4; s >= 2; --s) {
         const State& qi = q[cur];
@@ -462,27 +507,45 @@ hipError_t launch_adj_step(int prec, int precession, int anis, const RepDev* rep
         const State& qo = q[cur ^ 1];
         const State& lo = loc[cur ^ 1];
         if (prec == 0) {
-            if (precession) pass_ba_t<double, true>(anis, reps, blk, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
-            else pass_ba_t<double, false>(anis, reps, blk, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
+            if (precession) pass_ba_t<double, true>(anis, R, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
+            else pass_ba_t<double, false>(anis, R, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
         } else {
-            if (precession) pass_ba_t<float, true>(anis, reps, blk, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
-            else pass_ba_t<float, false>(anis, reps, blk, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
+            if (precession) pass_ba_t<float, true>(anis, R, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
+            else pass_ba_t<float, false>(anis, R, nblk, qi, li, sbar, xbar, kb, s, y[s - 2], dt, qo, lo, gD, part, st);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         cur ^= 1;
     }
-    if (prec == 0) pass_b_t<double>(anis, reps, blk, nblk, q[cur], loc[cur], sbar, xbar, kb, 1, st);
-    else pass_b_t<float>(anis, reps, blk, nblk, q[cur], loc[cur], sbar, xbar, kb, 1, st);
+    return hipSuccess;
+}
+
+hipError_t launch_adj_b1(int prec, int precession, int anis, const RepDev& R, int nblk,
+                         const State* y4prev, double dt, State sbar, State xbar, State kb,
+                         const State q[2], const State loc[2], double* gD, double* part,
+                         hipStream_t st) {
+    if (!y4prev) {
+        if (prec == 0) pass_b_t<double>(anis, R, nblk, q[1], loc[1], sbar, xbar, kb, 1, st);
+        else pass_b_t<float>(anis, R, nblk, q[1], loc[1], sbar, xbar, kb, 1, st);
+        return hipGetLastError();
+    }
+    const double sc = dt / 6.0;
+    if (prec == 0) {
+        if (precession) pass_ba_t<double, true>(anis, R, nblk, q[1], loc[1], sbar, xbar, kb, 1, *y4prev, sc, q[0], loc[0], gD, part, st);
+        else pass_ba_t<double, false>(anis, R, nblk, q[1], loc[1], sbar, xbar, kb, 1, *y4prev, sc, q[0], loc[0], gD, part, st);
+    } else {
+        if (precession) pass_ba_t<float, true>(anis, R, nblk, q[1], loc[1], sbar, xbar, kb, 1, *y4prev, sc, q[0], loc[0], gD, part, st);
+        else pass_ba_t<float, false>(anis, R, nblk, q[1], loc[1], sbar, xbar, kb, 1, *y4prev, sc, q[0], loc[0], gD, part, st);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_adj_kick(int prec, const RepDev* reps, const int32_t* blk, int nblk, State spre,
+hipError_t launch_adj_kick(int prec, const RepDev& R, int nblk, State spre,
                            State sbar, uint64_t k, double sigma_override, hipStream_t st) {
     if (prec == 0)
-        hipLaunchKernelGGL(adj_kick_kernel<double>, dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, spre, sbar, k, sigma_override);
+        hipLaunchKernelGGL(adj_kick_kernel<double>, dim3(nblk), dim3(kAdjBlock), 0, st, R, spre, sbar, k, sigma_override);
     else
-        hipLaunchKernelGGL(adj_kick_kernel<float>, dim3(nblk), dim3(kAdjBlock), 0, st, reps, blk, spre, sbar, k, sigma_override);
+        hipLaunchKernelGGL(adj_kick_kernel<float>, dim3(nblk), dim3(kAdjBlock), 0, st, R, spre, sbar, k, sigma_override);
     return hipGetLastError();
 }
 

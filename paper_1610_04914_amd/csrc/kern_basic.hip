@@ -568,23 +568,27 @@ __device__ __forceinline__ void site_k(const RepDev& R, const SiteCtx& c, const 
     const int64_t N = (int64_t)Lx * Ly * Lz;
     int x, y, z;
     site_xyz(c.i, Lx, Ly, x, y, z);
-    const bool pbc = R.bc == 0;
     const T* yx = static_cast<const T*>(yin.x);
     const T* yy = static_cast<const T*>(yin.y);
     const T* yz = static_cast<const T*>(yin.z);
+    int64_t d[6];
+    bool has[6];
+    nbr_offsets(R, x, y, z, d, has);
+    T vx[6], vy[6], vz[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        vx[k] = yx[c.gi + d[k]];
+        vy[k] = yy[c.gi + d[k]];
+        vz[k] = yz[c.gi + d[k]];
+    }
+    // adding zero for a missing neighbour leaves the sum's bits unchanged
     T nx = 0, ny = 0, nz = 0;
-    auto add = [&](int xx, int yy_, int zz) {
-        const int64_t j = R.off + xx + (int64_t)Lx * (yy_ + (int64_t)Ly * zz);
-        nx += yx[j];
-        ny += yy[j];
-        nz += yz[j];
-    };
-    if (pbc || x > 0) add(x > 0 ? x - 1 : Lx - 1, y, z);
-    if (pbc || x + 1 < Lx) add(x + 1 < Lx ? x + 1 : 0, y, z);
-    if (pbc || y > 0) add(x, y > 0 ? y - 1 : Ly - 1, z);
-    if (pbc || y + 1 < Ly) add(x, y + 1 < Ly ? y + 1 : 0, z);
-    if (pbc || z > 0) add(x, y, z > 0 ? z - 1 : Lz - 1);
-    if (pbc || z + 1 < Lz) add(x, y, z + 1 < Lz ? z + 1 : 0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        nx += has[k] ? vx[k] : T(0);
+        ny += has[k] ? vy[k] : T(0);
+        nz += has[k] ? vz[k] : T(0);
+    }
     const T sx = yx[c.gi], sy = yy[c.gi], sz = yz[c.gi];
     const Coef<T> C = load_coef<T>(R);
     T Di = 0, ex = 0, ey = 0, ez = 0;

@@ -1184,11 +1184,15 @@ extern "C" lll_status lll_autotune(lll_lattice* L, const lll_params* p, const ch
 // every ckpt_every-th operation (an operation is one RK4 step or one kick)
 // and the final state; the backward pass walks the checkpoint blocks in
 // reverse, recomputes each block while keeping the stage inputs of every
-// step, and runs the reverse stages and kick reverses.  Work buffers of the
-// backward pass live in the lattice's engine and are reused by later calls;
-// a destroyed tape hands its checkpoint buffer back to the lattice, so a
-// forward/backward cycle of the same length allocates nothing after the
-// first.
+// step, and runs the reverse stages and kick reverses.  With ckpt_every = 0
+// (full tape) the forward itself keeps the stage inputs of every step, in
+// the same slot layout as a recomputed block that spans the whole run, and
+// the backward recomputes nothing: a trade of memory (four states per
+// operation) for one forward pass, cheap where the run fits in HBM many
+// times over.  Work buffers of the backward pass live in the lattice's
+// engine and are reused by later calls; a destroyed tape hands its
+// checkpoint buffer back to the lattice, so a forward/backward cycle of the
+// same length allocates nothing after the first.
 namespace {
 struct TmpAlloc {
     std::vector<void*> ptrs;
@@ -1229,7 +1233,9 @@ struct lll_tape {
     std::vector<int8_t> op;        // 0 = RK4 step, 1 = kick
     std::vector<uint64_t> opk;     // pulse index of each operation
     int64_t K = 1, nblocks = 0;
-    void* ck = nullptr;            // [nblocks + 1][3][N]: checkpoints, then s_T
+    bool full = false;             // ckpt_every = 0: every step's stage inputs kept
+    void* ck = nullptr;            // [nblocks + 1][3][N]: checkpoints, then s_T; full
+                                   // tape: [4 nops + 1][3][N], x y2 y3 y4 per operation
     size_t ck_bytes = 0;
 };
 
@@ -1241,14 +1247,16 @@ lll_lattice::~lll_lattice() {
         if (p) (void)hipFree(p);
 }
 
-// Adjoint work buffers of an engine: block buffer (4K + 1 states), ten
-// scratch states, parameter partials, their sum, the loss observables and
-// the kick maxima of recomputed kicks (kept apart from the lattice's own).
+// Adjoint work buffers of an engine: block buffer (4K + 1 states; none for a
+// full tape, K = 0), ten scratch states, parameter partials, their sum, the
+// loss observables and the kick maxima of recomputed kicks (kept apart from
+// the lattice's own).
 static lll_status ensure_adj_work(lll_lattice* L, int64_t K) {
     Engine& E = L->E;
     const size_t cb = (size_t)E.nsites * E.esz;
     lll_status s;
-    if ((s = ensure_buf(&L->adj_bb, &L->adj_bb_bytes, 3 * cb * (size_t)(4 * K + 1))) != LLL_OK)
+    if (K > 0 &&
+        (s = ensure_buf(&L->adj_bb, &L->adj_bb_bytes, 3 * cb * (size_t)(4 * K + 1))) != LLL_OK)
         return s;
     if ((s = ensure_buf(&L->adj_sc, &L->adj_sc_bytes, 3 * cb * 10)) != LLL_OK) return s;
     const size_t small = sizeof(double) * (5 * (size_t)E.nblk + 5 + 8) +
@@ -1287,9 +1295,9 @@ static lll_status tape_forward(lll_lattice* L, lll_tape* T, uint64_t first_pulse
         for (int64_t a = 0; a < n2; ++a) { T->op.push_back(0); T->opk.push_back(k); }
     }
     const int64_t nops = (int64_t)T->op.size();
-    T->nblocks = (nops + T->K - 1) / T->K;
+    T->nblocks = T->full ? 1 : (nops + T->K - 1) / T->K;
     const size_t cb = (size_t)E.nsites * E.esz;
-    const size_t need = 3 * cb * (size_t)(T->nblocks + 1);
+    const size_t need = 3 * cb * (size_t)(T->full ? 4 * nops + 1 : T->nblocks + 1);
     if (L->ck_pool && L->ck_pool_bytes >= need) {
         T->ck = L->ck_pool;
         T->ck_bytes = L->ck_pool_bytes;
@@ -1305,6 +1313,32 @@ static lll_status tape_forward(lll_lattice* L, lll_tape* T, uint64_t first_pulse
     if ((s = settle(E)) != LLL_OK) return s;
     E.carried = false;
     const int pr = E.prec;
+    if (T->full) {
+        // slot j holds x, y2, y3, y4 of operation j; slot nops holds s_T
+        auto slot = [&](int64_t j, int c) { return state_at(T->ck, cb, 4 * j + c); };
+        if (E.variant != 0 && (s = ensure_tiles(E)) != LLL_OK) return s;
+        if (E.variant == 0 && (s = ensure_adj_work(L, 0)) != LLL_OK) return s;
+        const int pc = E.precession, an = E.anis;
+        HIP_TRY(launch_copy(pr, slot(0, 0), E.s, E.nsites, E.st));
+        for (int64_t j = 0; j < nops; ++j) {
+            const State nx = slot(j + 1, 0);
+            if (T->op[j] == 0 && E.variant != 0) {
+                const State ys[3] = {slot(j, 1), slot(j, 2), slot(j, 3)};
+                HIP_TRY(launch_step_fused_stages(pr, pc, an, E.variant, eff_bz(E), E.dreps,
+                                                 E.d_tiles, E.ntiles, slot(j, 0), nx, ys, E.st));
+            } else if (T->op[j] == 0) {
+                HIP_TRY(launch_rk4_stages(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, slot(j, 0),
+                                          slot(j, 1), slot(j, 2), slot(j, 3),
+                                          state_at(L->adj_sc, cb, 2), nx, E.st));
+            } else {
+                HIP_TRY(launch_copy(pr, nx, slot(j, 0), E.nsites, E.st));
+                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, T->opk[j], -1.0, kd,
+                                    E.st));
+            }
+        }
+        HIP_TRY(launch_copy(pr, E.s, slot(nops, 0), E.nsites, E.st));
+        return LLL_OK;
+    }
     for (int64_t j = 0; j < nops;) {
         if (j % T->K == 0)
             HIP_TRY(launch_copy(pr, state_at(T->ck, cb, j / T->K), cur_state(E), E.nsites, E.st));
@@ -1333,11 +1367,11 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
     lll_status s = lattice_params(L, &T->p, true);
     if (s != LLL_OK) return s;
     Engine& E = L->E;
-    if ((s = ensure_adj_work(L, T->K)) != LLL_OK) return s;
+    if ((s = ensure_adj_work(L, T->full ? 0 : T->K)) != LLL_OK) return s;
     if (E.variant != 0 && (s = ensure_tiles(E)) != LLL_OK) return s;
     const size_t cb = (size_t)E.nsites * E.esz;
     const int64_t nops = (int64_t)T->op.size();
-    const int64_t K = T->K;
+    const int64_t K = T->full ? nops : T->K;
     double* part = (double*)L->adj_small;
     double* acc5 = part + 5 * (size_t)E.nblk;
     double* res8 = acc5 + 5;
@@ -1351,24 +1385,37 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
     (void)cur;
     (void)nxt;
     // block buffer: slot j holds x, y2, y3, y4 of operation j of the block
-    auto slot = [&](int64_t j, int c) { return state_at(L->adj_bb, cb, 4 * j + c); };
+    // (the full tape is one block that the forward has already filled)
+    void* const bb = T->full ? T->ck : L->adj_bb;
+    auto slot = [&](int64_t j, int c) { return state_at(bb, cb, 4 * j + c); };
     const bool site = T->p.D_site != nullptr;
     double* gD = site ? (double*)g_D : nullptr;
     HIP_TRY(hipMemsetAsync(L->adj_small, 0, sizeof(double) * (5 * (size_t)E.nblk + 5), E.st));
     if (site) HIP_TRY(hipMemsetAsync(gD, 0, sizeof(double) * E.nsites, E.st));
     const int pr = E.prec, pc = E.precession, an = E.anis;
-    const State sT = state_at(T->ck, cb, T->nblocks);
+    const State sT = T->full ? slot(nops, 0) : state_at(T->ck, cb, T->nblocks);
     const State cs = cot ? State{const_cast<void*>(cot), (char*)cot + cb, (char*)cot + 2 * cb}
                          : State{};
     HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, sT, E.d_partials, res8, nullptr,
                        0, E.st));
-    HIP_TRY(launch_adj_loss(pr, an, E.dreps, E.d_blk_rep, E.nblk, sT, cs, sbar, wE, wm, gD, part,
+    HIP_TRY(launch_adj_loss(pr, an, E.hreps[0], E.nblk, sT, cs, sbar, wE, wm, gD, part,
                             E.st));
     const double dt = T->p.dt;
+    // Stage 1's pass B of the last reversed step waits for the next operation
+    // to reverse: when that is a step, one launch also does its stage-4 pass A
+    // (pointwise in the finished cotangent), after its block is recomputed.
+    bool pend_b1 = false;
+    auto finish_b1 = [&](const State* y4prev) -> lll_status {
+        HIP_TRY(launch_adj_b1(pr, pc, an, E.hreps[0], E.nblk, y4prev, dt, sbar, xbar,
+                              kb, q2, loc2, gD, part, E.st));
+        std::swap(sbar, xbar);
+        pend_b1 = false;
+        return LLL_OK;
+    };
     for (int64_t b = T->nblocks - 1; b >= 0; --b) {
         const int64_t j0 = b * K, j1 = std::min(j0 + K, nops);
-        HIP_TRY(launch_copy(pr, slot(0, 0), state_at(T->ck, cb, b), E.nsites, E.st));
-        for (int64_t j = j0; j < j1; ++j) {
+        if (!T->full) HIP_TRY(launch_copy(pr, slot(0, 0), state_at(T->ck, cb, b), E.nsites, E.st));
+        for (int64_t j = T->full ? j1 : j0; j < j1; ++j) {
             const int64_t sl = j - j0;
             State nx = slot(sl + 1, 0);
             if (T->op[j] == 0 && E.variant != 0) {  // one fused launch: x', y2, y3, y4
@@ -1387,15 +1434,19 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
             const int64_t sl = j - j0;
             if (T->op[j] == 0) {
                 const State y[4] = {slot(sl, 0), slot(sl, 1), slot(sl, 2), slot(sl, 3)};
-                HIP_TRY(launch_adj_step(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, y, dt, sbar, xbar,
-                                        kb, q2, loc2, gD, part, E.st));
-                std::swap(sbar, xbar);
+                const bool a4 = !pend_b1;
+                if (pend_b1 && (s = finish_b1(&y[3])) != LLL_OK) return s;
+                HIP_TRY(launch_adj_step(pr, pc, an, E.hreps[0], E.nblk, y, dt, sbar, xbar,
+                                        kb, q2, loc2, gD, part, a4, E.st));
+                pend_b1 = true;
             } else {
-                HIP_TRY(launch_adj_kick(pr, E.dreps, E.d_blk_rep, E.nblk, slot(sl, 0), sbar,
+                if (pend_b1 && (s = finish_b1(nullptr)) != LLL_OK) return s;
+                HIP_TRY(launch_adj_kick(pr, E.hreps[0], E.nblk, slot(sl, 0), sbar,
                                         T->opk[j], -1.0, E.st));
             }
         }
     }
+    if (pend_b1 && (s = finish_b1(nullptr)) != LLL_OK) return s;
     HIP_TRY(launch_adj_finish(part, E.nblk, acc5, E.st));
     if (g_s0) {
         State dst{g_s0, (char*)g_s0 + cb, (char*)g_s0 + 2 * cb};
@@ -1418,7 +1469,7 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
 static lll_status tape_check_args(lll_lattice* L, const lll_params* p, int64_t n_pulses,
                                   int32_t ckpt_every) {
     if (!L || !p) return set_err(LLL_EINVAL, "NULL argument");
-    if (n_pulses < 0 || ckpt_every < 1) return set_err(LLL_EINVAL, "bad n_pulses or ckpt_every");
+    if (n_pulses < 0 || ckpt_every < 0) return set_err(LLL_EINVAL, "bad n_pulses or ckpt_every");
     if (p->integrator != LLL_RK4)
         return set_err(LLL_EUNSUPPORTED, "the adjoint is implemented for LLL_RK4 only");
     return lattice_params(L, p, true);
@@ -1433,7 +1484,8 @@ extern "C" lll_status lll_adjoint_forward(lll_lattice* L, const lll_params* p, u
     lll_tape* T = new lll_tape();
     T->lat = L;
     T->p = *p;
-    T->K = ckpt_every;
+    T->K = ckpt_every > 0 ? ckpt_every : 1;
+    T->full = ckpt_every == 0;
     if ((s = tape_forward(L, T, first_pulse, n_pulses, L->E.d_kickdev)) != LLL_OK) {
         tape_release_ck(T);
         delete T;
@@ -1475,7 +1527,8 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
     lll_tape T;
     T.lat = L;
     T.p = *p;
-    T.K = ckpt_every;
+    T.K = ckpt_every > 0 ? ckpt_every : 1;
+    T.full = ckpt_every == 0;
     // the forward's kicks go to the scratch maxima: the state is restored
     unsigned long long* kd =
         (unsigned long long*)((double*)L->adj_small + 5 * (size_t)L->E.nblk + 5 + 8);

@@ -157,16 +157,25 @@ hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* r
 // part: [nblk][5] fp64 running partials {Hbar x3, Jbar, Dbar} (zeroed by the
 // caller, added to by every pass, reduced in block order into acc[5] by
 // launch_adj_finish); gD: per-site fp64 Dbar_i (per-site anisotropy) or unused.
+// Adjoint launchers take the lattice's descriptor by value (host copy; the
+// adjoint runs on one lattice).
 // cot: cotangent of s added to the loss's own (null pointers: none).
-hipError_t launch_adj_loss(int prec, int anis, const RepDev* reps, const int32_t* blk, int nblk,
+hipError_t launch_adj_loss(int prec, int anis, const RepDev& R, int nblk,
                            State s, State cot, State sbar, double wE, const double wm[3],
                            double* gD, double* part, hipStream_t st);
-// q[2], loc[2]: two scratch pairs used alternately.
-hipError_t launch_adj_step(int prec, int precession, int anis, const RepDev* reps,
-                           const int32_t* blk, int nblk, const State y[4], double dt, State sbar,
+// Reverse of one RK4 step up to its last stage: pass A of stage 4 (unless a4
+// is false: then a launch_adj_b1 of the step after has done it), then passes
+// B + A of stages 4..2.  q[2], loc[2]: two scratch pairs used alternately;
+// stage 4's q is q[0], stage 1's q[1].
+hipError_t launch_adj_step(int prec, int precession, int anis, const RepDev& R, int nblk, const State y[4], double dt, State sbar,
                            State xbar, State kb, const State q[2], const State loc[2], double* gD,
-                           double* part, hipStream_t st);
+                           double* part, bool a4, hipStream_t st);
+// Pass B of stage 1, which finishes xbar; with y4prev (the stage-4 input of
+// the step before) the same launch also does that step's pass A of stage 4.
+hipError_t launch_adj_b1(int prec, int precession, int anis, const RepDev& R, int nblk, const State* y4prev, double dt, State sbar,
+                         State xbar, State kb, const State q[2], const State loc[2], double* gD,
+                         double* part, hipStream_t st);
 hipError_t launch_adj_finish(const double* part, int nblk, double* acc, hipStream_t st);
-hipError_t launch_adj_kick(int prec, const RepDev* reps, const int32_t* blk, int nblk, State spre,
+hipError_t launch_adj_kick(int prec, const RepDev& R, int nblk, State spre,
                            State sbar, uint64_t k, double sigma_override, hipStream_t st);
 }  // namespace lll

@@ -194,6 +194,8 @@ def test_status_codes_and_constants_match_header(P):
         assert getattr(P, k) == v, k
     lvl = float(re.search(r"#define LLL_NORM_WARN_LEVEL\s+([0-9.eE+-]+)", txt).group(1))
     assert P.NORM_WARN_LEVEL == lvl
+    full = int(re.search(r"#define LLL_TAPE_FULL\s+(\d+)", txt).group(1))
+    assert P.TAPE_FULL == full
 
 
 def test_site_arrays_rejected_before_any_launch():

@@ -114,6 +114,65 @@ def test_adjoint_every_step_configuration(P, prec, case):
         lat.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES[:3])
+def test_full_tape_matches_checkpointed(P, prec, case):
+    """A full tape (every step's stage inputs kept by the forward, nothing
+    recomputed) gives the checkpointed tape's gradients and final state bit
+    for bit with every step configuration, and the oracle's within the bar;
+    the forward of a full tape equals lll_run bit for bit."""
+    shape, bc, precession, site, dt, Dt, npl, ck = case
+    N = int(np.prod(shape))
+    s0 = _rounded(inputs.near_ordered_spins(N, 33), prec)
+    D, e = inputs.site_anisotropy(N, 34)
+    D, e = _rounded(D, prec), _rounded(e, prec)
+    kw = dict(J=0.9, H=(0.03, 0.01, 0.15), lam=0.04, T=0.6, dt=dt, Dt=Dt, precession=precession)
+    if site:
+        op = orc.Params(D_site=D, e_site=e, **kw)
+        gp = P.Params(D_site=_dev(D, prec), e_site=_dev(e, prec), seed=8, **kw)
+    else:
+        op = orc.Params(D=0.12, e=(0.0, 1.0, 1.0), **kw)
+        gp = P.Params(D=0.12, e=(0.0, 1.0, 1.0), seed=8, **kw)
+    wm = (0.2, 0.0, 1.0)
+    want = orc.adjoint(orc.geom(shape, bc), op, s0, seed=8, r=0, first_pulse=3, n_pulses=npl,
+                       wE=0.5, wm=wm)
+    cot = _dev(inputs.rng(35).standard_normal((3, N)), prec)
+    for v in P.step_variants(prec):
+        got = {}
+        for mode in (ck, P.TAPE_FULL):
+            lat = P.Lattice(shape, bc=bc, precision=prec, state=_dev(s0, prec))
+            lat.set_step_config(v, 4 if v else 0)
+            tape = lat.adjoint_forward(gp, 3, npl, ckpt_every=mode)
+            torch.cuda.synchronize()
+            sT = lat.state.clone()
+            r1 = tape.backward(cot=cot, wE=0.5, wm=wm)
+            r2 = tape.backward(wE=0.5, wm=wm)
+            got[mode] = (sT, r1, r2)
+            tape.close()
+            lat.close()
+        (sa, a1, a2), (sb, b1, b2) = got[ck], got[P.TAPE_FULL]
+        assert torch.equal(sa, sb), v
+        ref = P.Lattice(shape, bc=bc, precision=prec, state=_dev(s0, prec))
+        ref.set_step_config(v, 4 if v else 0)
+        ref.run(gp, first_pulse=3, n_pulses=npl)
+        torch.cuda.synchronize()
+        assert torch.equal(ref.state, sb), v
+        ref.close()
+        for ra, rb in ((a1, b1), (a2, b2)):
+            assert ra["loss"] == rb["loss"] and ra["g_H"] == rb["g_H"] and ra["g_J"] == rb["g_J"], v
+            if site:
+                assert torch.equal(ra["g_D"], rb["g_D"]), v
+            else:
+                assert ra["g_D"] == rb["g_D"], v
+            assert torch.equal(ra["g_s0"], rb["g_s0"]), v
+        tol = GTOL[prec]
+        assert _rel(b2["g_H"], want["g_H"]) < tol, v
+        assert _rel(b2["g_J"], want["g_J"]) < tol, v
+        gD = b2["g_D"].cpu().numpy() if site else b2["g_D"]
+        assert _rel(gD, want["g_D"]) < tol, v
+        assert _rel(b2["g_s0"].double().cpu().numpy(), want["g_s0"]) < tol, v
+
+
 def test_adjoint_finite_differences_gpu(P):
     """dL/dH_z and dL/dJ of the fp64 GPU adjoint against central differences of
     the GPU forward run."""
@@ -275,13 +334,14 @@ def config4():
     return shape, D, e, s0, kw, want
 
 
+@pytest.mark.parametrize("ckpt", [10, 0])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_adjoint_full_workload(P, config4, prec):
+def test_adjoint_full_workload(P, config4, prec, ckpt):
     shape, D, e, s0, kw, want = config4
     Dr, er = _rounded(D, prec), _rounded(e, prec)
     gp = P.Params(D_site=_dev(Dr, prec), e_site=_dev(er, prec), seed=0, **kw)
     lat = P.Lattice(shape, precision=prec, init="direction", direction=(0, 0, 1))
-    got = lat.adjoint(gp, 0, 3, ckpt_every=10, wE=1.0, wm=(0, 0, 1))
+    got = lat.adjoint(gp, 0, 3, ckpt_every=ckpt, wE=1.0, wm=(0, 0, 1))
     tol = GTOL[prec]
     assert got["loss"] == pytest.approx(want["loss"], rel=1e-12 if prec == "fp64" else 1e-5)
     assert _rel(got["g_H"], want["g_H"]) < tol

@@ -13,6 +13,7 @@
 // reduced per block into fp64 partials and summed in a fixed order (no
 // floating-point atomics).
 #include "lll_device.hpp"
+#include "lll_site.hpp"
 
 namespace lll {
 

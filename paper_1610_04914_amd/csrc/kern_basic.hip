@@ -3,6 +3,7 @@
 // launch per Runge-Kutta stage, used for small lattices and as a tuning
 // candidate).
 #include "lll_device.hpp"
+#include "lll_site.hpp"
 
 namespace lll {
 

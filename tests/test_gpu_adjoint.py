@@ -343,7 +343,10 @@ def test_adjoint_full_workload(P, config4, prec, ckpt):
     lat = P.Lattice(shape, precision=prec, init="direction", direction=(0, 0, 1))
     got = lat.adjoint(gp, 0, 3, ckpt_every=ckpt, wE=1.0, wm=(0, 0, 1))
     tol = GTOL[prec]
-    assert got["loss"] == pytest.approx(want["loss"], rel=1e-12 if prec == "fp64" else 1e-5)
-    assert _rel(got["g_H"], want["g_H"]) < tol
-    assert _rel(got["g_J"], want["g_J"]) < tol
-    assert _rel(got["g_D"].cpu().numpy(), want["g_D"]) < tol
+    err = {"loss": abs(got["loss"] - want["loss"]) / abs(want["loss"]),
+           "g_H": _rel(got["g_H"], want["g_H"]), "g_J": _rel(got["g_J"], want["g_J"]),
+           "g_D": _rel(got["g_D"].cpu().numpy(), want["g_D"])}
+    print(f"\nadjoint workload {prec} ckpt_every={ckpt}: relative error vs the oracle "
+          + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
+    assert err["loss"] < (1e-12 if prec == "fp64" else 1e-5)
+    assert err["g_H"] < tol and err["g_J"] < tol and err["g_D"] < tol

@@ -252,9 +252,12 @@ lll_status lll_autotune(lll_lattice* lat, const lll_params* params, const char* 
  * restored, in one call (the lattice's state and kick maximum are left as
  * they were).
  *
- * Work buffers of the backward pass (4 ckpt_every + 11 states; 10 for a
- * full tape) stay with the lattice and are reused.  ckpt_every < 0 is
- * LLL_EINVAL. */
+ * Work buffers of the backward pass (2 (4 ckpt_every + 1) + 10 states; 10
+ * for a full tape) stay with the lattice and are reused.  With checkpoints
+ * the backward recomputes the next block on a second stream of the
+ * lattice's (created on first use, default priority) while the current
+ * block is reversed, ordered by events; all of it is complete when the call
+ * returns.  ckpt_every < 0 is LLL_EINVAL. */
 #define LLL_TAPE_FULL 0
 typedef struct lll_tape lll_tape;
 lll_status lll_adjoint_forward(lll_lattice* lat, const lll_params* params, uint64_t first_pulse,

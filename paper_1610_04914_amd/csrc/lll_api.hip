@@ -657,6 +657,11 @@ struct lll_lattice {
     size_t adj_sc_bytes = 0;
     void* adj_small = nullptr;
     size_t adj_small_bytes = 0;
+    // the backward pass recomputes the next checkpoint block on a second
+    // stream while the current block is reversed: events 0 (work before the
+    // backward), 1-2 (block buffer k recomputed), 3-4 (block buffer k reversed)
+    hipStream_t adj_st2 = nullptr;
+    hipEvent_t adj_ev[5] = {};
     ~lll_lattice();
 };
 
@@ -1243,21 +1248,33 @@ lll_lattice::~lll_lattice() {
     // tapes may outlive their lattice: their backward calls then fail cleanly,
     // and destroying them still frees their checkpoints
     for (lll_tape* T : tapes) T->lat = nullptr;
+    if (adj_st2) {
+        (void)hipStreamSynchronize(adj_st2);
+        (void)hipStreamDestroy(adj_st2);
+    }
+    for (hipEvent_t e : adj_ev)
+        if (e) (void)hipEventDestroy(e);
     for (void* p : {ck_pool, adj_bb, adj_sc, adj_small})
         if (p) (void)hipFree(p);
 }
 
-// Adjoint work buffers of an engine: block buffer (4K + 1 states; none for a
-// full tape, K = 0), ten scratch states, parameter partials, their sum, the
-// loss observables and the kick maxima of recomputed kicks (kept apart from
-// the lattice's own).
+// Adjoint work buffers of an engine: two block buffers of 4K + 1 states each
+// (none for a full tape, K = 0), ten scratch states, parameter partials, their
+// sum, the loss observables and the kick maxima of recomputed kicks (kept
+// apart from the lattice's own); with checkpoints, the second stream and its
+// events.
 static lll_status ensure_adj_work(lll_lattice* L, int64_t K) {
     Engine& E = L->E;
     const size_t cb = (size_t)E.nsites * E.esz;
     lll_status s;
     if (K > 0 &&
-        (s = ensure_buf(&L->adj_bb, &L->adj_bb_bytes, 3 * cb * (size_t)(4 * K + 1))) != LLL_OK)
+        (s = ensure_buf(&L->adj_bb, &L->adj_bb_bytes, 3 * cb * 2 * (size_t)(4 * K + 1))) != LLL_OK)
         return s;
+    if (K > 0 && !L->adj_st2) {
+        // default priority, like every stream of the library
+        HIP_TRY(hipStreamCreateWithFlags(&L->adj_st2, hipStreamNonBlocking));
+        for (hipEvent_t& e : L->adj_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
     if ((s = ensure_buf(&L->adj_sc, &L->adj_sc_bytes, 3 * cb * 10)) != LLL_OK) return s;
     const size_t small = sizeof(double) * (5 * (size_t)E.nblk + 5 + 8) +
                          sizeof(unsigned long long) * kKickSlots;
@@ -1384,16 +1401,20 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
     const State loc2[2] = {state_at(L->adj_sc, cb, 7), state_at(L->adj_sc, cb, 9)};
     (void)cur;
     (void)nxt;
-    // block buffer: slot j holds x, y2, y3, y4 of operation j of the block
-    // (the full tape is one block that the forward has already filled)
+    // block buffer k (k = b & 1 for block b): slot j holds x, y2, y3, y4 of
+    // operation j of the block (the full tape is one block that the forward
+    // has already filled)
     void* const bb = T->full ? T->ck : L->adj_bb;
-    auto slot = [&](int64_t j, int c) { return state_at(bb, cb, 4 * j + c); };
+    const int64_t bstride = 4 * K + 1;
+    auto slot_of = [&](int64_t b, int64_t j, int c) {
+        return state_at(bb, cb, (T->full ? 0 : (b & 1) * bstride) + 4 * j + c);
+    };
     const bool site = T->p.D_site != nullptr;
     double* gD = site ? (double*)g_D : nullptr;
     HIP_TRY(hipMemsetAsync(L->adj_small, 0, sizeof(double) * (5 * (size_t)E.nblk + 5), E.st));
     if (site) HIP_TRY(hipMemsetAsync(gD, 0, sizeof(double) * E.nsites, E.st));
     const int pr = E.prec, pc = E.precession, an = E.anis;
-    const State sT = T->full ? slot(nops, 0) : state_at(T->ck, cb, T->nblocks);
+    const State sT = T->full ? slot_of(0, nops, 0) : state_at(T->ck, cb, T->nblocks);
     const State cs = cot ? State{const_cast<void*>(cot), (char*)cot + cb, (char*)cot + 2 * cb}
                          : State{};
     HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, sT, E.d_partials, res8, nullptr,
@@ -1401,6 +1422,36 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
     HIP_TRY(launch_adj_loss(pr, an, E.hreps[0], E.nblk, sT, cs, sbar, wE, wm, gD, part,
                             E.st));
     const double dt = T->p.dt;
+    // Recompute of checkpoint block b into buffer b & 1, on the second stream:
+    // it runs while the block after it is reversed on the lattice's stream
+    // (both are small, latency-bound launches that leave most CUs idle).  It
+    // waits for the reverse that last read its buffer; the reverse of block b
+    // waits for it.
+    hipStream_t const s2 = L->adj_st2;
+    bool reversed[2] = {false, false};
+    auto recompute = [&](int64_t b) -> lll_status {
+        const int64_t j0 = b * K, j1 = std::min(j0 + K, nops);
+        if (reversed[b & 1]) HIP_TRY(hipStreamWaitEvent(s2, L->adj_ev[3 + (b & 1)], 0));
+        HIP_TRY(launch_copy(pr, slot_of(b, 0, 0), state_at(T->ck, cb, b), E.nsites, s2));
+        for (int64_t j = j0; j < j1; ++j) {
+            const int64_t sl = j - j0;
+            const State x = slot_of(b, sl, 0), nx = slot_of(b, sl + 1, 0);
+            if (T->op[j] == 0 && E.variant != 0) {  // one fused launch: x', y2, y3, y4
+                const State ys[3] = {slot_of(b, sl, 1), slot_of(b, sl, 2), slot_of(b, sl, 3)};
+                HIP_TRY(launch_step_fused_stages(pr, pc, an, E.variant, eff_bz(E), E.dreps,
+                                                 E.d_tiles, E.ntiles, x, nx, ys, s2));
+            } else if (T->op[j] == 0) {
+                HIP_TRY(launch_rk4_stages(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, x,
+                                          slot_of(b, sl, 1), slot_of(b, sl, 2), slot_of(b, sl, 3),
+                                          accb, nx, s2));
+            } else {
+                HIP_TRY(launch_copy(pr, nx, x, E.nsites, s2));
+                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, T->opk[j], -1.0, kd, s2));
+            }
+        }
+        HIP_TRY(hipEventRecord(L->adj_ev[1 + (b & 1)], s2));
+        return LLL_OK;
+    };
     // Stage 1's pass B of the last reversed step waits for the next operation
     // to reverse: when that is a step, one launch also does its stage-4 pass A
     // (pointwise in the finished cotangent), after its block is recomputed.
@@ -1412,28 +1463,24 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
         pend_b1 = false;
         return LLL_OK;
     };
+    if (!T->full) {
+        // the second stream starts after everything queued on the lattice's
+        // stream so far (the forward that wrote the checkpoints included)
+        HIP_TRY(hipEventRecord(L->adj_ev[0], E.st));
+        HIP_TRY(hipStreamWaitEvent(s2, L->adj_ev[0], 0));
+        if ((s = recompute(T->nblocks - 1)) != LLL_OK) return s;
+    }
     for (int64_t b = T->nblocks - 1; b >= 0; --b) {
         const int64_t j0 = b * K, j1 = std::min(j0 + K, nops);
-        if (!T->full) HIP_TRY(launch_copy(pr, slot(0, 0), state_at(T->ck, cb, b), E.nsites, E.st));
-        for (int64_t j = T->full ? j1 : j0; j < j1; ++j) {
-            const int64_t sl = j - j0;
-            State nx = slot(sl + 1, 0);
-            if (T->op[j] == 0 && E.variant != 0) {  // one fused launch: x', y2, y3, y4
-                const State ys[3] = {slot(sl, 1), slot(sl, 2), slot(sl, 3)};
-                HIP_TRY(launch_step_fused_stages(pr, pc, an, E.variant, eff_bz(E), E.dreps,
-                                                 E.d_tiles, E.ntiles, slot(sl, 0), nx, ys, E.st));
-            } else if (T->op[j] == 0) {
-                HIP_TRY(launch_rk4_stages(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, slot(sl, 0),
-                                          slot(sl, 1), slot(sl, 2), slot(sl, 3), accb, nx, E.st));
-            } else {
-                HIP_TRY(launch_copy(pr, nx, slot(sl, 0), E.nsites, E.st));
-                HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, T->opk[j], -1.0, kd, E.st));
-            }
+        if (!T->full) {
+            if (b >= 1 && (s = recompute(b - 1)) != LLL_OK) return s;
+            HIP_TRY(hipStreamWaitEvent(E.st, L->adj_ev[1 + (b & 1)], 0));
         }
         for (int64_t j = j1 - 1; j >= j0; --j) {
             const int64_t sl = j - j0;
             if (T->op[j] == 0) {
-                const State y[4] = {slot(sl, 0), slot(sl, 1), slot(sl, 2), slot(sl, 3)};
+                const State y[4] = {slot_of(b, sl, 0), slot_of(b, sl, 1), slot_of(b, sl, 2),
+                                    slot_of(b, sl, 3)};
                 const bool a4 = !pend_b1;
                 if (pend_b1 && (s = finish_b1(&y[3])) != LLL_OK) return s;
                 HIP_TRY(launch_adj_step(pr, pc, an, E.hreps[0], E.nblk, y, dt, sbar, xbar,
@@ -1441,9 +1488,13 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
                 pend_b1 = true;
             } else {
                 if (pend_b1 && (s = finish_b1(nullptr)) != LLL_OK) return s;
-                HIP_TRY(launch_adj_kick(pr, E.hreps[0], E.nblk, slot(sl, 0), sbar,
+                HIP_TRY(launch_adj_kick(pr, E.hreps[0], E.nblk, slot_of(b, sl, 0), sbar,
                                         T->opk[j], -1.0, E.st));
             }
+        }
+        if (!T->full) {
+            HIP_TRY(hipEventRecord(L->adj_ev[3 + (b & 1)], E.st));
+            reversed[b & 1] = true;
         }
     }
     if (pend_b1 && (s = finish_b1(nullptr)) != LLL_OK) return s;
@@ -1509,6 +1560,7 @@ extern "C" void lll_tape_destroy(lll_tape* T) {
     if (L) {
         if (L->E.st) (void)hipStreamSynchronize(L->E.st);
         else (void)hipDeviceSynchronize();
+        if (L->adj_st2) (void)hipStreamSynchronize(L->adj_st2);
         auto& v = L->tapes;
         v.erase(std::remove(v.begin(), v.end(), T), v.end());
     }

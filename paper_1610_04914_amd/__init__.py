@@ -187,9 +187,11 @@ def lll_observables(h, params: lll_params) -> dict:
 
 
 def lll_run(h, params: lll_params, first_pulse: int, n_pulses: int, T_per_pulse=None,
-            obs_every: int = 0, trace: bool = True):
+            obs_every: int = 0, trace: bool = True, raw: bool = False):
     """trace=False: the measurements still run (running sums, last values on the
-    device) but none is copied back; returns []."""
+    device) but none is copied back; returns [].  raw=True: returns the host
+    array of lll_obs records as the library filled it (convert an entry with
+    .as_dict()), without building Python dicts."""
     nm = n_pulses // obs_every if obs_every > 0 and trace else 0
     tr = (lll_obs * max(nm, 1))()
     Tp = None
@@ -198,6 +200,8 @@ def lll_run(h, params: lll_params, first_pulse: int, n_pulses: int, T_per_pulse=
     st = lib().lll_run(h, C.byref(params), C.c_uint64(first_pulse), int(n_pulses), Tp,
                        int(obs_every), tr if nm > 0 else None)
     _check(st, "lll_run")
+    if raw:
+        return tr if nm > 0 else []
     return [tr[i].as_dict() for i in range(nm)]
 
 
@@ -338,8 +342,9 @@ class Lattice:
         return lll_observables(self.h, self._pc(p))
 
     def run(self, p: Params, first_pulse: int = 0, n_pulses: int = 1, T_per_pulse=None,
-            obs_every: int = 0, trace: bool = True):
-        return lll_run(self.h, self._pc(p), first_pulse, n_pulses, T_per_pulse, obs_every, trace)
+            obs_every: int = 0, trace: bool = True, raw: bool = False):
+        return lll_run(self.h, self._pc(p), first_pulse, n_pulses, T_per_pulse, obs_every, trace,
+                       raw)
 
     def kick_norm_dev(self, reset: bool = False) -> float:
         v = C.c_double()

@@ -13,6 +13,7 @@
 
 #include "../../include/lll.h"
 #include "lll_internal.hpp"
+#include "tile_order.hpp"
 
 using namespace lll;
 
@@ -334,92 +335,8 @@ int eff_bz(const Engine& E) { return E.bz > 0 ? E.bz : (E.prec == 0 ? 32 : 16); 
 // Tile list of the fused kernel: (replica, tile x, tile y, tile z) per
 // workgroup, ordered so that the eight XCDs (workgroups are dealt out to them
 // round-robin) each receive a contiguous z-major range of tiles, keeping halo
-// re-reads inside one XCD's L2.
-// Tile order of a replica batch, as the contiguous list that the XCD-aware
-// mapping below deals out (XCD k receives list positions [k per, (k+1) per)
-// and dispatches them in order).  Replicas of different sizes march z-chunks
-// of different lengths, so a replica-major list leaves the XCDs that received
-// the big replicas working long after the others.  Whole replicas are dealt
-// instead, largest work first, each to the least-loaded XCD that still has
-// room (work of a tile = planes it marches: its chunk plus 8 of pipeline);
-// tiles are then moved, shortest first, from XCDs over their share to those
-// under it; each XCD runs its longest tiles first.  A replica's tiles stay on
-// one XCD where the counts allow, so their shared halo columns meet in its L2.
-static std::vector<int4> balance_tiles(const Engine& E, const std::vector<int4>& list,
-                                       const std::vector<int>& bz_of) {
-    const int n = (int)list.size();
-    const int per = (n + 7) / 8;
-    auto len = [&](const int4& t) {
-        const RepDev& R = E.hreps[t.x];
-        const int bzr = bz_of[t.x];
-        return std::min(bzr, R.Lz - t.w * bzr) + 8;
-    };
-    auto longest_first = [&](std::vector<int4>& v) {
-        std::stable_sort(v.begin(), v.end(),
-                         [&](const int4& a, const int4& b) { return len(a) > len(b); });
-    };
-    // Where the blocks of positions do not map onto whole workgroup-id
-    // classes, the mapping keeps the list order (workgroups then go round the
-    // XCDs in list order): the longest tiles simply go first.
-    for (int p = 0; p < n; ++p) {
-        const int id = (p % per) * 8 + p / per;
-        if (id >= n) {
-            std::vector<int4> v = list;
-            longest_first(v);
-            return v;
-        }
-    }
-    // share of each XCD: the list positions it receives
-    int cap[8];
-    for (int k = 0; k < 8; ++k) cap[k] = std::max(0, std::min(per, n - k * per));
-    std::vector<int64_t> work(E.nrep, 0);
-    std::vector<std::vector<int4>> of_rep(E.nrep);
-    for (const int4& t : list) {
-        work[t.x] += len(t);
-        of_rep[t.x].push_back(t);
-    }
-    std::vector<int> rord(E.nrep);
-    for (int r = 0; r < E.nrep; ++r) rord[r] = r;
-    std::stable_sort(rord.begin(), rord.end(), [&](int a, int b) { return work[a] > work[b]; });
-    std::vector<int4> xl[8];
-    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int r : rord) {
-        int best = -1;
-        for (int k = 0; k < 8; ++k) {
-            if (cap[k] == 0) continue;
-            const bool fits = (int)(xl[k].size() + of_rep[r].size()) <= cap[k];
-            const bool bfits =
-                best >= 0 && (int)(xl[best].size() + of_rep[r].size()) <= cap[best];
-            if (best < 0 || (fits && !bfits) || (fits == bfits && load[k] < load[best]))
-                best = k;
-        }
-        xl[best].insert(xl[best].end(), of_rep[r].begin(), of_rep[r].end());
-        load[best] += work[r];
-    }
-    // even out the counts: shortest tiles move from full XCDs to the least
-    // loaded one with room
-    for (int k = 0; k < 8; ++k) {
-        longest_first(xl[k]);
-        while ((int)xl[k].size() > cap[k]) {
-            int to = -1;
-            for (int m = 0; m < 8; ++m)
-                if ((int)xl[m].size() < cap[m] && (to < 0 || load[m] < load[to])) to = m;
-            const int4 t = xl[k].back();
-            xl[k].pop_back();
-            load[k] -= len(t);
-            xl[to].push_back(t);
-            load[to] += len(t);
-        }
-    }
-    std::vector<int4> out;
-    out.reserve(n);
-    for (int k = 0; k < 8; ++k) {
-        longest_first(xl[k]);
-        out.insert(out.end(), xl[k].begin(), xl[k].end());
-    }
-    return out;
-}
-
+// re-reads inside one XCD's L2; a batch of replicas is first ordered by
+// balance_tiles (tile_order.hpp).
 lll_status ensure_tiles(Engine& E) {
     if (E.tiles_variant == E.variant && E.tiles_bz == E.bz && E.d_tiles) return LLL_OK;
     FusedInfo fi;
@@ -441,29 +358,16 @@ lll_status ensure_tiles(Engine& E) {
             for (int ty = 0; ty < R.ty; ++ty)
                 for (int tx = 0; tx < R.tx; ++tx) list.push_back(make_int4(r, tx, ty, tz));
     }
-    if (E.nrep > 1) list = balance_tiles(E, list, bz_of);
+    if (E.nrep > 1) {
+        std::vector<int> lz(E.nrep);
+        for (int r = 0; r < E.nrep; ++r) lz[r] = E.hreps[r].Lz;
+        list = tileord::balance_tiles(list, lz, bz_of);
+    }
     // XCD-aware order: workgroup w runs on XCD w % 8.
     const int n = (int)list.size();
     std::vector<int4> ord(n);
-    const int per = (n + 7) / 8;
-    int w = 0;
-    std::vector<int> slot_of(n);
-    {
-        // position p of the contiguous list goes to workgroup id
-        // (p % per) * 8 + p / per when that id exists; fall back to identity otherwise
-        std::vector<int> taken(n, 0);
-        bool ok = true;
-        for (int p = 0; p < n; ++p) {
-            int id = (p % per) * 8 + p / per;
-            if (id >= n || taken[id]) { ok = false; break; }
-            taken[id] = 1;
-            slot_of[p] = id;
-        }
-        if (!ok)
-            for (int p = 0; p < n; ++p) slot_of[p] = p;
-    }
+    const std::vector<int> slot_of = tileord::xcd_slots(n);
     for (int p = 0; p < n; ++p) ord[slot_of[p]] = list[p];
-    (void)w;
     if (n > E.tiles_cap) {
         if (E.d_tiles) (void)hipFree(E.d_tiles);
         E.d_tiles = nullptr;

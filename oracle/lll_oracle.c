@@ -33,7 +33,7 @@
 #include <omp.h>
 #endif
 
-/* Threads a parallel loop of this build uses (1 without OpenMP). */
+/* Threads a parallel loop uses: the OpenMP team size, or 1 when compiled without OpenMP. */
 int orc_threads(void)
 {
 #ifdef _OPENMP

@@ -252,8 +252,8 @@ lll_status lll_autotune(lll_lattice* lat, const lll_params* params, const char* 
  * restored, in one call (the lattice's state and kick maximum are left as
  * they were).
  *
- * Work buffers of the backward pass (2 (4 ckpt_every + 1) + 10 states; 10
- * for a full tape) stay with the lattice and are reused.  With checkpoints
+ * Work buffers of the backward pass (2 (4 ckpt_every + 1) + 8 states; 8 for
+ * a full tape) stay with the lattice and are reused.  With checkpoints
  * the backward recomputes the next block on a second stream of the
  * lattice's (created on first use, default priority) while the current
  * block is reversed, ordered by events; all of it is complete when the call

@@ -1250,8 +1250,14 @@ lll_lattice::~lll_lattice() {
         if (p) (void)hipFree(p);
 }
 
+// Scratch states of the backward pass: the RK4 accumulator of a per-stage
+// recompute (slot 0), the cotangents of the step output and input, the stage
+// cotangent, and the two (q, loc) pairs of the reverse passes.
+constexpr int kAdjScratch = 8;
+constexpr int kAdjAcc = 0;
+
 // Adjoint work buffers of an engine: two block buffers of 4K + 1 states each
-// (none for a full tape, K = 0), ten scratch states, parameter partials, their
+// (none for a full tape, K = 0), eight scratch states, parameter partials, their
 // sum, the loss observables and the kick maxima of recomputed kicks (kept
 // apart from the lattice's own); with checkpoints, the second stream and its
 // events.
@@ -1267,7 +1273,7 @@ static lll_status ensure_adj_work(lll_lattice* L, int64_t K) {
         HIP_TRY(hipStreamCreateWithFlags(&L->adj_st2, hipStreamNonBlocking));
         for (hipEvent_t& e : L->adj_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
-    if ((s = ensure_buf(&L->adj_sc, &L->adj_sc_bytes, 3 * cb * 10)) != LLL_OK) return s;
+    if ((s = ensure_buf(&L->adj_sc, &L->adj_sc_bytes, 3 * cb * kAdjScratch)) != LLL_OK) return s;
     const size_t small = sizeof(double) * (5 * (size_t)E.nblk + 5 + 8) +
                          sizeof(unsigned long long) * kKickSlots;
     return ensure_buf(&L->adj_small, &L->adj_small_bytes, small);
@@ -1338,7 +1344,7 @@ static lll_status tape_forward(lll_lattice* L, lll_tape* T, uint64_t first_pulse
             } else if (T->op[j] == 0) {
                 HIP_TRY(launch_rk4_stages(pr, pc, an, E.dreps, E.d_blk_rep, E.nblk, slot(j, 0),
                                           slot(j, 1), slot(j, 2), slot(j, 3),
-                                          state_at(L->adj_sc, cb, 2), nx, E.st));
+                                          state_at(L->adj_sc, cb, kAdjAcc), nx, E.st));
             } else {
                 HIP_TRY(launch_copy(pr, nx, slot(j, 0), E.nsites, E.st));
                 HIP_TRY(launch_kick(pr, E.dreps, E.d_blk_rep, E.nblk, nx, T->opk[j], -1.0, kd,
@@ -1385,14 +1391,11 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
     double* acc5 = part + 5 * (size_t)E.nblk;
     double* res8 = acc5 + 5;
     unsigned long long* kd = (unsigned long long*)(res8 + 8);
-    State cur = state_at(L->adj_sc, cb, 0), nxt = state_at(L->adj_sc, cb, 1);
-    State accb = state_at(L->adj_sc, cb, 2);
-    State sbar = state_at(L->adj_sc, cb, 3), xbar = state_at(L->adj_sc, cb, 4);
-    State kb = state_at(L->adj_sc, cb, 5);
-    const State q2[2] = {state_at(L->adj_sc, cb, 6), state_at(L->adj_sc, cb, 8)};
-    const State loc2[2] = {state_at(L->adj_sc, cb, 7), state_at(L->adj_sc, cb, 9)};
-    (void)cur;
-    (void)nxt;
+    State accb = state_at(L->adj_sc, cb, kAdjAcc);
+    State sbar = state_at(L->adj_sc, cb, 1), xbar = state_at(L->adj_sc, cb, 2);
+    State kb = state_at(L->adj_sc, cb, 3);
+    const State q2[2] = {state_at(L->adj_sc, cb, 4), state_at(L->adj_sc, cb, 6)};
+    const State loc2[2] = {state_at(L->adj_sc, cb, 5), state_at(L->adj_sc, cb, 7)};
     // block buffer k (k = b & 1 for block b): slot j holds x, y2, y3, y4 of
     // operation j of the block (the full tape is one block that the forward
     // has already filled)

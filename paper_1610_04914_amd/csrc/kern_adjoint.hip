@@ -17,7 +17,6 @@
 
 namespace lll {
 
-constexpr int kAdjBlock = 256;
 
 struct SiteA {
     int r;

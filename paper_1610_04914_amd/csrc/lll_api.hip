@@ -1256,6 +1256,9 @@ lll_lattice::~lll_lattice() {
 constexpr int kAdjScratch = 8;
 constexpr int kAdjAcc = 0;
 
+// Blocks of the adjoint's per-site kernels (one wave each).
+static int adj_blocks(const Engine& E) { return (int)((E.nsites + kAdjBlock - 1) / kAdjBlock); }
+
 // Adjoint work buffers of an engine: two block buffers of 4K + 1 states each
 // (none for a full tape, K = 0), eight scratch states, parameter partials, their
 // sum, the loss observables and the kick maxima of recomputed kicks (kept
@@ -1274,7 +1277,7 @@ static lll_status ensure_adj_work(lll_lattice* L, int64_t K) {
         for (hipEvent_t& e : L->adj_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     if ((s = ensure_buf(&L->adj_sc, &L->adj_sc_bytes, 3 * cb * kAdjScratch)) != LLL_OK) return s;
-    const size_t small = sizeof(double) * (5 * (size_t)E.nblk + 5 + 8) +
+    const size_t small = sizeof(double) * (5 * (size_t)adj_blocks(E) + 5 + 8) +
                          sizeof(unsigned long long) * kKickSlots;
     return ensure_buf(&L->adj_small, &L->adj_small_bytes, small);
 }
@@ -1388,7 +1391,8 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
     const int64_t nops = (int64_t)T->op.size();
     const int64_t K = T->full ? nops : T->K;
     double* part = (double*)L->adj_small;
-    double* acc5 = part + 5 * (size_t)E.nblk;
+    const int anb = adj_blocks(E);
+    double* acc5 = part + 5 * (size_t)anb;
     double* res8 = acc5 + 5;
     unsigned long long* kd = (unsigned long long*)(res8 + 8);
     State accb = state_at(L->adj_sc, cb, kAdjAcc);
@@ -1406,7 +1410,7 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
     };
     const bool site = T->p.D_site != nullptr;
     double* gD = site ? (double*)g_D : nullptr;
-    HIP_TRY(hipMemsetAsync(L->adj_small, 0, sizeof(double) * (5 * (size_t)E.nblk + 5), E.st));
+    HIP_TRY(hipMemsetAsync(L->adj_small, 0, sizeof(double) * (5 * (size_t)anb + 5), E.st));
     if (site) HIP_TRY(hipMemsetAsync(gD, 0, sizeof(double) * E.nsites, E.st));
     const int pr = E.prec, pc = E.precession, an = E.anis;
     const State sT = T->full ? slot_of(0, nops, 0) : state_at(T->ck, cb, T->nblocks);
@@ -1414,7 +1418,7 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
                          : State{};
     HIP_TRY(launch_obs(pr, an, E.dreps, E.d_oblk_rep, E.nobblk, 1, sT, E.d_partials, res8, nullptr,
                        0, E.st));
-    HIP_TRY(launch_adj_loss(pr, an, E.hreps[0], E.nblk, sT, cs, sbar, wE, wm, gD, part,
+    HIP_TRY(launch_adj_loss(pr, an, E.hreps[0], anb, sT, cs, sbar, wE, wm, gD, part,
                             E.st));
     const double dt = T->p.dt;
     // Recompute of checkpoint block b into buffer b & 1, on the second stream:
@@ -1452,7 +1456,7 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
     // (pointwise in the finished cotangent), after its block is recomputed.
     bool pend_b1 = false;
     auto finish_b1 = [&](const State* y4prev) -> lll_status {
-        HIP_TRY(launch_adj_b1(pr, pc, an, E.hreps[0], E.nblk, y4prev, dt, sbar, xbar,
+        HIP_TRY(launch_adj_b1(pr, pc, an, E.hreps[0], anb, y4prev, dt, sbar, xbar,
                               kb, q2, loc2, gD, part, E.st));
         std::swap(sbar, xbar);
         pend_b1 = false;
@@ -1478,12 +1482,12 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
                                     slot_of(b, sl, 3)};
                 const bool a4 = !pend_b1;
                 if (pend_b1 && (s = finish_b1(&y[3])) != LLL_OK) return s;
-                HIP_TRY(launch_adj_step(pr, pc, an, E.hreps[0], E.nblk, y, dt, sbar, xbar,
+                HIP_TRY(launch_adj_step(pr, pc, an, E.hreps[0], anb, y, dt, sbar, xbar,
                                         kb, q2, loc2, gD, part, a4, E.st));
                 pend_b1 = true;
             } else {
                 if (pend_b1 && (s = finish_b1(nullptr)) != LLL_OK) return s;
-                HIP_TRY(launch_adj_kick(pr, E.hreps[0], E.nblk, slot_of(b, sl, 0), sbar,
+                HIP_TRY(launch_adj_kick(pr, E.hreps[0], anb, slot_of(b, sl, 0), sbar,
                                         T->opk[j], -1.0, E.st));
             }
         }
@@ -1493,7 +1497,7 @@ static lll_status tape_backward(lll_tape* T, const void* cot, double wE, const d
         }
     }
     if (pend_b1 && (s = finish_b1(nullptr)) != LLL_OK) return s;
-    HIP_TRY(launch_adj_finish(part, E.nblk, acc5, E.st));
+    HIP_TRY(launch_adj_finish(part, anb, acc5, E.st));
     if (g_s0) {
         State dst{g_s0, (char*)g_s0 + cb, (char*)g_s0 + 2 * cb};
         HIP_TRY(launch_copy(pr, dst, sbar, E.nsites, E.st));
@@ -1578,7 +1582,7 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
     T.full = ckpt_every == 0;
     // the forward's kicks go to the scratch maxima: the state is restored
     unsigned long long* kd =
-        (unsigned long long*)((double*)L->adj_small + 5 * (size_t)L->E.nblk + 5 + 8);
+        (unsigned long long*)((double*)L->adj_small + 5 * (size_t)adj_blocks(L->E) + 5 + 8);
     s = tape_forward(L, &T, first_pulse, n_pulses, kd);
     if (s == LLL_OK) s = tape_backward(&T, nullptr, wE, wm, loss, g_H, g_J, g_D, g_s0);
     Engine& E = L->E;

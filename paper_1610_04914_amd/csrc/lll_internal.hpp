@@ -158,7 +158,10 @@ hipError_t launch_rk4_stages(int prec, int precession, int anis, const RepDev* r
 // caller, added to by every pass, reduced in block order into acc[5] by
 // launch_adj_finish); gD: per-site fp64 Dbar_i (per-site anisotropy) or unused.
 // Adjoint launchers take the lattice's descriptor by value (host copy; the
-// adjoint runs on one lattice).
+// adjoint runs on one lattice).  Their per-site kernels run one wave per
+// block, kAdjBlock sites: nblk = ceil(N / kAdjBlock) blocks, and as many rows
+// of parameter partials.
+constexpr int kAdjBlock = 64;
 // cot: cotangent of s added to the loss's own (null pointers: none).
 hipError_t launch_adj_loss(int prec, int anis, const RepDev& R, int nblk,
                            State s, State cot, State sbar, double wE, const double wm[3],

@@ -146,7 +146,14 @@ def _timed(fn):
     return time.perf_counter() - t0, r
 
 
-def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 5000, burn: int = 1000):
+# Pulses of the batched accuracy runs (--acc-pulses).  Near T_c the |m| series
+# stay correlated over thousands of pulses: with 5000 the blocking analysis
+# converged for 4 of 96 replicas and the error bars were lower bounds; 20000
+# (about 100 s for both batches) gives converged errors for a quarter of them.
+ACC_PULSES = 20000
+
+
+def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 0, burn: int = 1000):
     """Uneven-replica workload: 32 each of 24^3, 48^3, 64^3, T uniform in
     [0.3, 2], lambda log-uniform in [0.005, 0.05], J = 1, H = 0, dt = 0.1,
     Dt = 1.0, random-sphere starts, per-replica noise keys.
@@ -173,6 +180,7 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 5000, burn
     import numpy as np
     import paper_1610_04914_amd as P
     from tests import inputs
+    n_acc = n_acc or ACC_PULSES
     reps = inputs.batch_replicas(seed=0)
     descs = [dict(r, J=1.0) for r in reps]
     sites = sum(int(np.prod(r["L"])) for r in reps)
@@ -204,11 +212,10 @@ def extra_batched(n_pulses: int = 500, n_seq: int = 100, n_acc: int = 5000, burn
         # ordered starts (+z): below T_c a random start keeps coarsening far
         # beyond the run, so time averages would not be stationary
         A = P.Batch([dict(d, init="direction") for d in descs], precision=prec, dt=0.1, Dt=1.0)
-        tr = A.run(first_pulse=0, n_pulses=n_acc, obs_every=1)
+        tr = A.run(first_pulse=0, n_pulses=n_acc, obs_every=1, raw=True)  # [m][r][8]
         A.close()
-        e = np.array([[tr[m][r]["E_total"] for m in range(n_acc)] for r in range(len(reps))])
-        mag = np.array([[np.linalg.norm(tr[m][r]["m"]) for m in range(n_acc)]
-                        for r in range(len(reps))])
+        e = tr[:, :, 0].T
+        mag = np.linalg.norm(tr[:, :, 4:7], axis=2).T
         N = np.array([float(np.prod(r["L"])) for r in reps])
         return e / N[:, None], mag
 
@@ -659,6 +666,7 @@ EXTRAS = {"temperatures": extra_temperatures, "headline_256": extra_headline_256
 
 
 def main():
+    global ACC_PULSES
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000, help="timed intervals (pulses)")
@@ -673,10 +681,13 @@ def main():
                     help="skip the batched, adjoint and 256^3 overdamped workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--acc-pulses", type=int, default=ACC_PULSES,
+                    help="pulses of the batched accuracy runs (fp32 and fp64 batches)")
     ap.add_argument("--extra", default=None, metavar="NAME",
                     help="only run the named extra workload (one of: " + ", ".join(EXTRAS) +
                          ") and print its JSON")
     args = ap.parse_args()
+    ACC_PULSES = args.acc_pulses
     if args.extra is not None:
         if args.extra not in EXTRAS:
             ap.error(f"unknown extra {args.extra!r}")

@@ -274,7 +274,7 @@ void lll_destroy(lll_lattice* lat);
 /* ---------------------------------------------------------------- batch --
  * Many independent replicas (uneven sizes, own T, lambda, seed) advanced
  * together: every kernel of the schedule covers all replicas in one launch,
- * and the whole run is one captured HIP graph.  Spins of all replicas live in
+ * and a run is replayed from captured HIP graphs.  Spins of all replicas live in
  * one packed SoA allocation owned by the batch. */
 typedef struct {
     int32_t Lx, Ly, Lz;
@@ -294,7 +294,10 @@ lll_status lll_batch_create(int32_t n_rep, const lll_replica_desc* reps, lll_pre
  * returns LLL_ENONFINITE or LLL_WARN_NORM as lll_run does, over all replicas.
  * The schedule is captured as a HIP graph on the first call with a given
  * (n_pulses, obs_every) and replayed by later calls with the same pair, for any
- * first_pulse (a long run made of equal chunks captures once). */
+ * first_pulse (a long run made of equal chunks captures once).  A run longer
+ * than 1000 pulses is done as chunks of at most 1000 (a whole number of
+ * obs_every), each a replay of one of two graphs kept by the batch; the
+ * results are those of one run. */
 lll_status lll_batch_run(lll_batch* b, uint64_t first_pulse, int64_t n_pulses, int32_t obs_every,
                          lll_obs* trace);
 /* Observables of every replica's current state (synchronises); statuses as

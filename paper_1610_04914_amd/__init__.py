@@ -632,13 +632,21 @@ class Batch:
                "lll_batch_create")
         self.h = h
 
-    def run(self, first_pulse: int, n_pulses: int, obs_every: int = 0, trace: bool = True):
+    def run(self, first_pulse: int, n_pulses: int, obs_every: int = 0, trace: bool = True,
+            raw: bool = False):
         """trace=False: measurements run on the device (running sums) without
-        copying a trace back; returns []."""
+        copying a trace back; returns [].  raw=True: the trace as a numpy array
+        [measurement][replica][8] of the lll_obs fields in order (E_total,
+        E_exch, E_zeeman, E_anis, m_x, m_y, m_z, max_norm_dev), without
+        building Python dicts."""
         nm = n_pulses // obs_every if obs_every > 0 and trace else 0
         tr = (lll_obs * max(nm * self.n, 1))()
         _check(lib().lll_batch_run(self.h, C.c_uint64(first_pulse), int(n_pulses), int(obs_every),
                                    tr if nm > 0 else None), "lll_batch_run")
+        if raw:
+            import numpy as np
+            a = np.frombuffer(tr, dtype=np.float64, count=8 * nm * self.n)
+            return a.reshape(nm, self.n, 8).copy()
         return [[tr[m * self.n + r].as_dict() for r in range(self.n)] for m in range(nm)]
 
     def observables(self):

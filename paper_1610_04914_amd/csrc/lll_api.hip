@@ -1598,18 +1598,41 @@ extern "C" lll_status lll_adjoint(lll_lattice* L, const lll_params* p, uint64_t 
 }
 
 // --------------------------------------------------------------- batch -----
+// A captured run schedule of a batch: n_pulses intervals measured every
+// obs_every, replayable for any first pulse.
+struct BatchGraph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int64_t npulses = -1;
+    int32_t obs_every = -1;
+    uint64_t used = 0;  // recency, for replacing the older of the two
+    void clear() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        npulses = -1;
+        obs_every = -1;
+    }
+};
+
+// Pulses captured in one graph at most: a longer run replays the graph of a
+// chunk of this length (a whole number of measurement spacings) and one of the
+// remainder, the two graphs kept side by side.  A single graph of tens of
+// thousands of intervals (hundreds of thousands of kernel nodes) is not built.
+constexpr int64_t kBatchGraphPulses = 1000;
+
 struct lll_batch {
     Engine E;
     double dt = 0, Dt = 0;
     int64_t n = 0;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    int64_t g_npulses = -1;
-    int32_t g_obs_every = -1;
-    ~lll_batch() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (graph) (void)hipGraphDestroy(graph);
+    BatchGraph g[2];
+    uint64_t uses = 0;
+    void clear_graphs() {
+        g[0].clear();
+        g[1].clear();
     }
+    ~lll_batch() { clear_graphs(); }
 };
 
 extern "C" lll_status lll_batch_create(int32_t n_rep, const lll_replica_desc* reps,
@@ -1671,10 +1694,9 @@ extern "C" lll_status lll_batch_create(int32_t n_rep, const lll_replica_desc* re
     return LLL_OK;
 }
 
-extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t n_pulses,
-                                    int32_t obs_every, lll_obs* trace) {
-    if (!B) return set_err(LLL_EINVAL, "batch is NULL");
-    if (n_pulses < 0 || obs_every < 0) return set_err(LLL_EINVAL, "bad counts");
+// One captured (or replayed) schedule of at most kBatchGraphPulses intervals.
+static lll_status batch_run_chunk(lll_batch* B, uint64_t first_pulse, int64_t n_pulses,
+                                  int32_t obs_every, lll_obs* trace) {
     Engine& E = B->E;
     const int64_t nmeas = obs_every > 0 ? n_pulses / obs_every : 0;
     lll_status s;
@@ -1691,10 +1713,12 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
     // The captured schedule carries pulse indices relative to the first pulse
     // (the kernels add the descriptors' kbase), so it replays for any first
     // pulse with the same length and measurement spacing.
-    const bool reuse = B->gexec && B->g_npulses == n_pulses && B->g_obs_every == obs_every;
-    if (!reuse) {
-        if (B->gexec) { (void)hipGraphExecDestroy(B->gexec); B->gexec = nullptr; }
-        if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
+    BatchGraph* G = nullptr;
+    for (BatchGraph& c : B->g)
+        if (c.exec && c.npulses == n_pulses && c.obs_every == obs_every) G = &c;
+    if (!G) {
+        G = B->g[0].used <= B->g[1].used ? &B->g[0] : &B->g[1];
+        G->clear();
         hipStream_t cs = E.st;
         bool made_stream = false;
         if (!cs) {
@@ -1728,13 +1752,14 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
             return set_err(LLL_EDEVICE, "graph capture failed: %s", hipGetErrorString(ee));
         }
         if (made_stream) (void)hipStreamDestroy(cs);
-        B->graph = g;
-        HIP_TRY(hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
-        B->g_npulses = n_pulses;
-        B->g_obs_every = obs_every;
+        G->graph = g;
+        HIP_TRY(hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0));
+        G->npulses = n_pulses;
+        G->obs_every = obs_every;
     }
+    G->used = ++B->uses;
     HIP_TRY(launch_set_pulse_base(E.dreps, E.nrep, first_pulse, E.st));
-    HIP_TRY(hipGraphLaunch(B->gexec, E.st));
+    HIP_TRY(hipGraphLaunch(G->exec, E.st));
     if (trace && nmeas > 0) {
         std::vector<double> h((size_t)nmeas * 8 * E.nrep);
         HIP_TRY(hipMemcpyAsync(h.data(), E.d_trace, sizeof(double) * h.size(),
@@ -1750,6 +1775,31 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
         if (dev > LLL_NORM_WARN_LEVEL) return norm_warning(dev);
     }
     return LLL_OK;
+}
+
+extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t n_pulses,
+                                    int32_t obs_every, lll_obs* trace) {
+    if (!B) return set_err(LLL_EINVAL, "batch is NULL");
+    if (n_pulses < 0 || obs_every < 0) return set_err(LLL_EINVAL, "bad counts");
+    if (n_pulses <= kBatchGraphPulses)
+        return batch_run_chunk(B, first_pulse, n_pulses, obs_every, trace);
+    // chunks of a whole number of measurement spacings, so that every
+    // measurement falls where one run would take it; the intervals, kicks and
+    // measurements are the same (a kick is applied with the same bits whether
+    // it rides on the step before it or not), and the running sums are added in
+    // measurement order
+    int64_t chunk = kBatchGraphPulses;
+    if (obs_every > 0) chunk = std::max<int64_t>(obs_every, chunk / obs_every * obs_every);
+    lll_status warn = LLL_OK;
+    for (int64_t done = 0; done < n_pulses;) {
+        const int64_t len = std::min(chunk, n_pulses - done);
+        lll_obs* tr = trace && obs_every > 0 ? trace + (done / obs_every) * B->E.nrep : nullptr;
+        const lll_status s = batch_run_chunk(B, first_pulse + (uint64_t)done, len, obs_every, tr);
+        if (s < 0) return s;
+        if (s != LLL_OK) warn = s;  // a warning: the work was done; report it at the end
+        done += len;
+    }
+    return warn;
 }
 
 extern "C" lll_status lll_batch_observables(lll_batch* B, lll_obs* out) {
@@ -1813,14 +1863,7 @@ extern "C" lll_status lll_batch_autotune(lll_batch* B, const char* cache_path,
     snprintf(buf, sizeof buf, "B%d_%lld_%016llx_%s_prec%d_anis%d", E.nrep, (long long)E.nsites,
              (unsigned long long)h, E.prec == 0 ? "fp64" : "fp32", E.precession, E.anis);
     lll_status s = engine_autotune(E, buf, maxLz, B->n, cache_path, chosen_variant, chosen_bz);
-    if (B->gexec) {
-        (void)hipGraphExecDestroy(B->gexec);
-        B->gexec = nullptr;
-    }
-    if (B->graph) {
-        (void)hipGraphDestroy(B->graph);
-        B->graph = nullptr;
-    }
+    B->clear_graphs();
     return s;
 }
 

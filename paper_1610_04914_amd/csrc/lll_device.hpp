@@ -115,10 +115,13 @@ __device__ __forceinline__ void angle_of<float>(float ph2, float& inv, float& sn
 // Renormalisation s = s'/|s'| after a kick; returns | |s'| - 1 | in fp64.
 // fp64 state: the norm and the quotient in fp64.  fp32 state: |s'|^2 of the
 // fp32 components is formed in fp64 (each square exact, so the deviation
-// |s'|^2 - 1 keeps its relative accuracy however small it is), and
-// | |s'| - 1 | = | |s'|^2 - 1 | / (|s'| + 1) takes the well-conditioned
-// denominator from the fp32 reciprocal square root, which also rescales the
-// spin (about 1 ulp).
+// |s'|^2 - 1 keeps its relative accuracy however small it is); 1/|s'| is the
+// hardware's fp32 reciprocal square root refined by one Newton step in fp64
+// (the estimate alone is about 1 ulp off and leans low: spins rescaled with
+// it kept |s| about 4e-8 below 1 on average, which lowered |E| by about two
+// parts in 1e7), and each component is rounded to fp32 once, from fp64, so
+// that |s| - 1 averages zero; | |s'| - 1 | = | |s'|^2 - 1 | / (|s'| + 1)
+// with the well-conditioned denominator.
 template <typename T>
 __device__ __forceinline__ double renorm(T ox, T oy, T oz, T& sx, T& sy, T& sz);
 
@@ -138,12 +141,12 @@ __device__ __forceinline__ double renorm<float>(float ox, float oy, float oz, fl
                                                 float& sz) {
     const double dx = (double)ox, dy = (double)oy, dz = (double)oz;
     const double n2 = dx * dx + dy * dy + dz * dz;
-    const float n2f = (float)n2;
-    const float r = __builtin_amdgcn_rsqf(n2f);
-    sx = ox * r;
-    sy = oy * r;
-    sz = oz * r;
-    const float den = n2f * r + 1.0f;
+    const double r0 = (double)__builtin_amdgcn_rsqf((float)n2);
+    const double inv = r0 * (1.5 - 0.5 * n2 * (r0 * r0));
+    sx = (float)(dx * inv);
+    sy = (float)(dy * inv);
+    sz = (float)(dz * inv);
+    const float den = (float)(n2 * inv) + 1.0f;
     return fabs(n2 - 1.0) * (double)__builtin_amdgcn_rcpf(den);
 }
 

@@ -735,6 +735,39 @@ def test_batch_replay_across_pulse_counter_wrap(P):
         X.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_long_run_in_chunks(P, prec):
+    """A run longer than one captured graph (1000 pulses) is done as replays of
+    chunks a whole number of measurement spacings long: one call of 2100
+    pulses measured every 7 (chunks of 994, 994 and 112) ends in the states of
+    21 calls of 100 pulses, bit for bit, and its trace equals theirs wherever
+    both measure (pulses that are multiples of 7 in calls 0, 7 and 14)."""
+    reps = BATCH_SETS["mixed"]
+    A = P.Batch(reps, precision=prec, dt=0.2, Dt=0.4)
+    B = P.Batch(reps, precision=prec, dt=0.2, Dt=0.4)
+    ta = A.run(first_pulse=3, n_pulses=2100, obs_every=7, raw=True)
+    tb = [B.run(first_pulse=3 + 100 * c, n_pulses=100, obs_every=7, raw=True) for c in range(21)]
+    torch.cuda.synchronize()
+    # 100-pulse calls measure at 7, 14, ..., 98 of each call; the long run at
+    # every 7th pulse of the whole: compare where both measure
+    want = {}
+    for c, t in enumerate(tb):
+        for m in range(t.shape[0]):
+            want[100 * c + 7 * (m + 1)] = t[m]
+    assert ta.shape == (300, len(reps), 8)
+    common = 0
+    for m in range(ta.shape[0]):
+        q = 7 * (m + 1)
+        if q in want:
+            assert np.array_equal(ta[m], want[q]), q
+            common += 1
+    assert common > 20
+    for r in range(len(reps)):
+        assert torch.equal(A.state(r), B.state(r)), r
+    A.close()
+    B.close()
+
+
 # ------------------------------------------- the other workload configs -----
 def test_small_fp64_workload_per_segment(P):
     """16^3 periodic fp64 ferromagnet (J = 1, H = 0, D = 0, lambda = 0.01, T = 1,

@@ -296,8 +296,9 @@ lll_status lll_batch_create(int32_t n_rep, const lll_replica_desc* reps, lll_pre
  * (n_pulses, obs_every) and replayed by later calls with the same pair, for any
  * first_pulse (a long run made of equal chunks captures once).  A run longer
  * than 1000 pulses is done as chunks of at most 1000 (a whole number of
- * obs_every), each a replay of one of two graphs kept by the batch; the
- * results are those of one run. */
+ * obs_every; with obs_every above 1000, each measurement period as unmeasured
+ * chunks and a last one measured at its end), each a replay of one of three
+ * graphs kept by the batch; the results are those of one run. */
 lll_status lll_batch_run(lll_batch* b, uint64_t first_pulse, int64_t n_pulses, int32_t obs_every,
                          lll_obs* trace);
 /* Observables of every replica's current state (synchronises); statuses as

@@ -1616,21 +1616,21 @@ struct BatchGraph {
     }
 };
 
-// Pulses captured in one graph at most: a longer run replays the graph of a
-// chunk of this length (a whole number of measurement spacings) and one of the
-// remainder, the two graphs kept side by side.  A single graph of tens of
-// thousands of intervals (hundreds of thousands of kernel nodes) is not built.
+// Pulses captured in one graph at most: a longer run replays graphs of chunks
+// of at most this length (see lll_batch_run), up to three kept side by side.
+// A single graph of tens of thousands of intervals (hundreds of thousands of
+// kernel nodes) is not built.
 constexpr int64_t kBatchGraphPulses = 1000;
+constexpr int kBatchGraphs = 3;
 
 struct lll_batch {
     Engine E;
     double dt = 0, Dt = 0;
     int64_t n = 0;
-    BatchGraph g[2];
+    BatchGraph g[kBatchGraphs];
     uint64_t uses = 0;
     void clear_graphs() {
-        g[0].clear();
-        g[1].clear();
+        for (BatchGraph& c : g) c.clear();
     }
     ~lll_batch() { clear_graphs(); }
 };
@@ -1717,7 +1717,9 @@ static lll_status batch_run_chunk(lll_batch* B, uint64_t first_pulse, int64_t n_
     for (BatchGraph& c : B->g)
         if (c.exec && c.npulses == n_pulses && c.obs_every == obs_every) G = &c;
     if (!G) {
-        G = B->g[0].used <= B->g[1].used ? &B->g[0] : &B->g[1];
+        G = &B->g[0];  // the least recently used
+        for (BatchGraph& c : B->g)
+            if (c.used < G->used) G = &c;
         G->clear();
         hipStream_t cs = E.st;
         bool made_stream = false;
@@ -1783,20 +1785,49 @@ extern "C" lll_status lll_batch_run(lll_batch* B, uint64_t first_pulse, int64_t 
     if (n_pulses < 0 || obs_every < 0) return set_err(LLL_EINVAL, "bad counts");
     if (n_pulses <= kBatchGraphPulses)
         return batch_run_chunk(B, first_pulse, n_pulses, obs_every, trace);
-    // chunks of a whole number of measurement spacings, so that every
-    // measurement falls where one run would take it; the intervals, kicks and
-    // measurements are the same (a kick is applied with the same bits whether
-    // it rides on the step before it or not), and the running sums are added in
-    // measurement order
-    int64_t chunk = kBatchGraphPulses;
-    if (obs_every > 0) chunk = std::max<int64_t>(obs_every, chunk / obs_every * obs_every);
+    // Chunks whose measurements fall where one run would take them: with a
+    // spacing of at most kBatchGraphPulses, chunks of a whole number of
+    // spacings; with a longer spacing, each measurement period as unmeasured
+    // chunks of kBatchGraphPulses and a last chunk measured at its end.  The
+    // intervals, kicks and measurements are those of one run (a kick is
+    // applied with the same bits whether it rides on the step before it or
+    // not), and the running sums are added in measurement order.
     lll_status warn = LLL_OK;
-    for (int64_t done = 0; done < n_pulses;) {
-        const int64_t len = std::min(chunk, n_pulses - done);
-        lll_obs* tr = trace && obs_every > 0 ? trace + (done / obs_every) * B->E.nrep : nullptr;
-        const lll_status s = batch_run_chunk(B, first_pulse + (uint64_t)done, len, obs_every, tr);
+    auto part = [&](uint64_t done, int64_t len, int32_t every, int64_t meas_before) {
+        lll_obs* tr = trace && every > 0 ? trace + meas_before * B->E.nrep : nullptr;
+        const lll_status s = batch_run_chunk(B, first_pulse + done, len, every, tr);
+        if (s > 0) warn = s;  // a warning: the work was done; report it at the end
+        return s;
+    };
+    if (obs_every == 0 || obs_every <= kBatchGraphPulses) {
+        int64_t chunk = kBatchGraphPulses;
+        if (obs_every > 0) chunk = chunk / obs_every * obs_every;
+        for (int64_t done = 0; done < n_pulses;) {
+            const int64_t len = std::min(chunk, n_pulses - done);
+            const lll_status s = part((uint64_t)done, len, obs_every,
+                                      obs_every > 0 ? done / obs_every : 0);
+            if (s < 0) return s;
+            done += len;
+        }
+        return warn;
+    }
+    int64_t done = 0, meas = 0;
+    for (; done + obs_every <= n_pulses; ++meas) {
+        int64_t left = obs_every;
+        while (left > kBatchGraphPulses) {
+            const lll_status s = part((uint64_t)done, kBatchGraphPulses, 0, 0);
+            if (s < 0) return s;
+            done += kBatchGraphPulses;
+            left -= kBatchGraphPulses;
+        }
+        const lll_status s = part((uint64_t)done, left, (int32_t)left, meas);
         if (s < 0) return s;
-        if (s != LLL_OK) warn = s;  // a warning: the work was done; report it at the end
+        done += left;
+    }
+    while (done < n_pulses) {
+        const int64_t len = std::min(kBatchGraphPulses, n_pulses - done);
+        const lll_status s = part((uint64_t)done, len, 0, 0);
+        if (s < 0) return s;
         done += len;
     }
     return warn;

@@ -768,6 +768,35 @@ def test_batch_long_run_in_chunks(P, prec):
     B.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_long_spacing_in_chunks(P, prec):
+    """A measurement spacing above one graph (1200 pulses): each period runs as
+    an unmeasured chunk of 1000 and a chunk of 200 measured at its end.  2500
+    pulses in one call measure after pulses 1200 and 2400 what the observables
+    of 25 unmeasured calls of 100 pulses give there, bit for bit, and end in
+    the same states."""
+    reps = BATCH_SETS["mixed"]
+    A = P.Batch(reps, precision=prec, dt=0.2, Dt=0.4)
+    B = P.Batch(reps, precision=prec, dt=0.2, Dt=0.4)
+    ta = A.run(first_pulse=3, n_pulses=2500, obs_every=1200, raw=True)
+    want = []
+    for c in range(25):
+        B.run(first_pulse=3 + 100 * c, n_pulses=100)
+        if c in (11, 23):
+            want.append(B.observables())
+    torch.cuda.synchronize()
+    assert ta.shape == (2, len(reps), 8)
+    for m, obs in enumerate(want):
+        for r, o in enumerate(obs):
+            row = [o["E_total"], o["E_exch"], o["E_zeeman"], o["E_anis"], *o["m"],
+                   o["max_norm_dev"]]
+            assert np.array_equal(ta[m, r], np.array(row)), (m, r)
+    for r in range(len(reps)):
+        assert torch.equal(A.state(r), B.state(r)), r
+    A.close()
+    B.close()
+
+
 # ------------------------------------------- the other workload configs -----
 def test_small_fp64_workload_per_segment(P):
     """16^3 periodic fp64 ferromagnet (J = 1, H = 0, D = 0, lambda = 0.01, T = 1,

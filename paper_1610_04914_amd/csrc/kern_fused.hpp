@@ -701,6 +701,8 @@ inline hipError_t fused_f64(LLL_FUSED_ARGS) {
         case 3: return launch_p<double, 16, 16, 256, SCHEME>(LLL_FUSED_PASS);
         case 4: return launch_p<double, 32, 8, 256, SCHEME>(LLL_FUSED_PASS);
         case 5: return launch_p<double, 16, 8, 384, SCHEME>(LLL_FUSED_PASS);
+        case 6: return launch_p<double, 16, 16, 512, SCHEME>(LLL_FUSED_PASS);
+        case 7: return launch_p<double, 32, 8, 512, SCHEME>(LLL_FUSED_PASS);
         default: return hipErrorInvalidValue;
     }
 }

@@ -12,7 +12,7 @@ struct VariantDesc {
 static const VariantDesc kVar32[] = {{32, 16, 960}, {32, 16, 512}, {16, 16, 576}, {32, 8, 640},
                                      {64, 8, 512}, {32, 16, 1024}};
 static const VariantDesc kVar64[] = {{32, 8, 640}, {16, 16, 576}, {16, 16, 256}, {32, 8, 256},
-                                     {16, 8, 384}};
+                                     {16, 8, 384}, {16, 16, 512}, {32, 8, 512}};
 
 static int lds_bytes(int bx, int by, int es) {
     int r = 0;

@@ -13,6 +13,8 @@ hipError_t fused_f64_stages(int precession, int anis, int variant, int bz, const
         case 3: return launch_stages_v<double, 16, 16, 256>(LLL_ST_PASS);
         case 4: return launch_stages_v<double, 32, 8, 256>(LLL_ST_PASS);
         case 5: return launch_stages_v<double, 16, 8, 384>(LLL_ST_PASS);
+        case 6: return launch_stages_v<double, 16, 16, 512>(LLL_ST_PASS);
+        case 7: return launch_stages_v<double, 32, 8, 512>(LLL_ST_PASS);
         default: return hipErrorInvalidValue;
     }
 #undef LLL_ST_PASS

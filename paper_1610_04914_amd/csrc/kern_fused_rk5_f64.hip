@@ -19,6 +19,8 @@ static hipError_t fused_f64_rk5(int precession, int anis, int variant, int bz, c
         case 3: return launch_rk5_p<double, 16, 16, 256, 256>(LLL_RK5_PASS);
         case 4: return launch_rk5_p<double, 32, 8, 256, 256>(LLL_RK5_PASS);
         case 5: return launch_rk5_p<double, 16, 8, 384, 256>(LLL_RK5_PASS);
+        case 6: return launch_rk5_p<double, 16, 16, 512, 448>(LLL_RK5_PASS);
+        case 7: return launch_rk5_p<double, 32, 8, 512, 448>(LLL_RK5_PASS);
         default: return hipErrorInvalidValue;
     }
 #undef LLL_RK5_PASS

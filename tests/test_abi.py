@@ -141,6 +141,47 @@ def test_validation_before_device_use(P):
     assert b"too many sites" in L.lll_last_error()
 
 
+
+def test_null_handles_rejected(P):
+    """Every entry point that takes a lattice, batch or tape handle returns
+    LLL_EINVAL with a message for a NULL handle, before any device call; the
+    destroy calls accept NULL."""
+    L = P.lib()
+    o = P.lll_obs()
+    d = (C.c_double * 8)()
+    i1, i2 = C.c_int32(), C.c_int32()
+    v = C.c_void_p()
+    i64 = C.c_int64()
+    wm = (C.c_double * 3)()
+    calls = {
+        "lll_noise_pulse": lambda: L.lll_noise_pulse(None, None, 0),
+        "lll_observables": lambda: L.lll_observables(None, None, C.byref(o)),
+        "lll_get_state": lambda: L.lll_get_state(None, C.byref(v), C.byref(v), C.byref(v)),
+        "lll_kick_norm_dev": lambda: L.lll_kick_norm_dev(None, d, 0),
+        "lll_accumulators": lambda: L.lll_accumulators(None, d, 0),
+        "lll_set_step_config": lambda: L.lll_set_step_config(None, 1, 0),
+        "lll_get_step_config": lambda: L.lll_get_step_config(None, C.byref(i1), C.byref(i2)),
+        "lll_set_kick_fusion": lambda: L.lll_set_kick_fusion(None, 1),
+        "lll_kernel_timing": lambda: L.lll_kernel_timing(None, 1, d, C.byref(i64)),
+        "lll_autotune": lambda: L.lll_autotune(None, None, None, C.byref(i1), C.byref(i2)),
+        "lll_adjoint_forward": lambda: L.lll_adjoint_forward(None, None, 0, 1, 10, C.byref(v)),
+        "lll_adjoint_backward": lambda: L.lll_adjoint_backward(None, None, 1.0, wm, d, d, d,
+                                                               d, None),
+        "lll_batch_run": lambda: L.lll_batch_run(None, 0, 1, 0, None),
+        "lll_batch_observables": lambda: L.lll_batch_observables(None, C.byref(o)),
+        "lll_batch_state": lambda: L.lll_batch_state(None, 0, C.byref(v), C.byref(v), C.byref(v)),
+        "lll_batch_accumulators": lambda: L.lll_batch_accumulators(None, d, 0),
+        "lll_batch_autotune": lambda: L.lll_batch_autotune(None, None, C.byref(i1), C.byref(i2)),
+        "lll_escape_times": lambda: L.lll_escape_times(None, 1, 1, None, None),
+    }
+    for name, call in calls.items():
+        assert call() == P.LLL_EINVAL, name
+        assert L.lll_last_error(), name
+    L.lll_destroy(None)
+    L.lll_batch_destroy(None)
+    L.lll_tape_destroy(None)
+
+
 def test_variant_table(P):
     for prec in ("fp32", "fp64"):
         vs = P.step_variants(prec)

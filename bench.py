@@ -800,7 +800,7 @@ def main():
                      "avg_launch_ms": step_ms, "launches_timed": n_timed,
                      "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": achieved_gbs / HBM_PEAK_GBS}},
-        "final_obs": trace[len(trace) - 1].as_dict() if len(trace) else None,
+        "final_obs": P.obs_row_dict(trace[len(trace) - 1]) if len(trace) else None,
     }
     if args.extras:
         out["extras"] = {"headline_variants": extra_headline_variants(lat, p),

@@ -189,9 +189,10 @@ def lll_observables(h, params: lll_params) -> dict:
 def lll_run(h, params: lll_params, first_pulse: int, n_pulses: int, T_per_pulse=None,
             obs_every: int = 0, trace: bool = True, raw: bool = False):
     """trace=False: the measurements still run (running sums, last values on the
-    device) but none is copied back; returns [].  raw=True: returns the host
-    array of lll_obs records as the library filled it (convert an entry with
-    .as_dict()), without building Python dicts."""
+    device) but none is copied back; returns [].  raw=True: the trace as a
+    numpy array [measurement][8] of the lll_obs fields in order (E_total,
+    E_exch, E_zeeman, E_anis, m_x, m_y, m_z, max_norm_dev; obs_row_dict turns a
+    row into the dict form), without building Python dicts."""
     nm = n_pulses // obs_every if obs_every > 0 and trace else 0
     tr = (lll_obs * max(nm, 1))()
     Tp = None
@@ -201,8 +202,16 @@ def lll_run(h, params: lll_params, first_pulse: int, n_pulses: int, T_per_pulse=
                        int(obs_every), tr if nm > 0 else None)
     _check(st, "lll_run")
     if raw:
-        return tr if nm > 0 else []
+        import numpy as np
+        return np.frombuffer(tr, dtype=np.float64, count=8 * nm).reshape(nm, 8).copy()
     return [tr[i].as_dict() for i in range(nm)]
+
+
+def obs_row_dict(row) -> dict:
+    """The dict form (as lll_obs.as_dict) of one row of a raw trace."""
+    return {"E_total": float(row[0]), "E_exch": float(row[1]), "E_zeeman": float(row[2]),
+            "E_anis": float(row[3]), "m": (float(row[4]), float(row[5]), float(row[6])),
+            "max_norm_dev": float(row[7])}
 
 
 def lll_observables_noalloc(Lx, Ly, Lz, bc, prec, params: lll_params, sx, sy, sz, out_dev,

@@ -182,6 +182,21 @@ def test_null_handles_rejected(P):
     L.lll_tape_destroy(None)
 
 
+
+def test_raw_trace_rows_follow_the_record_layout(P):
+    """A raw trace row (numpy view of the lll_obs records) converts to the same
+    dict as the record itself."""
+    import numpy as np
+    recs = (P.lll_obs * 2)()
+    for k, r in enumerate(recs):
+        r.E_total, r.E_exch, r.E_zeeman, r.E_anis = 1.0 + k, 2.0 + k, 3.0 + k, 4.0 + k
+        r.m[0], r.m[1], r.m[2] = 5.0 + k, 6.0 + k, 7.0 + k
+        r.max_norm_dev = 8.0 + k
+    rows = np.frombuffer(recs, dtype=np.float64, count=16).reshape(2, 8)
+    for k in range(2):
+        assert P.obs_row_dict(rows[k]) == recs[k].as_dict()
+
+
 def test_variant_table(P):
     for prec in ("fp32", "fp64"):
         vs = P.step_variants(prec)

@@ -735,6 +735,22 @@ def test_batch_replay_across_pulse_counter_wrap(P):
         X.close()
 
 
+def test_lattice_raw_trace_matches_dicts(P):
+    """Lattice.run(raw=True) returns the same measurements, as rows of the
+    lll_obs fields, as the dict trace of an identical run."""
+    p = P.Params(J=1.0, H=(0.0, 0.0, 0.1), D=0.05, lam=0.01, T=1.0, dt=0.2, Dt=0.4, seed=3)
+    a = P.Lattice((12, 10, 9), precision="fp64", init="random", seed=1)
+    b = P.Lattice((12, 10, 9), precision="fp64", init="random", seed=1)
+    rows = a.run(p, first_pulse=0, n_pulses=6, obs_every=2, raw=True)
+    dicts = b.run(p, first_pulse=0, n_pulses=6, obs_every=2)
+    assert rows.shape == (3, 8)
+    assert [P.obs_row_dict(r) for r in rows] == [
+        dict(d, m=tuple(float(x) for x in d["m"])) for d in dicts]
+    assert a.run(p, first_pulse=6, n_pulses=2, obs_every=0, raw=True).shape == (0, 8)
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_batch_long_run_in_chunks(P, prec):
     """A run longer than one captured graph (1000 pulses) is done as replays of

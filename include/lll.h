@@ -189,9 +189,11 @@ lll_status lll_get_step_config(lll_lattice* lat, int32_t* variant, int32_t* bz);
  * unfused step. */
 lll_status lll_set_kick_fusion(lll_lattice* lat, int32_t fused);
 /* Kernel timing of the fused RK4 step (launches without kick epilogue).
- * enable != 0 starts a measurement: later launches record events taken from
- * their own dispatch into a ring of 64 pairs (a pair still in flight is
- * skipped, so the timed launches are a sample spread over the run).
+ * enable != 0 starts a measurement: every 16th later launch records events
+ * taken from its own dispatch into a ring of 64 pairs (a pair still in flight
+ * is skipped), so the timed launches are a sample spread over the run.  A
+ * launch that records its own events starts a few microseconds later, so
+ * timing every launch would slow the run it measures.
  * enable == 0 synchronises the lattice's stream, ends the measurement and
  * returns the mean kernel duration *avg_ms over *n_timed launches (either
  * pointer may be NULL; 0 launches gives 0.0). */

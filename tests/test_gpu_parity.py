@@ -735,6 +735,23 @@ def test_batch_replay_across_pulse_counter_wrap(P):
         X.close()
 
 
+def test_kernel_timing_samples_fused_launches(P):
+    """Dispatch-event timing of the fused step covers a sample of the plain
+    launches (one in 16, none with the kick epilogue) and gives a positive
+    mean duration."""
+    p = P.Params(J=1.0, H=(0.0, 0.0, 0.1), D=0.05, lam=0.01, T=1.0, dt=0.2, Dt=0.4, seed=3)
+    lat = P.Lattice((32, 32, 32), precision="fp32", init="random", seed=1)
+    lat.set_step_config(1, 16)
+    lat.kernel_timing_start()
+    lat.step(p, 160)
+    ms, n = lat.kernel_timing_stop()
+    assert 1 <= n <= 10 and ms > 0.0, (n, ms)
+    lat.kernel_timing_start()
+    ms0, n0 = lat.kernel_timing_stop()
+    assert (ms0, n0) == (0.0, 0)
+    lat.close()
+
+
 def test_lattice_raw_trace_matches_dicts(P):
     """Lattice.run(raw=True) returns the same measurements, as rows of the
     lll_obs fields, as the dict trace of an identical run."""

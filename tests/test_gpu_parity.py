@@ -830,6 +830,24 @@ def test_batch_long_spacing_in_chunks(P, prec):
     B.close()
 
 
+def test_batch_run_shorter_than_its_spacing(P):
+    """1200 pulses with a measurement spacing of 1500: no measurement, chunks
+    of 1000 and 200 pulses, the same final states as 12 unmeasured calls of
+    100 pulses."""
+    reps = BATCH_SETS["mixed"]
+    A = P.Batch(reps, precision="fp32", dt=0.2, Dt=0.4)
+    B = P.Batch(reps, precision="fp32", dt=0.2, Dt=0.4)
+    ta = A.run(first_pulse=11, n_pulses=1200, obs_every=1500, raw=True)
+    for c in range(12):
+        B.run(first_pulse=11 + 100 * c, n_pulses=100)
+    torch.cuda.synchronize()
+    assert ta.shape == (0, len(reps), 8)
+    for r in range(len(reps)):
+        assert torch.equal(A.state(r), B.state(r)), r
+    A.close()
+    B.close()
+
+
 # ------------------------------------------- the other workload configs -----
 def test_small_fp64_workload_per_segment(P):
     """16^3 periodic fp64 ferromagnet (J = 1, H = 0, D = 0, lambda = 0.01, T = 1,

@@ -744,14 +744,11 @@ def main():
     # still runs about 8% slower than in steady state (measured: 20 timed
     # intervals after a 5-interval warm-up gave 0.350 ms per interval, 200
     # after 20 gave 0.309).
-    # Host set-up that the timed region needs (its CUDA events and the
-    # library's dispatch events) is done here: the GPU's clock drops within
-    # milliseconds of idling (measured: 20 intervals started 10 ms after the
-    # previous work ran at 5.9e10 spin-steps/s, back to back at 6.9e10), so
-    # nothing but the synchronisation separates the warm-up from the timed run.
-    stream = torch.cuda.current_stream()  # the library's stream (the handle was made on it)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # Host set-up that the timed region needs (the library's dispatch events)
+    # is done here: the GPU's clock drops within milliseconds of idling
+    # (measured: 20 intervals started 10 ms after the previous work ran at
+    # 5.9e10 spin-steps/s, back to back at 6.9e10), so nothing but the
+    # synchronisation separates the warm-up from the timed run.
     _prepare_timing(lat)
     if args.settle and args.warmup < args.steps:
         lat.run(p, first_pulse=10**7, n_pulses=args.steps, obs_every=1)
@@ -769,17 +766,15 @@ def main():
     # pairs that a sample of the timed region's step launches record at their
     # own dispatch (start and end of the kernel, as a kernel trace sees them).
     lat.kernel_timing_start()
+    # The timed region is the wall time between two synchronisations (timing
+    # events recorded on the stream around it would add about 40 us of their
+    # own to it).  The trace comes back to the host inside it; its records
+    # become Python dicts after it.
     t0 = time.perf_counter()
-    e0.record(stream)
-    # the trace comes back to the host inside the timed region; its records
-    # become Python dicts after it
     trace = lat.run(p, first_pulse=args.warmup, n_pulses=args.steps, obs_every=1, raw=True)
-    e1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    elapsed = time.perf_counter() - t0
     step_ms, n_timed = lat.kernel_timing_stop()
-    ev_ms = e0.elapsed_time(e1)
-    elapsed = max(wall, ev_ms / 1e3)
     spin_steps = N * n * args.steps
     value = spin_steps / elapsed
     alg_bytes = BYTES_PER_SPIN_STEP[prec] * N
